@@ -1,0 +1,25 @@
+"""CPU FP64 oracle for the mixed-basis (2D plane waves x B-splines) problem.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package; the library's compute
+path never does.  It shares no code with the HIP library: its B-splines,
+quadrature, G sets, matrix elements and solver are written here from the
+paper's definitions with numpy / scipy primitives.
+
+Modules
+-------
+bspline   : knot sequence, Cox-de Boor recursion (eqs. 1-2), derivative (eq. 3),
+            Gauss-Legendre rule per interval, 1D overlap / derivative matrices
+            (Sec. II.A and the overlap / kinetic elements of Sec. II.B.1).
+lattice   : reciprocal vectors, in-plane G sets, k-points (basis of Sec. II.B.1).
+operators : dense S, T, local potential (grid-consistent and analytic forms),
+            Kleinman-Bylander projectors (Sec. II.B.1), H assembly.
+solve     : lowest eigenpairs of H c = eps S c by LAPACK (generalized form of
+            Sec. II.B.2), residuals.
+rows      : selected rows of H x and S x without a dense matrix (same
+            definitions, evaluated one output at a time) for large cells.
+
+Parity status: every function is pinned by the CPU tests against closed forms,
+brute-force quadrature, library routines or mathematical invariants; none is
+"parity unpinned".
+"""
