@@ -1,0 +1,208 @@
+/*
+ * mbks.h - C ABI of the mixed-basis Kohn-Sham operator library for MI355X (gfx950).
+ *
+ * Basis (paper Sec. II.B.1): phi_{G,i}(r) = A_c^{-1/2} exp(i(k+G).rho) B_i(z), with
+ * G an in-plane reciprocal lattice vector and B_i a B-spline of order kappa on a
+ * clamped knot sequence (Sec. II.A, eqs. 1-3).  The first and last spline are
+ * dropped (hard walls), so with N_int knot intervals there are
+ * N_b = N_int + kappa - 3 basis splines.  The discrete problem is the generalized
+ * Hermitian eigenproblem H c = eps S c (Sec. II.B.2 form) with
+ *   S = I_G (x) S_z                           (overlap elements, Sec. II.B.1)
+ *   T = 1/2 (D_z + |k+G|^2 S_z) per G         (kinetic elements, Sec. II.B.1; Hartree)
+ *   V_loc: Gaussian local potential applied through the in-plane grid
+ *          (matrix elements of Sec. II.B.1 with the transform taken on the grid)
+ *   V_NL = sum_p E_p |beta_p><beta_p|        (Kleinman-Bylander form, eq. KBeq)
+ * Integrals of non-polynomial integrands use a per-interval Gauss-Legendre rule.
+ *
+ * Units: Hartree atomic units (energies Ha, lengths bohr).
+ *
+ * Vector layout (all entry points): a block of nbands vectors is one array
+ *   x[band][i][G] (G fastest), row stride ld >= N_G complex elements,
+ * interleaved complex: complex128 (re, im doubles) for MB_FP64, complex64
+ * (re, im floats) for MB_FP32 and MB_BF16X3.  G runs over the library's
+ * G-set order of the k-point (see mb_problem_gvectors).  Entries [N_G, ld) of
+ * each row are padding: inputs ignore them, outputs set them to zero.
+ *
+ * Memory and streams: vector pointers are device pointers owned by the caller;
+ * the library never frees them.  `stream` is a hipStream_t (NULL = default
+ * stream); apply/solve calls are enqueued on it and return without
+ * synchronising.  lanczos_lowest synchronises `stream` (it returns host
+ * eigenvalues).  A problem handle owns its device tables and work buffers; one
+ * handle must not be used from two host threads at the same time, and calls on
+ * different streams that share a handle's work buffers must not overlap.
+ *
+ * Errors: every entry point returns an mb_status; arguments are validated
+ * before anything is enqueued.  mb_last_error() returns a thread-local message
+ * for the last failure.
+ */
+#ifndef MBKS_H
+#define MBKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MB_OK = 0,
+    MB_ERR_INVALID_ARG = -1,  /* a size, pointer or option is outside what the call accepts */
+    MB_ERR_NOT_SPD = -2,      /* the overlap S_z (or a preconditioner block) is not positive definite */
+    MB_ERR_NOT_CONVERGED = -3,/* lanczos_lowest hit max_iter; outputs hold the last iterate */
+    MB_ERR_NONFINITE = -4,    /* a NaN or Inf appeared in the eigensolver's small matrices or residuals */
+    MB_ERR_OOM = -5,          /* a device allocation failed */
+    MB_ERR_HIP = -6,          /* a HIP runtime call failed */
+    MB_ERR_NO_DEVICE = -7     /* the call needs a GPU and the handle was created host-only */
+} mb_status;
+
+typedef enum {
+    MB_FP64 = 0,   /* complex128 vectors; every step in FP64 */
+    MB_FP32 = 1,   /* complex64 vectors; FFT, potential multiply and projector contractions in FP32 */
+    MB_BF16X3 = 2  /* complex64 vectors; as MB_FP32 but projector contractions as three BF16 products */
+} mb_precision;
+
+#define MB_MAX_GAUSS 4
+
+/* One species: local part sum_t gauss_A[t] exp(-r^2 / gauss_w[t]^2) (the Gaussian
+ * terms of the local pseudopotential, Sec. II.B.1) and, if nonlocal != 0, one s and
+ * three real Cartesian p Kleinman-Bylander projectors (eq. KBeq; Gaussian radial
+ * parts exp(-alpha r^2), normalised to one) with energies E_s, E_p. */
+typedef struct {
+    int32_t ngauss;
+    double gauss_A[MB_MAX_GAUSS];
+    double gauss_w[MB_MAX_GAUSS];
+    int32_t nonlocal;
+    double alpha_s, alpha_p;
+    double E_s, E_p;
+} mb_species;
+
+typedef struct {
+    int32_t species;
+    double pos[3];   /* Cartesian, bohr */
+} mb_atom;
+
+#define MB_GSET_BOX 0
+#define MB_GSET_SPHERE 1
+
+/* Problem description.  Pointers are read during mb_problem_create only. */
+typedef struct {
+    double a1[2], a2[2];          /* in-plane lattice vectors */
+    int32_t order;                /* spline order kappa, 2..6 (4 = cubic) */
+    int32_t nbreak;               /* number of breakpoints = N_int + 1 >= 2 */
+    const double* breakpoints;    /* strictly increasing z_0 < ... < z_Nint */
+    int32_t nq;                   /* Gauss points per interval, 1..8 */
+    int32_t grid[2];              /* in-plane FFT grid N1 x N2, each 2^a 3^b 5^c, 4..256 */
+    int32_t gset_kind;            /* MB_GSET_BOX: |m_i| <= mmax[i]; MB_GSET_SPHERE: 1/2|k+G|^2 <= ecut */
+    int32_t mmax[2];
+    double ecut;
+    int32_t nk;
+    const double* kfrac;          /* nk x 2 fractional k-point coordinates */
+    int32_t nspecies;
+    const mb_species* species;
+    int32_t natoms;
+    const mb_atom* atoms;
+} mb_desc;
+
+typedef struct mb_problem mb_problem;
+
+/* Build every table of the problem on the host (knots, Gauss rule, B-spline
+ * values, banded S_z / D_z and the Cholesky factor of S_z, G sets, grid maps,
+ * projector factors) and upload them to `device`, where the local potential is
+ * sampled on the grid.  With device < 0 the handle is host-only: queries work,
+ * GPU calls return MB_ERR_NO_DEVICE.  Returns MB_ERR_INVALID_ARG for an
+ * inconsistent description (a G that does not map to a distinct grid point,
+ * non-increasing breakpoints, ...), MB_ERR_NOT_SPD if S_z is singular. */
+mb_status mb_problem_create(const mb_desc* desc, int device, mb_problem** out);
+mb_status mb_problem_destroy(mb_problem* p);
+
+/* Sizes for k-point ik: N_G, N_b, recommended ld, number of projectors, number
+ * of Gauss points N_q = nq * N_int. Any output pointer may be NULL. */
+mb_status mb_problem_dims(const mb_problem* p, int ik, int64_t* ng, int64_t* nb, int64_t* ld,
+                          int64_t* nproj, int64_t* nzq);
+
+/* Host copies of set-up tables (for checks against an independent code):
+ * mb_problem_gvectors: m (N_G x 2 int32, library order) and |k+G|^2 (N_G doubles);
+ * mb_problem_zrule: z_q and w_q (N_q doubles each);
+ * mb_problem_zbands: S_z and D_z as N_b x kappa arrays, band[i][d] = M[i][i+d]
+ *   (zero past the end);
+ * mb_problem_projectors: F (N_p x N_G complex128 = 2*N_p*N_G doubles), Z (N_p x N_b),
+ *   E (N_p) with <G,i|beta_p> = F[p][G] Z[p][i]. */
+mb_status mb_problem_gvectors(const mb_problem* p, int ik, int32_t* m, double* kg2);
+mb_status mb_problem_zrule(const mb_problem* p, double* zq, double* wq);
+mb_status mb_problem_zbands(const mb_problem* p, double* sband, double* dband);
+mb_status mb_problem_projectors(const mb_problem* p, int ik, double* F, double* Z, double* E);
+
+/* Replace the local potential by a caller-given real grid V[q][j1][j2]
+ * (N_q x N1 x N2 doubles, host memory, V at rho = j1/N1 a1 + j2/N2 a2, z = z_q).
+ * Synchronous. */
+mb_status mb_problem_set_potential(mb_problem* p, const double* v_host);
+
+/* y = H c for nbands vectors of k-point ik (all terms of H above).  The local
+ * part is one pass of: B-spline evaluate at the Gauss planes, G-sphere scatter,
+ * inverse 2D FFT, multiply by V(rho, z_q), forward 2D FFT, gather, B-spline
+ * project (matrix elements of the local potential, Sec. II.B.1).
+ * c and y must not overlap. */
+mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                     mb_precision prec, void* stream);
+
+/* y = S c (banded overlap, Sec. II.B.1).  c and y must not overlap. */
+mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                     mb_precision prec, void* stream);
+
+/* x = S^{-1} r by forward and back substitution with the banded Cholesky factor
+ * of S_z, shared by every G and band.  x may equal r (in place). */
+mb_status s_solve(mb_problem* p, int ik, const void* r, void* x, int64_t nbands, int64_t ld,
+                  mb_precision prec, void* stream);
+
+typedef struct {
+    int32_t block;        /* vectors per block of the block cycle (>= 1) */
+    int32_t krylov;       /* Krylov vectors per block per block cycle (>= 1) */
+    int32_t krylov_global;/* Krylov vectors of the global cycle (>= 0) */
+    int32_t max_iter;     /* grand cycles (>= 1) */
+    double tol;           /* converged when every ||H x - eps S x||_2 <= tol (x^H S x = 1) */
+    double sigma;         /* shift of the kinetic preconditioner (T + sigma S)^{-1}, Ha; <= 0: S^{-1} */
+    double switch_tol;    /* MB_FP32/MB_BF16X3: residual at which the solve continues in FP64 */
+    uint64_t seed;        /* seed of the random start when x0 is NULL */
+} mb_lanczos_opts;
+
+typedef struct {
+    int32_t iters;        /* grand cycles done */
+    int32_t iters_low;    /* of which in reduced precision */
+    int64_t h_applies;    /* band-vectors of H applied */
+    int64_t h_applies_low;/* of which in reduced precision */
+    double max_resid;     /* largest final residual norm */
+    double time_ms;       /* wall time of the call */
+} mb_lanczos_info;
+
+/* Fill opts with the defaults. */
+void mb_lanczos_default_opts(mb_lanczos_opts* opts);
+
+/* Lowest nev eigenpairs of H c = eps S c for k-point ik by the generalized
+ * Lanczos-Krylov method (Sec. II.C): alternating (a) a global Rayleigh-Ritz over
+ * the trial vectors together with a Krylov subspace grown from one trial vector
+ * and (b) a block cycle in which each small block of trial vectors is
+ * diagonalised together with a Krylov subspace grown from one of its vectors,
+ * roots selected by maximum overlap with the block's inputs.  Gram-Schmidt in the
+ * S inner product throughout, Jacobi diagonalisation of every projected matrix.
+ * Krylov vectors are grown with a preconditioned shifted operator
+ * K (H - theta S), K = (T + sigma S)^{-1}.
+ * prec = MB_FP64: all in FP64.  MB_FP32 / MB_BF16X3: H is applied in reduced
+ * precision until every residual is below opts->switch_tol, then the solve
+ * continues in FP64 (orthonormalisation, Krylov coefficients and every
+ * projected eigenproblem are FP64 throughout).
+ * x0: device complex128 [nev][N_b][ld] start vectors, or NULL for a seeded random
+ * start.  eig: host, nev doubles (ascending).  x: device complex128
+ * [nev][N_b][ld] output, S-orthonormal.  info and opts may be NULL (defaults).
+ * Returns MB_ERR_NOT_CONVERGED (outputs filled) after opts->max_iter cycles. */
+mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
+                         const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
+                         mb_lanczos_info* info, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* mb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBKS_H */

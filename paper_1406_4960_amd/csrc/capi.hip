@@ -1,0 +1,330 @@
+// C ABI entry points: argument validation, device upload of the set-up tables and
+// composition of the operator kernels on the caller's stream.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "cplx.h"
+#include "mbks_internal.h"
+
+struct mb_problem {
+    mb::Problem p;
+};
+
+namespace mb {
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename T>
+mb_status upload_vec(T** dst, const std::vector<T>& src) {
+    if (src.empty()) {
+        *dst = nullptr;
+        return MB_OK;
+    }
+    if (hipMalloc(dst, src.size() * sizeof(T)) != hipSuccess) return set_error(MB_ERR_OOM, "hipMalloc failed");
+    MB_HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MB_OK;
+}
+
+template <typename T>
+mb_status upload_f32(float** dst, const std::vector<T>& src) {
+    std::vector<float> f(src.begin(), src.end());
+    return upload_vec(dst, f);
+}
+
+#define MB_TRY(call)                       \
+    do {                                   \
+        mb_status s_ = (call);             \
+        if (s_ != MB_OK) return s_;        \
+    } while (0)
+
+mb_status upload_twiddles(int n, void** d64, void** d32) {
+    std::vector<cx<double>> t(n);
+    std::vector<cx<float>> tf(n);
+    for (int k = 0; k < n; ++k) {
+        double a = 2.0 * 3.14159265358979323846 * k / n;
+        t[k] = mk<double>(std::cos(a), std::sin(a));
+        tf[k] = mk<float>((float)t[k].x, (float)t[k].y);
+    }
+    MB_TRY(upload_vec((cx<double>**)d64, t));
+    MB_TRY(upload_vec((cx<float>**)d32, tf));
+    return MB_OK;
+}
+
+void free_all(Problem* p) {
+    if (p->device < 0) return;
+    void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
+                    p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
+                    p->d_V, p->d_Vf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->ws_part.ptr,
+                    p->ws_proj.ptr, p->ws_lz.ptr, p->ws_small.ptr, p->ws_conv.ptr};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (auto& kp : p->kp) {
+        void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_F64, kp.d_F32, kp.d_pfac};
+        for (void* q : kq)
+            if (q) (void)hipFree(q);
+    }
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void* out, int64_t nbands, int64_t ld,
+                         const char* what) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": problem is NULL");
+    const Problem& p = h->p;
+    if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, std::string(what) + ": host-only problem");
+    if (ik < 0 || ik >= (int)p.kp.size()) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ik out of range");
+    if (nbands < 0 || nbands > (1 << 20)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": nbands");
+    if (ld < p.kp[ik].ng || ld > (1 << 24)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ld < N_G");
+    if (nbands > 0 && (!in || !out)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": NULL vector");
+    if (p.order != 4) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": GPU kernels support order 4 only");
+    return MB_OK;
+}
+
+}  // namespace
+
+mb_status set_error(mb_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+mb_status ensure_ws(Workspace& w, size_t bytes) {
+    if (w.bytes >= bytes) return MB_OK;
+    if (w.ptr) {
+        MB_HIP_TRY(hipDeviceSynchronize());
+        MB_HIP_TRY(hipFree(w.ptr));
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc(&w.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(MB_ERR_OOM, "device workspace allocation failed");
+    }
+    w.bytes = want;
+    return MB_OK;
+}
+
+mb_status upload(Problem* p) {
+    MB_TRY(upload_vec(&p->d_bval, p->bval));
+    MB_TRY(upload_f32(&p->d_bvalf, p->bval));
+    MB_TRY(upload_vec(&p->d_wbval, p->wbval));
+    MB_TRY(upload_f32(&p->d_wbvalf, p->wbval));
+    MB_TRY(upload_vec(&p->d_sband, p->sband));
+    MB_TRY(upload_f32(&p->d_sbandf, p->sband));
+    MB_TRY(upload_vec(&p->d_dband, p->dband));
+    MB_TRY(upload_f32(&p->d_dbandf, p->dband));
+    MB_TRY(upload_vec(&p->d_lband, p->lband));
+    MB_TRY(upload_f32(&p->d_lbandf, p->lband));
+    if (p->np > 0) {
+        MB_TRY(upload_vec(&p->d_Z, p->Zp));
+        MB_TRY(upload_f32(&p->d_Zf, p->Zp));
+        MB_TRY(upload_vec(&p->d_E, p->Ep));
+        MB_TRY(upload_f32(&p->d_Ef, p->Ep));
+        MB_TRY(upload_vec(&p->d_zwin, p->zwin));
+    }
+    size_t nv = (size_t)p->nzq * p->N1 * p->N2;
+    if (hipMalloc(&p->d_V, nv * sizeof(double)) != hipSuccess) return set_error(MB_ERR_OOM, "potential grid");
+    if (hipMalloc(&p->d_Vf, nv * sizeof(float)) != hipSuccess) return set_error(MB_ERR_OOM, "potential grid");
+    MB_TRY(upload_twiddles(p->N1, &p->d_tw1, &p->d_tw1f));
+    MB_TRY(upload_twiddles(p->N2, &p->d_tw2, &p->d_tw2f));
+    for (auto& kp : p->kp) {
+        MB_TRY(upload_vec(&kp.d_kg2, kp.kg2));
+        MB_TRY(upload_f32(&kp.d_kg2f, kp.kg2));
+        MB_TRY(upload_vec(&kp.d_gmap, kp.gmap));
+        MB_TRY(upload_vec(&kp.d_rows, kp.rows));
+        if (p->np > 0) {
+            std::vector<cx<double>> F(kp.F.size());
+            std::vector<cx<float>> Ff(kp.F.size());
+            for (size_t e = 0; e < kp.F.size(); ++e) {
+                F[e] = mk<double>(kp.F[e].real(), kp.F[e].imag());
+                Ff[e] = mk<float>((float)kp.F[e].real(), (float)kp.F[e].imag());
+            }
+            MB_TRY(upload_vec((cx<double>**)&kp.d_F64, F));
+            MB_TRY(upload_vec((cx<float>**)&kp.d_F32, Ff));
+        }
+    }
+    MB_TRY(launch_vgrid(p, 0));
+    return MB_OK;
+}
+
+// y = H c (sy = S c if non-null).  prec: 0 FP64, 1 FP32 (c64), 2 c128 vectors with FP32 local/nonlocal.
+mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec, hipStream_t s) {
+    if (nbands == 0) return MB_OK;
+    size_t csz = prec == 0 ? sizeof(cx<double>) : sizeof(cx<float>);
+    size_t part_bytes = (size_t)nbands * p->nint * 4 * ld * csz;
+    MB_TRY(ensure_ws(p->ws_part, part_bytes));
+    void* proj = nullptr;
+    if (p->np > 0) {
+        MB_TRY(ensure_ws(p->ws_proj, (size_t)nbands * p->np * csz));
+        proj = p->ws_proj.ptr;
+        MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, prec, s));
+    }
+    MB_TRY(launch_local(p, ik, c, p->ws_part.ptr, nbands, ld, prec, s));
+    MB_TRY(launch_combine(p, ik, c, p->ws_part.ptr, proj, y, sy, nbands, ld, prec, s));
+    return MB_OK;
+}
+
+}  // namespace mb
+
+using mb::set_error;
+
+extern "C" {
+
+const char* mb_last_error(void) { return mb::g_last_error.c_str(); }
+
+mb_status mb_problem_create(const mb_desc* desc, int device, mb_problem** out) {
+    if (!out) return set_error(MB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    auto* h = new mb_problem;
+    mb_status st = mb::build_tables(desc, &h->p);
+    if (st != MB_OK) {
+        delete h;
+        return st;
+    }
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+            delete h;
+            return set_error(MB_ERR_NO_DEVICE, "no such GPU");
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            delete h;
+            return set_error(MB_ERR_HIP, "hipSetDevice failed");
+        }
+        h->p.device = device;
+        st = mb::upload(&h->p);
+        if (st != MB_OK) {
+            mb::free_all(&h->p);
+            delete h;
+            return st;
+        }
+    }
+    *out = h;
+    return MB_OK;
+}
+
+mb_status mb_problem_destroy(mb_problem* h) {
+    if (!h) return MB_OK;
+    if (h->p.device >= 0) {
+        (void)hipDeviceSynchronize();
+        mb::free_all(&h->p);
+    }
+    delete h;
+    return MB_OK;
+}
+
+mb_status mb_problem_dims(const mb_problem* h, int ik, int64_t* ng, int64_t* nb, int64_t* ld, int64_t* nproj,
+                          int64_t* nzq) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "ik out of range");
+    if (ng) *ng = h->p.kp[ik].ng;
+    if (nb) *nb = h->p.nb;
+    if (ld) *ld = h->p.kp[ik].ld;
+    if (nproj) *nproj = h->p.np;
+    if (nzq) *nzq = h->p.nzq;
+    return MB_OK;
+}
+
+mb_status mb_problem_gvectors(const mb_problem* h, int ik, int32_t* m, double* kg2) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "ik out of range");
+    const auto& kp = h->p.kp[ik];
+    if (m) std::memcpy(m, kp.m.data(), kp.m.size() * sizeof(int32_t));
+    if (kg2) std::memcpy(kg2, kp.kg2.data(), kp.kg2.size() * sizeof(double));
+    return MB_OK;
+}
+
+mb_status mb_problem_zrule(const mb_problem* h, double* zq, double* wq) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    if (zq) std::memcpy(zq, h->p.zq.data(), h->p.zq.size() * sizeof(double));
+    if (wq) std::memcpy(wq, h->p.wq.data(), h->p.wq.size() * sizeof(double));
+    return MB_OK;
+}
+
+mb_status mb_problem_zbands(const mb_problem* h, double* sband, double* dband) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    if (sband) std::memcpy(sband, h->p.sband.data(), h->p.sband.size() * sizeof(double));
+    if (dband) std::memcpy(dband, h->p.dband.data(), h->p.dband.size() * sizeof(double));
+    return MB_OK;
+}
+
+mb_status mb_problem_projectors(const mb_problem* h, int ik, double* F, double* Z, double* E) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "ik out of range");
+    const auto& p = h->p;
+    const auto& kp = p.kp[ik];
+    if (F)
+        for (int q = 0; q < p.np; ++q)
+            for (int g = 0; g < kp.ng; ++g) {
+                F[2 * ((size_t)q * kp.ng + g)] = kp.F[(size_t)q * kp.ld + g].real();
+                F[2 * ((size_t)q * kp.ng + g) + 1] = kp.F[(size_t)q * kp.ld + g].imag();
+            }
+    if (Z) std::memcpy(Z, p.Zp.data(), p.Zp.size() * sizeof(double));
+    if (E) std::memcpy(E, p.Ep.data(), p.Ep.size() * sizeof(double));
+    return MB_OK;
+}
+
+mb_status mb_problem_set_potential(mb_problem* h, const double* v) {
+    if (!h || !v) return set_error(MB_ERR_INVALID_ARG, "NULL argument");
+    auto& p = h->p;
+    if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, "host-only problem");
+    size_t n = (size_t)p.nzq * p.N1 * p.N2;
+    for (size_t e = 0; e < n; ++e)
+        if (!std::isfinite(v[e])) return set_error(MB_ERR_NONFINITE, "potential holds a NaN or Inf");
+    std::vector<float> vf(v, v + n);
+    MB_HIP_TRY(hipMemcpy(p.d_V, v, n * sizeof(double), hipMemcpyHostToDevice));
+    MB_HIP_TRY(hipMemcpy(p.d_Vf, vf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    return MB_OK;
+}
+
+mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,
+                     void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, c, y, nbands, ld, "hpsi_apply");
+    if (st != MB_OK) return st;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply: unknown precision");
+    size_t bytes = (size_t)nbands * h->p.nb * ld * (prec == MB_FP64 ? 16 : 8);
+    if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply: c and y overlap");
+    return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1,
+                       (hipStream_t)stream);
+}
+
+mb_status spsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,
+                     void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, c, y, nbands, ld, "spsi_apply");
+    if (st != MB_OK) return st;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "spsi_apply: unknown precision");
+    size_t bytes = (size_t)nbands * h->p.nb * ld * (prec == MB_FP64 ? 16 : 8);
+    if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
+        return set_error(MB_ERR_INVALID_ARG, "spsi_apply: c and y overlap");
+    if (nbands == 0) return MB_OK;
+    return mb::launch_spsi(&h->p, ik, c, y, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
+}
+
+mb_status s_solve(mb_problem* h, int ik, const void* r, void* x, int64_t nbands, int64_t ld, mb_precision prec,
+                  void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, r, x, nbands, ld, "s_solve");
+    if (st != MB_OK) return st;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "s_solve: unknown precision");
+    size_t bytes = (size_t)nbands * h->p.nb * ld * (prec == MB_FP64 ? 16 : 8);
+    if (nbands > 0 && r != x && mb::ranges_overlap(r, bytes, x, bytes))
+        return set_error(MB_ERR_INVALID_ARG, "s_solve: r and x partially overlap");
+    if (nbands == 0) return MB_OK;
+    return mb::launch_ssolve(&h->p, ik, r, x, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// internal access for the eigensolver translation unit
+namespace mb {
+Problem* problem_of(mb_problem* h) { return h ? &h->p : nullptr; }
+}  // namespace mb

@@ -1,0 +1,389 @@
+// Local-potential part of H c: one workgroup per (band, knot interval) does, for
+// each Gauss plane z_q of its interval,
+//   evaluate   psi(G, z_q) = sum_t B_{s-1+t}(z_q) c(G, s-1+t)      (kappa terms)
+//   scatter    psi(G) onto the in-plane grid (zero elsewhere)
+//   inverse 2D FFT (unnormalised, exp(+i G.rho)), only grid rows that hold G
+//   multiply   by V(rho, z_q) (real)
+//   forward 2D FFT, exp(-i G.rho) / (N1 N2), gather the sphere
+//   project    part(t, G) += w_q B_{s-1+t}(z_q) (V psi)(G, z_q)
+// with the plane resident in LDS throughout.  Each interval's kappa partial rows
+// are written once; the combine kernel adds the (up to kappa) partials of each
+// spline row without atomics.  These are the matrix elements of a local
+// potential in the mixed basis (Sec. II.B.1) with the in-plane transform taken
+// on the grid (circular convolution), applied without forming the matrix.
+#include <cmath>
+
+#include "cplx.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+constexpr int KORD = 4;
+constexpr int MAXB = 4;  // butterflies per thread per FFT stage
+
+template <typename TI, typename T>
+struct LocalArgs {
+    const cx<TI>* c;
+    cx<T>* part;
+    const T* bval;
+    const T* wbval;
+    const T* V;
+    const int32_t* gmap;
+    const int32_t* rows;
+    const cx<T>* tw1;
+    const cx<T>* tw2;
+    int nbands, ld, ng, nint, nq, nb, N1, N2, nrows;
+    T inv_n;
+    FftPlan p1, p2;
+};
+
+// y_k = sum_r v_r exp(sign 2 pi i r k / R) for R in {2, 3, 4, 5}
+template <typename T, int R>
+__device__ inline void butterfly(cx<T>* v, int sign) {
+    if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        cx<T> t2 = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        T s = (T)sign;
+        cx<T> t3 = mk<T>(-s * d.y, s * d.x);  // (sign i) * d
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    } else if constexpr (R == 3) {
+        const T c3 = (T)-0.5;
+        const T s3 = (T)0.86602540378443864676;  // sqrt(3)/2
+        cx<T> t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        cx<T> a = mk<T>(v[0].x + c3 * t.x, v[0].y + c3 * t.y);
+        T ss = (T)sign * s3;
+        cx<T> b = mk<T>(-ss * d.y, ss * d.x);
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(a, b);
+        v[2] = csub(a, b);
+    } else if constexpr (R == 5) {
+        const T c1 = (T)0.30901699437494742410;   // cos(2 pi / 5) = (sqrt 5 - 1) / 4
+        const T c2 = (T)-0.80901699437494742410;  // cos(4 pi / 5) = -(sqrt 5 + 1) / 4
+        const T s1 = (T)0.95105651629515357212;   // sin(2 pi / 5)
+        const T s2 = (T)0.58778525229247312917;   // sin(4 pi / 5)
+        cx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        cx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        T s = (T)sign;
+        cx<T> a1 = mk<T>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        cx<T> a2 = mk<T>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        cx<T> e1 = mk<T>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+        cx<T> e2 = mk<T>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+        cx<T> b1 = mk<T>(-s * e1.y, s * e1.x);
+        cx<T> b2 = mk<T>(-s * e2.y, s * e2.x);
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+}
+
+// One Stockham radix-R stage over `nlines` lines of length n held in LDS, in
+// place: every thread first loads its butterflies' inputs, the block
+// synchronises, then twiddles, transforms and stores.
+template <typename T, int NT, int R>
+__device__ inline void fft_stage(cx<T>* buf, const cx<T>* tw, int n, int Ns, int nlines,
+                                 const int32_t* rows, int rowmul, int stride, int sign) {
+    const int nbf = n / R;
+    const int total = nlines * nbf;
+    const int twstep = n / (Ns * R);
+    cx<T> v[MAXB][R];
+    int base[MAXB], jj[MAXB];
+#pragma unroll
+    for (int kk = 0; kk < MAXB; ++kk) {
+        int idx = threadIdx.x + kk * NT;
+        if (idx < total) {
+            int line = idx / nbf;
+            int j = idx - line * nbf;
+            int b = (rows ? rows[line] : line) * rowmul;
+            base[kk] = b;
+            jj[kk] = j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[kk][r] = buf[b + (j + r * nbf) * stride];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < MAXB; ++kk) {
+        int idx = threadIdx.x + kk * NT;
+        if (idx < total) {
+            int j = jj[kk];
+            int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[r * k * twstep];
+                if (sign < 0) w.y = -w.y;
+                v[kk][r] = cmul(v[kk][r], w);
+            }
+            butterfly<T, R>(v[kk], sign);
+            int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[base[kk] + (o + r * Ns) * stride] = v[kk][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ void fft_axis(cx<T>* buf, const cx<T>* tw, const FftPlan& pl, int nlines,
+                         const int32_t* rows, int rowmul, int stride, int sign) {
+    int Ns = 1;
+    for (int st = 0; st < pl.nr; ++st) {
+        int R = pl.rad[st];
+        switch (R) {
+            case 2: fft_stage<T, NT, 2>(buf, tw, pl.n, Ns, nlines, rows, rowmul, stride, sign); break;
+            case 3: fft_stage<T, NT, 3>(buf, tw, pl.n, Ns, nlines, rows, rowmul, stride, sign); break;
+            case 4: fft_stage<T, NT, 4>(buf, tw, pl.n, Ns, nlines, rows, rowmul, stride, sign); break;
+            default: fft_stage<T, NT, 5>(buf, tw, pl.n, Ns, nlines, rows, rowmul, stride, sign); break;
+        }
+        Ns *= R;
+    }
+}
+
+template <typename TI, typename T, int NT, int MAXG>
+__global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw);
+    const int npts = a.N1 * a.N2;
+    cx<T>* tw1 = grid + npts;
+    cx<T>* tw2 = tw1 + a.N1;
+    int32_t* rows = reinterpret_cast<int32_t*>(tw2 + a.N2);
+
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int b = (int)(L % (unsigned)a.nbands);
+    const int s = (int)(L / (unsigned)a.nbands);
+    if (s >= a.nint) return;
+
+    for (int e = threadIdx.x; e < a.N1; e += NT) tw1[e] = a.tw1[e];
+    for (int e = threadIdx.x; e < a.N2; e += NT) tw2[e] = a.tw2[e];
+    for (int e = threadIdx.x; e < a.nrows; e += NT) rows[e] = a.rows[e];
+
+    const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
+    cx<T> acc[KORD][MAXG];
+#pragma unroll
+    for (int t = 0; t < KORD; ++t)
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) acc[t][k] = mk<T>(0, 0);
+
+    for (int jq = 0; jq < a.nq; ++jq) {
+        const int q = s * a.nq + jq;
+        for (int e = threadIdx.x; e < npts; e += NT) grid[e] = mk<T>(0, 0);
+        __syncthreads();
+        T bv[KORD];
+#pragma unroll
+        for (int t = 0; t < KORD; ++t) bv[t] = a.bval[q * KORD + t];
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) {
+            int g = threadIdx.x + k * NT;
+            if (g < a.ng) {
+                cx<T> psi = mk<T>(0, 0);
+#pragma unroll
+                for (int t = 0; t < KORD; ++t) {
+                    int row = s - 1 + t;
+                    if (row >= 0 && row < a.nb) {
+                        cx<TI> cv = cb[(size_t)row * a.ld + g];
+                        psi.x = fma(bv[t], (T)cv.x, psi.x);
+                        psi.y = fma(bv[t], (T)cv.y, psi.y);
+                    }
+                }
+                grid[a.gmap[g]] = psi;
+            }
+        }
+        __syncthreads();
+        // inverse transform: rows (axis 2) that hold G, then all columns (axis 1)
+        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, a.N2, 1, +1);
+        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, a.N2, +1);
+        const T* Vq = a.V + (size_t)q * npts;
+        for (int e = threadIdx.x; e < npts; e += NT) {
+            T v = Vq[e];
+            cx<T> u = grid[e];
+            grid[e] = mk<T>(u.x * v, u.y * v);
+        }
+        __syncthreads();
+        // forward transform: all columns, then the rows that hold G
+        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, a.N2, -1);
+        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, a.N2, 1, -1);
+        T wb[KORD];
+#pragma unroll
+        for (int t = 0; t < KORD; ++t) wb[t] = a.wbval[q * KORD + t] * a.inv_n;
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) {
+            int g = threadIdx.x + k * NT;
+            if (g < a.ng) {
+                cx<T> u = grid[a.gmap[g]];
+#pragma unroll
+                for (int t = 0; t < KORD; ++t) {
+                    acc[t][k].x = fma(wb[t], u.x, acc[t][k].x);
+                    acc[t][k].y = fma(wb[t], u.y, acc[t][k].y);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    cx<T>* pb = a.part + ((size_t)b * a.nint + s) * KORD * a.ld;
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k) {
+        int g = threadIdx.x + k * NT;
+        if (g < a.ng) {
+#pragma unroll
+            for (int t = 0; t < KORD; ++t) pb[(size_t)t * a.ld + g] = acc[t][k];
+        }
+    }
+}
+
+int max_stage_work(const FftPlan& pl, int nlines) {
+    int w = 0;
+    for (int st = 0; st < pl.nr; ++st) w = std::max(w, nlines * (pl.n / pl.rad[st]));
+    return w;
+}
+
+template <typename TI, typename T, int NT, int MAXG>
+mb_status run_local(const LocalArgs<TI, T>& a, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    auto kern = k_local<TI, T, NT, MAXG>;
+    if (!attr_set) {
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds > 65536 ? 163840 : 65536));
+        attr_set = true;
+    }
+    unsigned nblocks = (unsigned)a.nbands * (unsigned)a.nint;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    LocalArgs<TI, T> a;
+    a.c = (const cx<TI>*)c;
+    a.part = (cx<T>*)part;
+    const bool dbl = sizeof(T) == 8;
+    a.bval = (const T*)(dbl ? (const void*)p->d_bval : (const void*)p->d_bvalf);
+    a.wbval = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
+    a.V = (const T*)(dbl ? (const void*)p->d_V : (const void*)p->d_Vf);
+    a.gmap = kp.d_gmap;
+    a.rows = kp.d_rows;
+    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
+    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
+    a.nbands = nbands;
+    a.ld = ld;
+    a.ng = kp.ng;
+    a.nint = p->nint;
+    a.nq = p->nq;
+    a.nb = p->nb;
+    a.N1 = p->N1;
+    a.N2 = p->N2;
+    a.nrows = (int)kp.rows.size();
+    a.inv_n = (T)(1.0 / ((double)p->N1 * p->N2));
+    a.p1 = p->plan1;
+    a.p2 = p->plan2;
+    size_t lds = sizeof(cx<T>) * ((size_t)p->N1 * p->N2 + p->N1 + p->N2) + sizeof(int32_t) * a.nrows;
+    if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
+    int work = std::max(max_stage_work(p->plan2, a.nrows), max_stage_work(p->plan1, p->N2));
+    // smallest block that covers the FFT stages and the G set
+    if (work <= 256 * MAXB && kp.ng <= 256 * 2) return run_local<TI, T, 256, 2>(a, lds, s);
+    if (work <= 256 * MAXB && kp.ng <= 256 * 4) return run_local<TI, T, 256, 4>(a, lds, s);
+    if (work <= 512 * MAXB && kp.ng <= 512 * 4) return run_local<TI, T, 512, 4>(a, lds, s);
+    if (work <= 1024 * MAXB && kp.ng <= 1024 * 4) return run_local<TI, T, 1024, 4>(a, lds, s);
+    if (work <= 1024 * MAXB && kp.ng <= 1024 * 8) return run_local<TI, T, 1024, 8>(a, lds, s);
+    return set_error(MB_ERR_INVALID_ARG, "in-plane grid or G set too large for the local kernel");
+}
+
+// V(rho_j, z_q) = sum_atoms sum_t A_t sum_L exp(-|r - R - L|^2 / w_t^2) on the grid.
+struct VTerm {
+    double X, Y, Z, A, inv_w2;
+    int nimg;
+};
+
+__global__ void k_vgrid(double* V, float* Vf, const VTerm* terms, int nterms, int N1, int N2, int nzq,
+                        const double* zq, double a1x, double a1y, double a2x, double a2y) {
+    const int npts = N1 * N2;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)npts * nzq) return;
+    int q = (int)(idx / npts);
+    int e = (int)(idx - (size_t)q * npts);
+    int j1 = e / N2, j2 = e - j1 * N2;
+    double f1 = (double)j1 / N1, f2 = (double)j2 / N2;
+    double x = f1 * a1x + f2 * a2x, y = f1 * a1y + f2 * a2y, z = zq[q];
+    double v = 0.0;
+    for (int t = 0; t < nterms; ++t) {
+        VTerm m = terms[t];
+        double dz = z - m.Z;
+        double ez = dz * dz * m.inv_w2;
+        if (ez > 60.0) continue;
+        double sum = 0.0;
+        for (int n1 = -m.nimg; n1 <= m.nimg; ++n1)
+            for (int n2 = -m.nimg; n2 <= m.nimg; ++n2) {
+                double dx = x - m.X - n1 * a1x - n2 * a2x;
+                double dy = y - m.Y - n1 * a1y - n2 * a2y;
+                double r2 = (dx * dx + dy * dy) * m.inv_w2;
+                if (r2 < 60.0) sum += exp(-r2);
+            }
+        v += m.A * exp(-ez) * sum;
+    }
+    V[idx] = v;
+    Vf[idx] = (float)v;
+}
+
+}  // namespace
+
+mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
+                       hipStream_t s) {
+    if (p->order != KORD) return set_error(MB_ERR_INVALID_ARG, "GPU kernels support order 4 only");
+    if (prec == 0) return local_impl<double, double>(p, ik, c, part, nbands, ld, s);
+    if (prec == 1) return local_impl<float, float>(p, ik, c, part, nbands, ld, s);
+    return local_impl<double, float>(p, ik, c, part, nbands, ld, s);
+}
+
+mb_status launch_vgrid(Problem* p, hipStream_t s) {
+    std::vector<VTerm> terms;
+    double h1 = p->area / std::hypot(p->a2[0], p->a2[1]);
+    double h2 = p->area / std::hypot(p->a1[0], p->a1[1]);
+    double hmin = std::min(h1, h2);
+    for (const auto& at : p->atoms) {
+        const mb_species& sp = p->species[at.species];
+        for (int t = 0; t < sp.ngauss; ++t) {
+            VTerm m;
+            m.X = at.pos[0];
+            m.Y = at.pos[1];
+            m.Z = at.pos[2];
+            m.A = sp.gauss_A[t];
+            m.inv_w2 = 1.0 / (sp.gauss_w[t] * sp.gauss_w[t]);
+            // images closer than sqrt(60) w (exp(-60) ~ 1e-26) to the cell
+            m.nimg = (int)std::ceil(std::sqrt(60.0) * sp.gauss_w[t] / hmin) + 1;
+            terms.push_back(m);
+        }
+    }
+    size_t n = (size_t)p->nzq * p->N1 * p->N2;
+    if (terms.empty()) {
+        MB_HIP_TRY(hipMemsetAsync(p->d_V, 0, n * sizeof(double), s));
+        MB_HIP_TRY(hipMemsetAsync(p->d_Vf, 0, n * sizeof(float), s));
+        return MB_OK;
+    }
+    VTerm* d_terms = nullptr;
+    double* d_zq = nullptr;
+    MB_HIP_TRY(hipMalloc(&d_terms, terms.size() * sizeof(VTerm)));
+    MB_HIP_TRY(hipMalloc(&d_zq, p->zq.size() * sizeof(double)));
+    MB_HIP_TRY(hipMemcpy(d_terms, terms.data(), terms.size() * sizeof(VTerm), hipMemcpyHostToDevice));
+    MB_HIP_TRY(hipMemcpy(d_zq, p->zq.data(), p->zq.size() * sizeof(double), hipMemcpyHostToDevice));
+    unsigned nblk = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_vgrid, dim3(nblk), dim3(256), 0, s, p->d_V, p->d_Vf, d_terms, (int)terms.size(),
+                       p->N1, p->N2, p->nzq, d_zq, p->a1[0], p->a1[1], p->a2[0], p->a2[1]);
+    MB_HIP_TRY(hipGetLastError());
+    MB_HIP_TRY(hipStreamSynchronize(s));
+    MB_HIP_TRY(hipFree(d_terms));
+    MB_HIP_TRY(hipFree(d_zq));
+    return MB_OK;
+}
+
+}  // namespace mb

@@ -1,0 +1,315 @@
+// Operators that are banded along z and diagonal in G (Sec. II.B.1):
+//   overlap  S = I_G (x) S_z,   kinetic T = 1/2 (D_z + |k+G|^2 S_z) per G,
+// both with bandwidth kappa - 1 = 3.  The combine kernel reads c once per
+// (band, row chunk, G) and writes
+//   y(G,i) = (T c)(G,i) + sum of the local partials of row i
+//            + sum_p F_p(G) Z_p(i) E_p <beta_p|c>
+// so the kinetic term, the projection of the local potential and the
+// Kleinman-Bylander expansion leave in one pass.  s_solve and the
+// preconditioner are forward / back substitutions with banded Cholesky factors.
+#include <cmath>
+
+#include "cplx.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+constexpr int KORD = 4;
+constexpr int CH = 16;  // rows per thread in the combine kernel
+
+template <typename TI, typename T>
+struct CombineArgs {
+    const cx<TI>* c;
+    const cx<T>* part;    // [b][s][t][ld] or null
+    const cx<T>* proj;    // [b][np] (already times E_p) or null
+    const cx<T>* F;       // [np][ld]
+    const T* Z;           // [np][nb]
+    const int32_t* zwin;  // [np][2]
+    cx<TI>* y;            // may be null
+    cx<TI>* sy;           // may be null
+    const double* sband;
+    const double* dband;
+    const double* kg2;
+    int nbands, ld, ng, nb, nint, np;
+};
+
+template <typename TI, typename T>
+__global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nchunk = (a.nb + CH - 1) / CH;
+    const int b = blockIdx.y / nchunk;
+    const int i0 = (blockIdx.y - b * nchunk) * CH;
+    if (g >= a.ld) return;
+    const size_t vb = (size_t)b * a.nb * a.ld;
+    const int i1 = min(i0 + CH, a.nb);
+    if (g >= a.ng) {
+        for (int i = i0; i < i1; ++i) {
+            if (a.y) a.y[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
+            if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
+        }
+        return;
+    }
+    const cx<TI>* cb = a.c + vb + g;
+    // sliding window of c rows i-3 .. i+3 in TI precision
+    cx<TI> w[2 * KORD - 1];
+#pragma unroll
+    for (int d = 0; d < 2 * KORD - 1; ++d) {
+        int j = i0 - (KORD - 1) + d;
+        w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
+    }
+    const double kk = a.y ? 0.5 * a.kg2[g] : 0.0;
+    for (int i = i0; i < i1; ++i) {
+        // banded products with symmetric S_z, D_z
+        double sr = 0, si = 0, tr = 0, ti = 0;
+#pragma unroll
+        for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
+            int j = i + d;
+            if (j < 0 || j >= a.nb) continue;
+            int lo = d >= 0 ? i : j;
+            int dd = d >= 0 ? d : -d;
+            double sv = a.sband[lo * KORD + dd];
+            cx<TI> cv = w[d + KORD - 1];
+            sr += sv * (double)cv.x;
+            si += sv * (double)cv.y;
+            if (a.y) {
+                double tv = 0.5 * a.dband[lo * KORD + dd];
+                tr += tv * (double)cv.x;
+                ti += tv * (double)cv.y;
+            }
+        }
+        if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
+        if (a.y) {
+            double yr = tr + kk * sr, yi = ti + kk * si;
+            if (a.part) {
+                T pr = 0, pi = 0;
+#pragma unroll
+                for (int t = 0; t < KORD; ++t) {
+                    int s = i + 1 - t;
+                    if (s < 0 || s >= a.nint) continue;
+                    cx<T> v = a.part[(((size_t)b * a.nint + s) * KORD + t) * a.ld + g];
+                    pr += v.x;
+                    pi += v.y;
+                }
+                yr += (double)pr;
+                yi += (double)pi;
+            }
+            if (a.proj) {
+                cx<T> acc = mk<T>(0, 0);
+                for (int p = 0; p < a.np; ++p) {
+                    if (i < a.zwin[2 * p] || i > a.zwin[2 * p + 1]) continue;
+                    cx<T> coef = cscale(a.proj[(size_t)b * a.np + p], a.Z[(size_t)p * a.nb + i]);
+                    cfma(acc, a.F[(size_t)p * a.ld + g], coef);
+                }
+                yr += (double)acc.x;
+                yi += (double)acc.y;
+            }
+            a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
+        }
+        // slide the window
+#pragma unroll
+        for (int d = 0; d < 2 * KORD - 2; ++d) w[d] = w[d + 1];
+        int jn = i + KORD;
+        w[2 * KORD - 2] = (jn < a.nb) ? cb[(size_t)jn * a.ld] : mk<TI>(0, 0);
+    }
+}
+
+// x = (L L^T)^{-1} r along i with a banded lower factor lf[i][d] = L[i][i-d]
+// (shared, pstride = 0) or per G (lf[(i*4+d)*ld + g], pstride = 1).
+template <typename TI>
+__device__ inline void band_solve(const cx<TI>* r, cx<TI>* x, const double* lf, int nb, int ld, int g,
+                                  int per_g, double theta, const cx<TI>* sv) {
+    // forward: L w = r   (r - theta * sv when sv != null)
+    cx<double> h1 = mk<double>(0, 0), h2 = h1, h3 = h1;  // w_{i-1}, w_{i-2}, w_{i-3}
+    for (int i = 0; i < nb; ++i) {
+        size_t o = (size_t)i * ld + g;
+        cx<TI> rv = r[o];
+        double vr = (double)rv.x, vi = (double)rv.y;
+        if (sv) {
+            cx<TI> s = sv[o];
+            vr -= theta * (double)s.x;
+            vi -= theta * (double)s.y;
+        }
+        auto L = [&](int row, int d) -> double {
+            return per_g ? lf[((size_t)row * KORD + d) * ld + g] : lf[row * KORD + d];
+        };
+        if (i >= 1) { double l = L(i, 1); vr -= l * h1.x; vi -= l * h1.y; }
+        if (i >= 2) { double l = L(i, 2); vr -= l * h2.x; vi -= l * h2.y; }
+        if (i >= 3) { double l = L(i, 3); vr -= l * h3.x; vi -= l * h3.y; }
+        double inv = 1.0 / L(i, 0);
+        cx<double> wv = mk<double>(vr * inv, vi * inv);
+        h3 = h2;
+        h2 = h1;
+        h1 = wv;
+        x[o] = mk<TI>((TI)wv.x, (TI)wv.y);
+    }
+    // back: L^T x = w
+    h1 = mk<double>(0, 0);
+    h2 = h1;
+    h3 = h1;  // x_{i+1}, x_{i+2}, x_{i+3}
+    for (int i = nb - 1; i >= 0; --i) {
+        size_t o = (size_t)i * ld + g;
+        cx<TI> wv = x[o];
+        double vr = (double)wv.x, vi = (double)wv.y;
+        auto L = [&](int row, int d) -> double {
+            return per_g ? lf[((size_t)row * KORD + d) * ld + g] : lf[row * KORD + d];
+        };
+        if (i + 1 < nb) { double l = L(i + 1, 1); vr -= l * h1.x; vi -= l * h1.y; }
+        if (i + 2 < nb) { double l = L(i + 2, 2); vr -= l * h2.x; vi -= l * h2.y; }
+        if (i + 3 < nb) { double l = L(i + 3, 3); vr -= l * h3.x; vi -= l * h3.y; }
+        double inv = 1.0 / L(i, 0);
+        cx<double> xv = mk<double>(vr * inv, vi * inv);
+        h3 = h2;
+        h2 = h1;
+        h1 = xv;
+        x[o] = mk<TI>((TI)xv.x, (TI)xv.y);
+    }
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void k_ssolve(const cx<TI>* r, cx<TI>* x, const double* lband, int nbands,
+                                                int ng, int nb, int ld) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (g >= ld || b >= nbands) return;
+    const size_t vb = (size_t)b * nb * ld;
+    if (g >= ng) {
+        for (int i = 0; i < nb; ++i) x[vb + (size_t)i * ld + g] = mk<TI>(0, 0);
+        return;
+    }
+    band_solve<TI>(r + vb, x + vb, lband, nb, ld, g, 0, 0.0, nullptr);
+}
+
+// banded Cholesky of 1/2 D_z + (1/2 |k+G|^2 + sigma) S_z for every G
+__global__ void k_prec_factor(double* pf, const double* sband, const double* dband, const double* kg2,
+                              double sigma, int ng, int nb, int ld, int* fail) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const double sh = 0.5 * kg2[g] + sigma;
+    auto M = [&](int i, int j) -> double {
+        if (i > j) { int t = i; i = j; j = t; }
+        return 0.5 * dband[i * KORD + (j - i)] + sh * sband[i * KORD + (j - i)];
+    };
+    auto L = [&](int i, int j) -> double& { return pf[((size_t)i * KORD + (i - j)) * ld + g]; };
+    for (int i = 0; i < nb; ++i) {
+        int j0 = max(0, i - (KORD - 1));
+        for (int j = j0; j <= i; ++j) {
+            double sum = M(i, j);
+            for (int k = max(j0, j - (KORD - 1)); k < j; ++k) sum -= L(i, k) * L(j, k);
+            if (j == i) {
+                if (!(sum > 0)) { atomicExch(fail, 1); sum = 1.0; }
+                L(i, i) = sqrt(sum);
+            } else {
+                L(i, j) = sum / L(j, j);
+            }
+        }
+        for (int d = i + 1; d < KORD; ++d) pf[((size_t)i * KORD + d) * ld + g] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prec_apply(const cx<double>* h, const cx<double>* sv,
+                                                    const double* theta, const int32_t* sel, cx<double>* x,
+                                                    const double* pf, int nvec, int ng, int nb, int ld) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (g >= ld || j >= nvec) return;
+    const int src = sel ? sel[j] : j;
+    const size_t vo = (size_t)j * nb * ld, vi = (size_t)src * nb * ld;
+    if (g >= ng) {
+        for (int i = 0; i < nb; ++i) x[vo + (size_t)i * ld + g] = mk<double>(0, 0);
+        return;
+    }
+    band_solve<double>(h + vi, x + vo, pf, nb, ld, g, 1, theta ? theta[j] : 0.0, sv ? sv + vi : nullptr);
+}
+
+template <typename TI, typename T>
+mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
+                       void* sy, int nbands, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    CombineArgs<TI, T> a;
+    const bool dbl = sizeof(T) == 8;
+    a.c = (const cx<TI>*)c;
+    a.part = (const cx<T>*)part;
+    a.proj = (const cx<T>*)proj;
+    a.F = (const cx<T>*)(dbl ? kp.d_F64 : kp.d_F32);
+    a.Z = (const T*)(dbl ? (const void*)p->d_Z : (const void*)p->d_Zf);
+    a.zwin = p->d_zwin;
+    a.y = (cx<TI>*)y;
+    a.sy = (cx<TI>*)sy;
+    a.sband = p->d_sband;
+    a.dband = p->d_dband;
+    a.kg2 = kp.d_kg2;
+    a.nbands = nbands;
+    a.ld = ld;
+    a.ng = kp.ng;
+    a.nb = p->nb;
+    a.nint = p->nint;
+    a.np = p->np;
+    if (p->np == 0) a.proj = nullptr;
+    int nchunk = (p->nb + CH - 1) / CH;
+    dim3 grid((ld + 255) / 256, nbands * nchunk);
+    hipLaunchKernelGGL((k_combine<TI, T>), grid, dim3(256), 0, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+}  // namespace
+
+// prec: 0 = FP64 (c128), 1 = FP32 (c64), 2 = c128 vectors with FP32 local / nonlocal parts
+mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
+                         void* sy, int nbands, int ld, int prec, hipStream_t s) {
+    if (prec == 0) return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s);
+    if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
+    return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
+}
+
+mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec, hipStream_t s) {
+    if (prec == 1) return combine_impl<float, float>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
+    return combine_impl<double, double>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
+}
+
+mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    dim3 grid((ld + 255) / 256, nbands);
+    if (prec == 1)
+        hipLaunchKernelGGL(k_ssolve<float>, grid, dim3(256), 0, s, (const cx<float>*)r, (cx<float>*)x,
+                           p->d_lband, nbands, kp.ng, p->nb, ld);
+    else
+        hipLaunchKernelGGL(k_ssolve<double>, grid, dim3(256), 0, s, (const cx<double>*)r, (cx<double>*)x,
+                           p->d_lband, nbands, kp.ng, p->nb, ld);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s) {
+    KPoint& kp = p->kp[ik];
+    if (kp.d_pfac && kp.pfac_sigma == sigma) return MB_OK;
+    if (!kp.d_pfac) MB_HIP_TRY(hipMalloc(&kp.d_pfac, (size_t)p->nb * KORD * kp.ld * sizeof(double)));
+    int* d_fail = nullptr;
+    MB_HIP_TRY(hipMalloc(&d_fail, sizeof(int)));
+    MB_HIP_TRY(hipMemsetAsync(d_fail, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_prec_factor, dim3((kp.ng + 127) / 128), dim3(128), 0, s, kp.d_pfac, p->d_sband,
+                       p->d_dband, kp.d_kg2, sigma, kp.ng, p->nb, kp.ld, d_fail);
+    MB_HIP_TRY(hipGetLastError());
+    int fail = 0;
+    MB_HIP_TRY(hipMemcpyAsync(&fail, d_fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    MB_HIP_TRY(hipStreamSynchronize(s));
+    MB_HIP_TRY(hipFree(d_fail));
+    if (fail) return set_error(MB_ERR_NOT_SPD, "preconditioner block not positive definite");
+    kp.pfac_sigma = sigma;
+    return MB_OK;
+}
+
+mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta,
+                            const int32_t* sel, void* x, int nvec, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    if (!kp.d_pfac || ld != kp.ld) return set_error(MB_ERR_INVALID_ARG, "preconditioner not built for this ld");
+    dim3 grid((ld + 255) / 256, nvec);
+    hipLaunchKernelGGL(k_prec_apply, grid, dim3(256), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
+                       sel, (cx<double>*)x, kp.d_pfac, nvec, kp.ng, p->nb, ld);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+}  // namespace mb

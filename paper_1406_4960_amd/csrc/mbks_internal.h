@@ -1,0 +1,145 @@
+// Internal declarations of the mixed-basis operator library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbks.h"
+
+namespace mb {
+
+using zd = std::complex<double>;
+
+// Radix plan of one FFT axis: n = prod rad[0..nr).
+struct FftPlan {
+    int n;
+    int nr;
+    int rad[12];
+};
+
+// Per-k-point tables.
+struct KPoint {
+    int ng = 0;
+    int ld = 0;
+    std::vector<int32_t> m;       // ng x 2
+    std::vector<double> kg;       // ng x 2, Cartesian k+G
+    std::vector<double> kg2;      // ng
+    std::vector<int32_t> gmap;    // ng: grid index j1 * N2 + j2 of G
+    std::vector<int32_t> rows;    // grid rows j1 that hold sphere points
+    std::vector<zd> F;            // np x ld, in-plane projector factors (padding zero)
+    // device copies
+    double* d_kg2 = nullptr;
+    float* d_kg2f = nullptr;
+    int32_t* d_gmap = nullptr;
+    int32_t* d_rows = nullptr;
+    void* d_F64 = nullptr;        // np x ld complex128
+    void* d_F32 = nullptr;        // np x ld complex64
+    // preconditioner factors (T + sigma S) per G, [i][d][ld] doubles, built on demand
+    double* d_pfac = nullptr;
+    double pfac_sigma = -1.0;
+};
+
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Problem {
+    // description
+    double a1[2], a2[2];
+    double area = 0.0;
+    double b1[2], b2[2];
+    int order = 4;
+    int nint = 0;        // knot intervals
+    int nb = 0;          // kept splines
+    int nq = 0;          // Gauss points per interval
+    int nzq = 0;         // nq * nint
+    int N1 = 0, N2 = 0;
+    int np = 0;          // projectors
+    std::vector<double> bp;      // breakpoints
+    std::vector<double> kfrac;   // nk x 2
+    std::vector<mb_species> species;
+    std::vector<mb_atom> atoms;
+
+    // z tables
+    std::vector<double> zq, wq;  // nzq
+    std::vector<double> bval;    // nzq x order: kept spline (s - 1 + t) at point q of interval s
+    std::vector<double> wbval;   // w_q * bval
+    std::vector<double> sband, dband;  // nb x order: M[i][i + d]
+    std::vector<double> lband;   // nb x order: Cholesky L[i][i - d]
+
+    // projectors
+    std::vector<double> Zp;      // np x nb
+    std::vector<double> Ep;      // np
+    std::vector<int32_t> zwin;   // np x 2: first, last row with a non-negligible Z
+    std::vector<KPoint> kp;
+
+    FftPlan plan1{}, plan2{};
+
+    // device
+    int device = -1;
+    double* d_bval = nullptr;  float* d_bvalf = nullptr;
+    double* d_wbval = nullptr; float* d_wbvalf = nullptr;
+    double* d_sband = nullptr; float* d_sbandf = nullptr;
+    double* d_dband = nullptr; float* d_dbandf = nullptr;
+    double* d_lband = nullptr; float* d_lbandf = nullptr;
+    double* d_Z = nullptr;     float* d_Zf = nullptr;
+    double* d_E = nullptr;     float* d_Ef = nullptr;
+    int32_t* d_zwin = nullptr;
+    double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
+    void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)
+    void* d_tw2 = nullptr; void* d_tw2f = nullptr;
+
+    Workspace ws_part;    // local-potential partial projections
+    Workspace ws_proj;    // projections <beta|c>
+    Workspace ws_lz;      // eigensolver vectors
+    Workspace ws_small;   // eigensolver small matrices
+    Workspace ws_conv;    // precision conversion buffers
+};
+
+// status helpers
+mb_status set_error(mb_status s, const std::string& msg);
+#define MB_HIP_TRY(call)                                                               \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::mb::set_error(MB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// host set-up (setup.cpp)
+mb_status build_tables(const mb_desc* d, Problem* p);
+bool fft_plan(int n, FftPlan* plan);
+int recommended_ld(int ng);
+
+// device upload (capi.hip)
+mb_status upload(Problem* p);
+mb_status ensure_ws(Workspace& w, size_t bytes);
+
+// kernel launchers (k_*.hip); prec 0 = fp64, 1 = fp32
+mb_status launch_vgrid(Problem* p, hipStream_t s);
+mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
+                       int prec, hipStream_t s);
+mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
+                            int prec, hipStream_t s);
+// y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null
+mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
+                         void* y, void* sy, int nbands, int ld, int prec, hipStream_t s);
+mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
+                      hipStream_t s);
+mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
+                        hipStream_t s);
+mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s);
+// x[j] = K (h[j] - theta[j] s[j]), K = (T + sigma S)^{-1}; theta on device (nvec doubles),
+// sel: optional device index list mapping output j to input vector sel[j]
+mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta,
+                            const int32_t* sel, void* x, int nvec, int ld, hipStream_t s);
+
+// composite operator (capi.hip): y = H c (and sy = S c if non-null), FP64 or FP32
+mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec,
+                  hipStream_t s);
+
+}  // namespace mb

@@ -1,0 +1,277 @@
+"""Python binding of libmbks (argument marshalling only).
+
+Every operation runs in the HIP library; this module converts the problem
+dictionary into the C description, hands torch device buffers and the current
+stream to the C entry points, and turns status codes into exceptions.  It never
+computes a step of the method itself; if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_uint64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmbks.so")
+
+MB_FP64, MB_FP32, MB_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": MB_FP64, "fp32": MB_FP32, "bf16x3": MB_BF16X3}
+STATUS = {0: "MB_OK", -1: "MB_ERR_INVALID_ARG", -2: "MB_ERR_NOT_SPD", -3: "MB_ERR_NOT_CONVERGED",
+          -4: "MB_ERR_NONFINITE", -5: "MB_ERR_OOM", -6: "MB_ERR_HIP", -7: "MB_ERR_NO_DEVICE"}
+MB_MAX_GAUSS = 4
+
+# every symbol the C header declares
+EXPORTS = ("mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
+           "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
+           "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
+           "mb_last_error")
+
+
+class MbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MbSpecies(ctypes.Structure):
+    _fields_ = [("ngauss", c_int32), ("gauss_A", c_double * MB_MAX_GAUSS), ("gauss_w", c_double * MB_MAX_GAUSS),
+                ("nonlocal_", c_int32), ("alpha_s", c_double), ("alpha_p", c_double), ("E_s", c_double),
+                ("E_p", c_double)]
+
+
+class MbAtom(ctypes.Structure):
+    _fields_ = [("species", c_int32), ("pos", c_double * 3)]
+
+
+class MbDesc(ctypes.Structure):
+    _fields_ = [("a1", c_double * 2), ("a2", c_double * 2), ("order", c_int32), ("nbreak", c_int32),
+                ("breakpoints", POINTER(c_double)), ("nq", c_int32), ("grid", c_int32 * 2),
+                ("gset_kind", c_int32), ("mmax", c_int32 * 2), ("ecut", c_double), ("nk", c_int32),
+                ("kfrac", POINTER(c_double)), ("nspecies", c_int32), ("species", POINTER(MbSpecies)),
+                ("natoms", c_int32), ("atoms", POINTER(MbAtom))]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("block", c_int32), ("krylov", c_int32), ("krylov_global", c_int32), ("max_iter", c_int32),
+                ("tol", c_double), ("sigma", c_double), ("switch_tol", c_double), ("seed", c_uint64)]
+
+
+class LanczosInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("iters_low", c_int32), ("h_applies", c_int64), ("h_applies_low", c_int64),
+                ("max_resid", c_double), ("time_ms", c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the in-tree library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmbks.so not found at {path}; run `python -m paper_1406_4960_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = c_void_p
+    lib.mb_problem_create.argtypes = [POINTER(MbDesc), c_int, POINTER(vp)]
+    lib.mb_problem_destroy.argtypes = [vp]
+    lib.mb_problem_dims.argtypes = [vp, c_int] + [POINTER(c_int64)] * 5
+    lib.mb_problem_gvectors.argtypes = [vp, c_int, vp, vp]
+    lib.mb_problem_zrule.argtypes = [vp, vp, vp]
+    lib.mb_problem_zbands.argtypes = [vp, vp, vp]
+    lib.mb_problem_projectors.argtypes = [vp, c_int, vp, vp, vp]
+    lib.mb_problem_set_potential.argtypes = [vp, vp]
+    for name in ("hpsi_apply", "spsi_apply", "s_solve"):
+        getattr(lib, name).argtypes = [vp, c_int, vp, vp, c_int64, c_int64, c_int, vp]
+    lib.mb_lanczos_default_opts.argtypes = [POINTER(LanczosOpts)]
+    lib.mb_lanczos_default_opts.restype = None
+    lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
+                                   POINTER(LanczosInfo), vp]
+    lib.mb_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("mb_lanczos_default_opts", "mb_last_error"):
+            getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise MbError(status, _lib.mb_last_error().decode())
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _stream(stream):
+    if stream is not None:
+        return c_void_p(stream)
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+class Problem:
+    """Handle of one problem description; device=None builds host tables only."""
+
+    def __init__(self, desc: dict, device: int | None = 0):
+        lib = load()
+        self.desc = desc
+        keep = []
+        bp = np.ascontiguousarray(desc["breakpoints"], dtype=np.float64)
+        kf = np.ascontiguousarray(np.array(desc["kpts"], dtype=np.float64).reshape(-1, 2))
+        keep += [bp, kf]
+        sp_arr = (MbSpecies * max(1, len(desc["species"])))()
+        for n, sp in enumerate(desc["species"]):
+            g = sp.get("gauss", [])
+            if len(g) > MB_MAX_GAUSS:
+                raise ValueError("too many Gaussian terms")
+            sp_arr[n].ngauss = len(g)
+            for t, (A, w) in enumerate(g):
+                sp_arr[n].gauss_A[t] = A
+                sp_arr[n].gauss_w[t] = w
+            nl = bool(sp.get("nonlocal", False))
+            sp_arr[n].nonlocal_ = int(nl)
+            if nl:
+                sp_arr[n].alpha_s = sp["alpha_s"]
+                sp_arr[n].alpha_p = sp["alpha_p"]
+                sp_arr[n].E_s = sp["E_s"]
+                sp_arr[n].E_p = sp["E_p"]
+        at_arr = (MbAtom * max(1, len(desc["atoms"])))()
+        for n, at in enumerate(desc["atoms"]):
+            at_arr[n].species = at["species"]
+            for c in range(3):
+                at_arr[n].pos[c] = at["pos"][c]
+        d = MbDesc()
+        d.a1[:] = list(desc["a1"])
+        d.a2[:] = list(desc["a2"])
+        d.order = desc["order"]
+        d.nbreak = len(bp)
+        d.breakpoints = bp.ctypes.data_as(POINTER(c_double))
+        d.nq = desc["nq"]
+        d.grid[:] = list(desc["grid"])
+        rule = desc["gset"]
+        if rule["kind"] == "box":
+            d.gset_kind = 0
+            d.mmax[:] = list(rule["mmax"])
+        else:
+            d.gset_kind = 1
+            d.ecut = rule["ecut"]
+        d.nk = len(kf)
+        d.kfrac = kf.ctypes.data_as(POINTER(c_double))
+        d.nspecies = len(desc["species"])
+        d.species = sp_arr
+        d.natoms = len(desc["atoms"])
+        d.atoms = at_arr
+        h = c_void_p()
+        _check(lib.mb_problem_create(ctypes.byref(d), -1 if device is None else int(device), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self.nk = len(kf)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mb_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # --- queries -------------------------------------------------------------
+    def dims(self, ik: int = 0):
+        v = [c_int64() for _ in range(5)]
+        _check(load().mb_problem_dims(self.h, ik, *[ctypes.byref(x) for x in v]))
+        ng, nb, ld, npj, nzq = (x.value for x in v)
+        return {"ng": ng, "nb": nb, "ld": ld, "np": npj, "nzq": nzq}
+
+    def gvectors(self, ik: int = 0):
+        dm = self.dims(ik)
+        m = np.zeros((dm["ng"], 2), dtype=np.int32)
+        kg2 = np.zeros(dm["ng"])
+        _check(load().mb_problem_gvectors(self.h, ik, c_void_p(m.ctypes.data), c_void_p(kg2.ctypes.data)))
+        return m, kg2
+
+    def zrule(self):
+        n = self.dims(0)["nzq"]
+        zq = np.zeros(n)
+        wq = np.zeros(n)
+        _check(load().mb_problem_zrule(self.h, c_void_p(zq.ctypes.data), c_void_p(wq.ctypes.data)))
+        return zq, wq
+
+    def zbands(self):
+        nb = self.dims(0)["nb"]
+        k = self.desc["order"]
+        s = np.zeros((nb, k))
+        d = np.zeros((nb, k))
+        _check(load().mb_problem_zbands(self.h, c_void_p(s.ctypes.data), c_void_p(d.ctypes.data)))
+        return s, d
+
+    def projectors(self, ik: int = 0):
+        dm = self.dims(ik)
+        F = np.zeros((dm["np"], dm["ng"]), dtype=np.complex128)
+        Z = np.zeros((dm["np"], dm["nb"]))
+        E = np.zeros(dm["np"])
+        _check(load().mb_problem_projectors(self.h, ik, c_void_p(F.ctypes.data), c_void_p(Z.ctypes.data),
+                                            c_void_p(E.ctypes.data)))
+        return F, Z, E
+
+    def set_potential(self, v: np.ndarray):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        _check(load().mb_problem_set_potential(self.h, c_void_p(v.ctypes.data)))
+
+    # --- operators -----------------------------------------------------------
+    def _vec_args(self, ik, c, y, prec):
+        nbands, nb, ld = c.shape
+        return nbands, ld
+
+    def hpsi(self, ik, c, y, prec="fp64", stream=None):
+        nbands, ld = self._vec_args(ik, c, y, prec)
+        _check(load().hpsi_apply(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
+
+    def spsi(self, ik, c, y, prec="fp64", stream=None):
+        nbands, ld = self._vec_args(ik, c, y, prec)
+        _check(load().spsi_apply(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
+
+    def s_solve(self, ik, r, x, prec="fp64", stream=None):
+        nbands, ld = self._vec_args(ik, r, x, prec)
+        _check(load().s_solve(self.h, ik, _ptr(r), _ptr(x), nbands, ld, _prec(prec), _stream(stream)))
+
+    @staticmethod
+    def default_opts() -> LanczosOpts:
+        o = LanczosOpts()
+        load().mb_lanczos_default_opts(ctypes.byref(o))
+        return o
+
+    def lanczos_lowest(self, ik, nev, prec="fp64", opts=None, x0=None, x=None, stream=None,
+                       raise_not_converged=True):
+        """Returns (eig numpy array, x torch tensor [nev][nb][ld] complex128, info dict, status)."""
+        import torch
+        dm = self.dims(ik)
+        if x is None:
+            x = torch.zeros((nev, dm["nb"], dm["ld"]), dtype=torch.complex128, device=f"cuda:{self.device}")
+        eig = np.zeros(nev)
+        info = LanczosInfo()
+        o = opts if opts is not None else self.default_opts()
+        st = load().lanczos_lowest(self.h, ik, nev, _prec(prec), ctypes.byref(o), _ptr(x0),
+                                   c_void_p(eig.ctypes.data), _ptr(x), ctypes.byref(info), _stream(stream))
+        if st != 0 and not (st == -3 and not raise_not_converged):
+            _check(st)
+        inf = {f: getattr(info, f) for f, _ in LanczosInfo._fields_}
+        return eig, x, inf, st

@@ -1,0 +1,152 @@
+"""GPU parity of the operator entry points (hpsi_apply, spsi_apply, s_solve)
+against the CPU oracle, element by element.
+
+Tolerances: FP64 results agree with the oracle to rounding; relative to the
+largest output entry the kernels' different summation order (FFT instead of a
+direct sum over G', banded partial sums) costs a few hundred ulps, so 1e-11 is
+used.  FP32 paths carry single-precision rounding of the same sums (about
+1e-7 relative per operation, a few hundred operations per output): 2e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lattice, operators, rows
+from paper_1406_4960_amd import mbks, workloads
+from tests.helpers import gperm, lib_to_oracle, oracle_to_lib, random_lib_block, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _setup(desc, ik=0):
+    p = mbks.Problem(desc, device=0)
+    dm = p.dims(ik)
+    m, _ = p.gvectors(ik)
+    mo, _ = lattice.gset(desc, ik)
+    return p, dm, gperm(m, mo)
+
+
+def _run(p, fn, ik, x, prec):
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    xt = torch.from_numpy(x).to(DEV).to(ct)
+    yt = torch.full_like(xt, complex(7.0, 7.0))
+    getattr(p, fn)(ik, xt, yt, prec)
+    torch.cuda.synchronize()
+    return yt.to(torch.complex128).cpu().numpy()
+
+
+CASES = {
+    "tiny": workloads.tiny,
+    "micro-nl": lambda: workloads.micro(seed=3, natoms=2, mmax=2, nint=11, grid=8),
+    "micro-odd-grid": lambda: workloads.micro(seed=5, natoms=1, mmax=2, nint=9, grid=15),
+    "micro-25": lambda: workloads.micro(seed=6, natoms=2, mmax=3, nint=6, grid=25),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hpsi_spsi_vs_dense(name, prec):
+    d = CASES[name]()
+    print(f"[case] hpsi {name} {prec}", flush=True)
+    p, dm, perm = _setup(d)
+    prob = operators.Problem(d, 0)
+    H, S = prob.hamiltonian(), prob.overlap()
+    x = random_lib_block(11, 5, dm["nb"], dm["ng"], dm["ld"])
+    xo = lib_to_oracle(x, dm["ng"], perm)
+    y = _run(p, "hpsi", 0, x, prec)
+    sy = _run(p, "spsi", 0, x, prec)
+    ref_h = oracle_to_lib((H @ xo.T).T, dm["nb"], dm["ng"], dm["ld"], perm)
+    ref_s = oracle_to_lib((S @ xo.T).T, dm["nb"], dm["ng"], dm["ld"], perm)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    assert rel_err(y, ref_h) < tol
+    assert rel_err(sy, ref_s) < tol
+    # padding columns are written as zeros
+    assert np.all(y[:, :, dm["ng"]:] == 0) and np.all(sy[:, :, dm["ng"]:] == 0)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_s_solve_roundtrip(prec):
+    d = workloads.graphene()
+    print(f"[case] s_solve graphene {prec}", flush=True)
+    p, dm, perm = _setup(d, 1)
+    x = random_lib_block(12, 3, dm["nb"], dm["ng"], dm["ld"])
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    xt = torch.from_numpy(x).to(DEV).to(ct)
+    r = torch.empty_like(xt)
+    p.spsi(1, xt, r, prec)
+    z = torch.empty_like(xt)
+    p.s_solve(1, r, z, prec)
+    p.s_solve(1, r, r, prec)  # in place
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    assert rel_err(z.to(torch.complex128).cpu().numpy(), x) < tol
+    assert torch.equal(z, r)
+    p.close()
+
+
+def _sampled_rows(d, ik, nb, ng, seed, count=10):
+    rng = np.random.default_rng(seed)
+    ii = list(rng.integers(0, nb, count)) + [0, nb - 1, nb // 2]
+    gg = list(rng.integers(0, ng, count)) + [0, ng - 1, 1]
+    return [(int(i), int(g)) for i, g in zip(ii, gg)]
+
+
+@pytest.mark.parametrize("cfg,ik,prec", [("graphene", 0, "fp64"), ("graphene", 3, "fp64"),
+                                         ("graphene", 2, "fp32"), ("graphene_2x2", 1, "fp64"),
+                                         ("graphene_2x2", 0, "fp32")])
+def test_hpsi_full_size_sampled_rows(cfg, ik, prec):
+    d = workloads.CONFIGS[cfg]()
+    print(f"[case] hpsi sampled {cfg} k{ik} {prec}", flush=True)
+    p, dm, perm = _setup(d, ik)
+    nbands = 8
+    x = random_lib_block(13, nbands, dm["nb"], dm["ng"], dm["ld"])
+    y = _run(p, "hpsi", ik, x, prec)
+    sy = _run(p, "spsi", ik, x, prec)
+    ro = rows.RowOracle(d, ik)
+    xo = np.zeros((nbands, dm["nb"], dm["ng"]), dtype=np.complex128)
+    xo[:, :, perm] = x[:, :, :dm["ng"]]
+    picks = _sampled_rows(d, ik, dm["nb"], dm["ng"], 5)
+    inv = np.argsort(perm)
+    Hr, Sr = ro.apply_rows(xo, [(i, perm[g]) for i, g in picks])
+    got_h = np.array([y[:, i, g] for i, g in picks]).T
+    got_s = np.array([sy[:, i, g] for i, g in picks]).T
+    del inv
+    scale_h = np.max(np.abs(y))
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    assert np.max(np.abs(got_h - Hr)) < tol * scale_h
+    assert np.max(np.abs(got_s - Sr)) < tol * np.max(np.abs(sy))
+    p.close()
+
+
+def test_hermiticity_on_gpu():
+    # <x, H y> = conj <y, H x> for the matrix-free operator (no dense matrix)
+    d = workloads.graphene()
+    p, dm, _ = _setup(d, 2)
+    x = torch.from_numpy(random_lib_block(21, 4, dm["nb"], dm["ng"], dm["ld"])).to(DEV)
+    yv = torch.from_numpy(random_lib_block(22, 4, dm["nb"], dm["ng"], dm["ld"])).to(DEV)
+    hx = torch.empty_like(x)
+    hy = torch.empty_like(x)
+    p.hpsi(2, x, hx)
+    p.hpsi(2, yv, hy)
+    a = torch.sum(x.conj() * hy, dim=(1, 2))
+    b = torch.sum(yv.conj() * hx, dim=(1, 2)).conj()
+    scale = torch.sum(torch.abs(x) * torch.abs(hy), dim=(1, 2))
+    assert float(torch.max(torch.abs(a - b) / scale)) < 1e-13
+    p.close()
+
+
+def test_zero_bands_and_bad_args():
+    d = workloads.tiny()
+    p, dm, _ = _setup(d)
+    x = torch.zeros((0, dm["nb"], dm["ld"]), dtype=torch.complex128, device=DEV)
+    p.hpsi(0, x, x.clone())
+    xb = torch.zeros((2, dm["nb"], dm["ld"]), dtype=torch.complex128, device=DEV)
+    with pytest.raises(mbks.MbError):
+        p.hpsi(0, xb, xb)  # in and out overlap
+    with pytest.raises(mbks.MbError):
+        bad = torch.zeros((2, dm["nb"], dm["ng"] - 1), dtype=torch.complex128, device=DEV)
+        p.hpsi(0, bad, bad.clone())  # ld < N_G
+    p.close()

@@ -1,0 +1,91 @@
+"""CPU checks of the library's host logic: it loads, exports every declared
+symbol, and its set-up tables (built in C++) agree with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bspline, lattice, operators
+from paper_1406_4960_amd import mbks, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "mbks.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:mb_status|void|const char\*)\s+(\w+)\s*\(", body, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mbks.load()
+    names = _header_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(mbks.EXPORTS) == names
+
+
+@pytest.mark.parametrize("maker", [workloads.tiny, workloads.graphene, workloads.graphene_2x2,
+                                   workloads.surface, lambda: workloads.micro(seed=3)])
+def test_setup_tables_match_oracle(maker):
+    d = maker()
+    p = mbks.Problem(d, device=None)
+    zb = bspline.ZBasis(d["breakpoints"], d["order"], d["nq"])
+    for ik in range(min(2, len(d["kpts"]))):
+        dm = p.dims(ik)
+        m, kg2 = p.gvectors(ik)
+        mo, kgo = lattice.gset(d, ik)
+        assert dm["ng"] == len(mo) and dm["nb"] == zb.nb and dm["ld"] >= dm["ng"]
+        assert {tuple(x) for x in m} == {tuple(x) for x in mo}
+        perm = {(int(a), int(b)): n for n, (a, b) in enumerate(mo)}
+        idx = np.array([perm[(int(a), int(b))] for a, b in m])
+        assert np.max(np.abs(kg2 - np.sum(kgo[idx] ** 2, axis=1))) < 1e-11
+        F, Z, E = p.projectors(ik)
+        Fo, Zo, Eo = operators.projector_factors(d, ik, zb)
+        assert F.shape == Fo[:, idx].shape
+        if F.size:
+            assert np.max(np.abs(F - Fo[:, idx])) < 1e-13 * np.max(np.abs(Fo))
+            assert np.max(np.abs(Z - Zo)) < 1e-13 * np.max(np.abs(Zo))
+            assert np.array_equal(E, Eo)
+    zq, wq = p.zrule()
+    assert np.max(np.abs(zq - zb.zq)) < 1e-13 and np.max(np.abs(wq - zb.wq)) < 1e-15
+    s, dd = p.zbands()
+    S, D = zb.overlap(), zb.deriv_overlap()
+    for i in range(zb.nb):
+        for k in range(4):
+            ref_s = S[i, i + k] if i + k < zb.nb else 0.0
+            ref_d = D[i, i + k] if i + k < zb.nb else 0.0
+            assert abs(s[i, k] - ref_s) < 1e-14 * np.max(S)
+            assert abs(dd[i, k] - ref_d) < 1e-13 * np.max(D)
+    p.close()
+
+
+def test_invalid_descriptions_rejected():
+    d = workloads.tiny()
+    bad = dict(d, breakpoints=[0.0, 1.0, 1.0, 2.0])
+    with pytest.raises(mbks.MbError) as e:
+        mbks.Problem(bad, device=None)
+    assert e.value.status == -1
+    with pytest.raises(mbks.MbError) as e:
+        mbks.Problem(dict(d, grid=[6, 16]), device=None)  # 2*3+1 = 7 > 6: G would alias
+    assert e.value.status == -1
+    with pytest.raises(mbks.MbError) as e:
+        mbks.Problem(dict(d, grid=[16, 14 * 7]), device=None)  # factor 7
+    assert e.value.status == -1
+    with pytest.raises(mbks.MbError):
+        mbks.Problem(dict(d, nq=0), device=None)
+
+
+def test_gpu_calls_on_host_only_handle_fail():
+    p = mbks.Problem(workloads.tiny(), device=None)
+    lib = mbks.load()
+    st = lib.hpsi_apply(p.h, 0, ctypes.c_void_p(16), ctypes.c_void_p(4096), 1, p.dims(0)["ld"], 0, None)
+    assert st == -7
+    st = lib.s_solve(p.h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 1, p.dims(0)["ld"], 0, None)
+    assert st == -7
+    assert b"host-only" in lib.mb_last_error()
+    p.close()
