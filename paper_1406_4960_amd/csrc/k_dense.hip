@@ -1,0 +1,583 @@
+// FP64 dense kernels of the eigensolver (Sec. II.C): Gram matrices in the S
+// inner product, linear combinations of vectors, batched dot products, and the
+// projected generalized eigenproblems solved by Cholesky reduction and the
+// cyclic Jacobi method.  Vectors are addressed through device tables of
+// pointers so one launch serves every block of the block cycle.
+#include <cmath>
+
+#include "cplx.h"
+#include "dense.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+using zc = cx<double>;
+
+// ---------------------------------------------------------------------------
+// Gram: C_z[m][n] = sum_k conj(A_{z,m}[k]) B_{z,n}[k], split over k chunks.
+// part[z][chunk][m][n]; reduced in fixed order by k_gram_reduce.
+// ---------------------------------------------------------------------------
+constexpr int GT = 16;   // output tile
+constexpr int GK = 32;   // k per LDS stage
+
+__global__ __launch_bounds__(256) void k_gram(const zc* const* ta, const zc* const* tb, int MA, int NB, int64_t K,
+                                              int64_t kchunk, int nchunk, int tiles_n, zc* part) {
+    __shared__ zc As[GT][GK + 1];
+    __shared__ zc Bs[GT][GK + 1];
+    const int z = blockIdx.z;
+    const int chunk = blockIdx.x;
+    const int tm = blockIdx.y / tiles_n, tn = blockIdx.y % tiles_n;
+    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;  // ty -> m, tx -> n
+    const int m0 = tm * GT, n0 = tn * GT;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    zc acc = mk<double>(0, 0);
+    for (int64_t kb = k0; kb < k1; kb += GK) {
+        // 256 threads load 16 x 32 of A and of B
+        for (int e = threadIdx.x; e < GT * GK; e += 256) {
+            int r = e / GK, kk = e % GK;
+            int64_t k = kb + kk;
+            zc va = mk<double>(0, 0), vb = mk<double>(0, 0);
+            if (k < k1) {
+                if (m0 + r < MA) va = ta[(size_t)z * MA + m0 + r][k];
+                if (n0 + r < NB) vb = tb[(size_t)z * NB + n0 + r][k];
+            }
+            As[r][kk] = va;
+            Bs[r][kk] = vb;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < GK; ++kk) cfmac(acc, As[ty][kk], Bs[tx][kk]);
+        __syncthreads();
+    }
+    const int m = m0 + ty, n = n0 + tx;
+    if (m < MA && n < NB) part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = acc;
+}
+
+__global__ void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t per = (size_t)MA * NB;
+    if (idx >= per * nz) return;
+    size_t z = idx / per, e = idx % per;
+    zc s = mk<double>(0, 0);
+    for (int c = 0; c < nchunk; ++c) s = cadd(s, part[(z * nchunk + c) * per + e]);
+    out[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Combination: Y_{z,n}[k] = alpha * sum_m W_z[m][n] X_{z,m}[k] + beta * Y_{z,n}[k]
+// ---------------------------------------------------------------------------
+constexpr int CN = 8;  // outputs per thread
+
+__global__ __launch_bounds__(256) void k_combo(const zc* const* tx, zc* const* ty, const zc* W, int MI, int NO,
+                                               int64_t K, double alpha, double beta) {
+    extern __shared__ unsigned char sm[];
+    zc* Ws = reinterpret_cast<zc*>(sm);  // MI x CN
+    const int z = blockIdx.z;
+    const int n0 = blockIdx.y * CN;
+    const int nn = min(CN, NO - n0);
+    const zc* Wz = W + (size_t)z * MI * NO;
+    for (int e = threadIdx.x; e < MI * CN; e += blockDim.x) {
+        int m = e / CN, j = e % CN;
+        Ws[e] = (j < nn) ? Wz[(size_t)m * NO + n0 + j] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    zc acc[CN];
+#pragma unroll
+    for (int j = 0; j < CN; ++j) acc[j] = mk<double>(0, 0);
+    for (int m = 0; m < MI; ++m) {
+        zc x = tx[(size_t)z * MI + m][k];
+#pragma unroll
+        for (int j = 0; j < CN; ++j) cfma(acc[j], Ws[m * CN + j], x);
+    }
+    for (int j = 0; j < nn; ++j) {
+        zc* yp = ty[(size_t)z * NO + n0 + j] + k;
+        zc o = cscale(acc[j], alpha);
+        if (beta != 0.0) o = cadd(o, cscale(*yp, beta));
+        *yp = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched dots d_v = sum_k conj(A_v[k]) B_v[k]; one block per vector
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dots(const zc* const* ta, const zc* const* tb, int64_t K, zc* out) {
+    const int v = blockIdx.x;
+    const zc* a = ta[v];
+    const zc* b = tb[v];
+    zc acc = mk<double>(0, 0);
+    for (int64_t k = threadIdx.x; k < K; k += 256) cfmac(acc, a[k], b[k]);
+    __shared__ zc red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+}
+
+// residual norms r_v = || h_v - theta_v s_v ||_2 and finiteness
+__global__ __launch_bounds__(256) void k_resid(const zc* const* th, const zc* const* ts, const double* theta,
+                                               int64_t K, double* out) {
+    const int v = blockIdx.x;
+    const zc* h = th[v];
+    const zc* s = ts[v];
+    const double t = theta[v];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < K; k += 256) {
+        zc a = h[k], b = s[k];
+        double re = a.x - t * b.x, im = a.y - t * b.y;
+        acc += re * re + im * im;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = sqrt(red[0]);
+}
+
+// Y_v[k] += sign * coef_v * X_v[k]
+__global__ void k_axpy_tab(zc* const* ty, const zc* const* tx, const zc* coef, double sign, int64_t K) {
+    const int v = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    zc c = cscale(coef[v], sign);
+    zc* y = ty[v];
+    cfma(y[k], c, tx[v][k]);
+}
+
+// X_v *= 1 / sqrt(re(d_v)) for every table entry (two tables scaled alike)
+__global__ void k_normalize_tab(zc* const* t1, zc* const* t2, const zc* d, int64_t K) {
+    const int v = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    // a vanished vector (converged seed) is zeroed; the projected problem deflates it
+    double s = (d[v].x > 1e-280 && isfinite(d[v].x)) ? 1.0 / sqrt(d[v].x) : 0.0;
+    t1[v][k] = cscale(t1[v][k], s);
+    if (t2) t2[v][k] = cscale(t2[v][k], s);
+}
+
+// counter-based uniform numbers (splitmix64 of seed + index) in [-1, 1)
+__device__ inline double u11(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void k_random(zc* x, int nvec, int nb, int ld, int ng, uint64_t seed) {
+    const int64_t K = (int64_t)nb * ld;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * nvec) return;
+    int g = (int)(idx % ld);
+    if (g >= ng) {
+        x[idx] = mk<double>(0, 0);
+        return;
+    }
+    uint64_t c = seed * 0x100000001B3ull + 2ull * (uint64_t)idx;
+    x[idx] = mk<double>(u11(c), u11(c + 1));
+}
+
+// ---------------------------------------------------------------------------
+// Batched generalized Hermitian eigenproblem H y = theta S y, N x N row-major.
+// S = L L^H (right-looking Cholesky), A = L^{-1} H L^{-H}, cyclic Jacobi on A
+// with the round-robin parallel ordering (N/2 disjoint rotations per step),
+// Y = L^{-H} V, ascending order.  One workgroup per problem.
+// ---------------------------------------------------------------------------
+__device__ inline int rr_pair(int r, int k, int Np) {
+    // circle method: players 0..Np-2 on the circle, Np-1 fixed
+    return (r + k) % (Np - 1);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
+                                               zc* gwork, int use_lds, int max_sweeps, int* status) {
+    extern __shared__ unsigned char sm[];
+    const int z = blockIdx.x;
+    const size_t NN = (size_t)N * N;
+    const zc* H = Hs + z * NN;
+    const zc* S = Ss + z * NN;
+    zc* Lg = gwork + z * 3 * NN;  // global copy of L
+    zc* P1 = use_lds ? reinterpret_cast<zc*>(sm) : Lg + NN;
+    zc* P2 = use_lds ? P1 + NN : Lg + 2 * NN;
+    const int tid = threadIdx.x;
+    __shared__ int bad;
+    __shared__ double s_off, s_norm;
+    __shared__ unsigned char dead[256];  // directions numerically in the span of earlier ones
+    if (tid == 0) bad = 0;
+    // 1. Cholesky of S in P1; a pivot that lost all but 1e-13 of its diagonal marks a
+    //    dependent direction: it is taken out of the reduction (unit pivot, zero column)
+    //    and later pinned at the top of the spectrum so it is never selected
+    for (size_t e = tid; e < NN; e += NT) P1[e] = S[e];
+    __syncthreads();
+    for (int j = 0; j < N; ++j) {
+        if (tid == 0) {
+            double d = P1[(size_t)j * N + j].x;
+            double d0 = S[(size_t)j * N + j].x;
+            dead[j] = 0;
+            if (!isfinite(d) || !isfinite(d0)) {
+                bad = 2;
+                d = 1.0;
+            } else if (!(d > 1e-13 * d0) || !(d0 > 0.0)) {
+                dead[j] = 1;
+                d = 1.0;
+            }
+            P1[(size_t)j * N + j] = mk<double>(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        double inv = 1.0 / P1[(size_t)j * N + j].x;
+        for (int i = j + 1 + tid; i < N; i += NT)
+            P1[(size_t)i * N + j] = dead[j] ? mk<double>(0, 0) : cscale(P1[(size_t)i * N + j], inv);
+        __syncthreads();
+        // trailing update of the lower triangle: A_ik -= L_ij conj(L_kj), i >= k > j
+        int w = N - j - 1;
+        for (int e = tid; e < w * w; e += NT) {
+            int i = j + 1 + e / w, k = j + 1 + e % w;
+            if (k > i) continue;
+            zc lij = P1[(size_t)i * N + j], lkj = P1[(size_t)k * N + j];
+            zc t = mk<double>(lij.x * lkj.x + lij.y * lkj.y, lij.y * lkj.x - lij.x * lkj.y);  // lij conj(lkj)
+            P1[(size_t)i * N + k] = csub(P1[(size_t)i * N + k], t);
+        }
+        __syncthreads();
+    }
+    for (size_t e = tid; e < NN; e += NT) {
+        int i = (int)(e / N), k = (int)(e % N);
+        Lg[e] = (k <= i) ? P1[e] : mk<double>(0, 0);
+    }
+    // 2. B = L^{-1} H in P2 (column-wise forward substitution)
+    for (size_t e = tid; e < NN; e += NT) P2[e] = H[e];
+    __syncthreads();
+    for (int col = tid; col < N; col += NT) {
+        for (int i = 0; i < N; ++i) {
+            zc v = P2[(size_t)i * N + col];
+            for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P2[(size_t)k * N + col]));
+            P2[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+        }
+    }
+    __syncthreads();
+    // 3. A = L^{-1} B^H into P1: column j solves L a = conj(row j of B)
+    for (int col = tid; col < N; col += NT) {
+        for (int i = 0; i < N; ++i) {
+            zc b = P2[(size_t)col * N + i];
+            zc v = mk<double>(b.x, -b.y);
+            for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P1[(size_t)k * N + col]));
+            P1[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+        }
+    }
+    __syncthreads();
+    // 4. Hermitian part of A; V = I
+    for (size_t e = tid; e < NN; e += NT) {
+        int i = (int)(e / N), k = (int)(e % N);
+        if (k < i) {
+            zc a = P1[(size_t)i * N + k], b = P1[(size_t)k * N + i];
+            zc h = mk<double>(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            P1[(size_t)i * N + k] = h;
+            P1[(size_t)k * N + i] = mk<double>(h.x, -h.y);
+        } else if (k == i) {
+            P1[e] = mk<double>(P1[e].x, 0.0);
+        }
+        P2[e] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (size_t e = tid; e < NN; e += NT) {
+        int i = (int)(e / N), k = (int)(e % N);
+        if (dead[i] || dead[k]) P1[e] = mk<double>(i == k ? 1e30 : 0.0, 0.0);
+    }
+    __syncthreads();
+    // 5. cyclic Jacobi
+    const int Np = N + (N & 1);
+    const int npair = Np / 2;
+    __shared__ double rc[128], rsr[128], rsi[128];  // c, s e^{i phi} per pair (npair <= 128 in LDS mode)
+    __shared__ int rp[128], rq[128];
+    double* gc = nullptr;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        // off-diagonal norm
+        if (tid == 0) { s_off = 0.0; s_norm = 0.0; }
+        __syncthreads();
+        double off = 0.0, nrm = 0.0;
+        for (size_t e = tid; e < NN; e += NT) {
+            int i = (int)(e / N), k = (int)(e % N);
+            zc a = P1[e];
+            double m2 = a.x * a.x + a.y * a.y;
+            nrm += m2;
+            if (i != k) off += m2;
+        }
+        atomicAdd(&s_off, off);
+        atomicAdd(&s_norm, nrm);
+        __syncthreads();
+        if (s_off <= 1e-30 * s_norm || s_off == 0.0) break;
+        for (int r = 0; r < Np - 1; ++r) {
+            for (int pi = tid; pi < npair; pi += NT) {
+                int p, q;
+                if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
+                else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
+                if (p > q) { int t = p; p = q; q = t; }
+                double c = 1.0, sr = 0.0, si = 0.0;
+                if (q < N) {
+                    zc apq = P1[(size_t)p * N + q];
+                    double rabs = sqrt(apq.x * apq.x + apq.y * apq.y);
+                    if (rabs > 1e-300) {
+                        double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
+                        double tau = (aqq - app) / (2.0 * rabs);
+                        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        double s = t * c;
+                        sr = s * apq.x / rabs;  // s e^{i phi}
+                        si = s * apq.y / rabs;
+                    }
+                }
+                rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
+            }
+            __syncthreads();
+            // rows: a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
+            for (int e = tid; e < npair * N; e += NT) {
+                int pi = e / N, j = e % N;
+                int p = rp[pi], q = rq[pi];
+                if (q >= N) continue;
+                double c = rc[pi];
+                zc se = mk<double>(rsr[pi], rsi[pi]);
+                zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
+                P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
+                P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
+            }
+            __syncthreads();
+            // columns of A and V: a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
+            for (int e = tid; e < npair * N; e += NT) {
+                int pi = e / N, i = e % N;
+                int p = rp[pi], q = rq[pi];
+                if (q >= N) continue;
+                double c = rc[pi];
+                zc se = mk<double>(rsr[pi], rsi[pi]);
+                zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
+                P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
+                P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
+                zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
+                P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
+                P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+            }
+            __syncthreads();
+        }
+    }
+    (void)gc;
+    // 6. order and back-transform: column rank(j) of Y = L^{-H} V[:, j]
+    double* ev = evals + (size_t)z * N;
+    zc* Y = Ys + z * NN;
+    for (int j = tid; j < N; j += NT) {
+        double dj = P1[(size_t)j * N + j].x;
+        int rank = 0;
+        for (int i = 0; i < N; ++i) {
+            double di = P1[(size_t)i * N + i].x;
+            if (di < dj || (di == dj && i < j)) ++rank;
+        }
+        ev[rank] = dj;
+        if (!isfinite(dj)) bad = 2;
+        // L^H y = v, back substitution
+        for (int i = N - 1; i >= 0; --i) {
+            zc v = P2[(size_t)i * N + j];
+            for (int k = i + 1; k < N; ++k) {
+                zc l = Lg[(size_t)k * N + i];
+                zc yk = Y[(size_t)k * N + rank];
+                v = csub(v, mk<double>(l.x * yk.x + l.y * yk.y, l.x * yk.y - l.y * yk.x));  // conj(l) yk
+            }
+            Y[(size_t)i * N + rank] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && bad) atomicMax(status, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Block selection: per block z with nr = b + m Ritz pairs (ascending) and the
+// b inputs as its first basis vectors, pick for each input slot the Ritz vector
+// of largest |<y_r|S|x_a>|^2 = |Y[a][r]|^2 (greedy, largest overlaps first);
+// then any unpicked Ritz value among the b lowest replaces the highest picked
+// one (new roots).  Writes coefficient columns C_z (nr x b) and theta.
+// ---------------------------------------------------------------------------
+__global__ void k_select(const zc* Ys, const double* ev, int nr, int b, zc* C, double* theta_out, int nblocks) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nblocks) return;
+    const zc* Y = Ys + (size_t)z * nr * nr;
+    const double* e = ev + (size_t)z * nr;
+    int pick[32];
+    bool used[64];
+    bool done[32];
+    for (int r = 0; r < nr; ++r) used[r] = false;
+    for (int a = 0; a < b; ++a) { pick[a] = -1; done[a] = false; }
+    for (int it = 0; it < b; ++it) {
+        double best = -1.0;
+        int ba = 0, br = 0;
+        for (int a = 0; a < b; ++a) {
+            if (done[a]) continue;
+            for (int r = 0; r < nr; ++r) {
+                if (used[r]) continue;
+                zc y = Y[(size_t)a * nr + r];
+                double o = y.x * y.x + y.y * y.y;
+                if (o > best) { best = o; ba = a; br = r; }
+            }
+        }
+        pick[ba] = br;
+        done[ba] = true;
+        used[br] = true;
+    }
+    for (int r = 0; r < b; ++r) {
+        if (used[r]) continue;
+        int worst = 0;
+        for (int a = 1; a < b; ++a)
+            if (pick[a] > pick[worst]) worst = a;
+        if (pick[worst] > r) {
+            used[pick[worst]] = false;
+            pick[worst] = r;
+            used[r] = true;
+        }
+    }
+    for (int a = 0; a < b; ++a) {
+        int r = pick[a];
+        theta_out[(size_t)z * b + a] = e[r];
+        for (int i = 0; i < nr; ++i) C[((size_t)z * nr + i) * b + a] = Y[(size_t)i * nr + r];
+    }
+}
+
+__global__ void k_copy_cols(const zc* Y, int ldy, int ncols, int nrows, zc* out) {
+    // out (nrows x ncols, row-major) = first ncols columns of Y (nrows x ldy)
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrows * ncols) return;
+    int i = e / ncols, j = e % ncols;
+    out[e] = Y[(size_t)i * ldy + j];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
+                     void* scratch, size_t scratch_bytes, hipStream_t s) {
+    if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
+    int tiles_m = (MA + GT - 1) / GT, tiles_n = (NB + GT - 1) / GT;
+    int ntiles = tiles_m * tiles_n * nz;
+    int64_t maxchunk = (K + 511) / 512;
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 2048 / std::max(1, ntiles)));
+    size_t need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
+    while (need > scratch_bytes && nchunk > 1) {
+        nchunk /= 2;
+        need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
+    }
+    if (need > scratch_bytes) return set_error(MB_ERR_INVALID_ARG, "gram scratch too small");
+    int64_t kchunk = (K + nchunk - 1) / nchunk;
+    kchunk = (kchunk + GK - 1) / GK * GK;
+    nchunk = (int)((K + kchunk - 1) / kchunk);
+    dim3 grid(nchunk, tiles_m * tiles_n, nz);
+    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk,
+                       nchunk, tiles_n, (zc*)scratch);
+    MB_HIP_TRY(hipGetLastError());
+    size_t tot = (size_t)MA * NB * nz;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const zc*)scratch,
+                       (zc*)out, MA, NB, nchunk, nz);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
+                      double alpha, double beta, hipStream_t s) {
+    if (MI <= 0 || NO <= 0 || nz <= 0) return MB_OK;
+    size_t lds = (size_t)MI * CN * sizeof(zc);
+    if (lds > 65536) return set_error(MB_ERR_INVALID_ARG, "combination with too many inputs");
+    dim3 grid((unsigned)((K + 255) / 256), (NO + CN - 1) / CN, nz);
+    hipLaunchKernelGGL(k_combo, grid, dim3(256), lds, s, (const zc* const*)tx, (zc* const*)ty, (const zc*)W, MI, NO,
+                       K, alpha, beta);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, hipStream_t s) {
+    if (nvec <= 0) return MB_OK;
+    hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, K, (zc*)out);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_resid(const void* const* th, const void* const* ts, const double* theta, int nvec, int64_t K,
+                      double* out, hipStream_t s) {
+    if (nvec <= 0) return MB_OK;
+    hipLaunchKernelGGL(k_resid, dim3(nvec), dim3(256), 0, s, (const zc* const*)th, (const zc* const*)ts, theta, K,
+                       out);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_axpy(void* const* ty, const void* const* tx, const void* coef, double sign, int nvec, int64_t K,
+                     hipStream_t s) {
+    if (nvec <= 0) return MB_OK;
+    dim3 grid((unsigned)((K + 255) / 256), nvec);
+    hipLaunchKernelGGL(k_axpy_tab, grid, dim3(256), 0, s, (zc* const*)ty, (const zc* const*)tx, (const zc*)coef, sign,
+                       K);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_normalize(void* const* t1, void* const* t2, const void* d, int nvec, int64_t K, hipStream_t s) {
+    if (nvec <= 0) return MB_OK;
+    dim3 grid((unsigned)((K + 255) / 256), nvec);
+    hipLaunchKernelGGL(k_normalize_tab, grid, dim3(256), 0, s, (zc* const*)t1, (zc* const*)t2, (const zc*)d, K);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed, hipStream_t s) {
+    int64_t tot = (int64_t)nvec * nb * ld;
+    hipLaunchKernelGGL(k_random, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (zc*)x, nvec, nb, ld, ng, seed);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
+                       int* status, hipStream_t s) {
+    if (N <= 0 || nz <= 0) return MB_OK;
+    size_t lds = 2 * (size_t)N * N * sizeof(zc);
+    int use_lds = lds <= 131072 ? 1 : 0;
+    if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
+    const size_t dyn = use_lds ? lds : 0;
+    if (N <= 48) {
+        if (dyn > 65536)
+            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_geneig<64>, dim3(nz), dim3(64), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
+                           (zc*)gwork, use_lds, 60, status);
+    } else {
+        if (dyn > 65536)
+            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_geneig<256>, dim3(nz), dim3(256), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
+                           (zc*)gwork, use_lds, 60, status);
+    }
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
+                       hipStream_t s) {
+    if (b > 32 || nr > 64) return set_error(MB_ERR_INVALID_ARG, "block too large for selection");
+    hipLaunchKernelGGL(k_select, dim3((nblocks + 63) / 64), dim3(64), 0, s, (const zc*)Y, ev, nr, b, (zc*)C, theta,
+                       nblocks);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* out, hipStream_t s) {
+    int tot = nrows * ncols;
+    hipLaunchKernelGGL(k_copy_cols, dim3((tot + 255) / 256), dim3(256), 0, s, (const zc*)Y, ldy, ncols, nrows,
+                       (zc*)out);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+}  // namespace mb

@@ -248,13 +248,9 @@ int max_stage_work(const FftPlan& pl, int nlines) {
 
 template <typename TI, typename T, int NT, int MAXG>
 mb_status run_local(const LocalArgs<TI, T>& a, size_t lds, hipStream_t s) {
-    static bool attr_set = false;
     auto kern = k_local<TI, T, NT, MAXG>;
-    if (!attr_set) {
-        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds > 65536 ? 163840 : 65536));
-        attr_set = true;
-    }
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned nblocks = (unsigned)a.nbands * (unsigned)a.nint;
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
     MB_HIP_TRY(hipGetLastError());

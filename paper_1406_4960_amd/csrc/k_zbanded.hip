@@ -181,15 +181,15 @@ __global__ __launch_bounds__(256) void k_ssolve(const cx<TI>* r, cx<TI>* x, cons
     band_solve<TI>(r + vb, x + vb, lband, nb, ld, g, 0, 0.0, nullptr);
 }
 
-// banded Cholesky of 1/2 D_z + (1/2 |k+G|^2 + sigma) S_z for every G
+// banded Cholesky of kin (1/2 D_z + 1/2 |k+G|^2 S_z) + shift S_z for every G
 __global__ void k_prec_factor(double* pf, const double* sband, const double* dband, const double* kg2,
-                              double sigma, int ng, int nb, int ld, int* fail) {
+                              double kin, double shift, int ng, int nb, int ld, int* fail) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
-    const double sh = 0.5 * kg2[g] + sigma;
+    const double sh = kin * 0.5 * kg2[g] + shift;
     auto M = [&](int i, int j) -> double {
         if (i > j) { int t = i; i = j; j = t; }
-        return 0.5 * dband[i * KORD + (j - i)] + sh * sband[i * KORD + (j - i)];
+        return kin * 0.5 * dband[i * KORD + (j - i)] + sh * sband[i * KORD + (j - i)];
     };
     auto L = [&](int i, int j) -> double& { return pf[((size_t)i * KORD + (i - j)) * ld + g]; };
     for (int i = 0; i < nb; ++i) {
@@ -289,8 +289,10 @@ mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s) {
     int* d_fail = nullptr;
     MB_HIP_TRY(hipMalloc(&d_fail, sizeof(int)));
     MB_HIP_TRY(hipMemsetAsync(d_fail, 0, sizeof(int), s));
+    // sigma > 0: (T + sigma S)^{-1}; sigma <= 0: S^{-1} (the plain generalized Krylov operator)
+    double kin = sigma > 0 ? 1.0 : 0.0, shift = sigma > 0 ? sigma : 1.0;
     hipLaunchKernelGGL(k_prec_factor, dim3((kp.ng + 127) / 128), dim3(128), 0, s, kp.d_pfac, p->d_sband,
-                       p->d_dband, kp.d_kg2, sigma, kp.ng, p->nb, kp.ld, d_fail);
+                       p->d_dband, kp.d_kg2, kin, shift, kp.ng, p->nb, kp.ld, d_fail);
     MB_HIP_TRY(hipGetLastError());
     int fail = 0;
     MB_HIP_TRY(hipMemcpyAsync(&fail, d_fail, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -1,19 +1,412 @@
-// Generalized Lanczos-Krylov eigensolver (Sec. II.C).
+// Generalized Lanczos-Krylov eigensolver (Sec. II.C) for H c = eps S c.
+//
+// The two grand cycles of the method alternate:
+//  (B) block cycle: the trial vectors are split into blocks of `block`
+//      consecutive roots; every block is diagonalised in the span of its own
+//      vectors and a Krylov subspace of depth `krylov` grown from the block
+//      member with the largest residual.  All blocks advance together, so each
+//      Krylov step is one H application to nblocks vectors.  Krylov vectors are
+//      S-orthogonalised (Gram-Schmidt, twice) against all trial vectors and the
+//      block's earlier Krylov vectors.  Roots are chosen by maximum overlap with
+//      the block's input vectors; lower unmatched roots of the block are picked
+//      up as new roots.
+//  (A) global cycle: Rayleigh-Ritz over the union of all trial vectors and a
+//      Krylov subspace of depth `krylov_global` grown from the trial vector with
+//      the largest residual; the nev lowest roots are kept.
+// Every projected matrix is diagonalised by the cyclic Jacobi method after a
+// Cholesky reduction of its overlap.  The Krylov sequence is generated with the
+// preconditioned shifted operator K (H - theta S), K = (T + sigma S)^{-1}
+// per G (or S^{-1} for sigma <= 0, which spans the same space as repeated
+// S^{-1} H).  Orthonormalisation, recurrence coefficients and projected
+// problems are FP64; reduced precision only enters H applications.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dense.h"
 #include "mbks_internal.h"
+
+namespace mb {
+
+Problem* problem_of(mb_problem* h);
+
+namespace {
+
+#define LZ_TRY(call)                \
+    do {                            \
+        mb_status s_ = (call);      \
+        if (s_ != MB_OK) return s_; \
+    } while (0)
+
+struct Solver {
+    Problem* p;
+    int ik;
+    hipStream_t s;
+    int M, b, nbl, m, mA, NG, NR;
+    int ld;
+    int64_t K;  // complex elements per vector
+    size_t vbytes;
+    // vectors
+    char* X;
+    char* HX;
+    char* SX;
+    char* Xn;
+    char* HXn;
+    char* SXn;
+    char* Kv;
+    char* HK;
+    char* SK;
+    // device tables
+    void** tX;
+    void** tHX;
+    void** tSX;
+    void** tXn;
+    void** tHXn;
+    void** tSXn;
+    void** tK;
+    void** tHK;
+    void** tSK;
+    void** tQ;
+    void** tHQ;
+    void** tSQ;
+    // small device arrays
+    void* Hp;
+    void* Sp;
+    void* Y;
+    void* W;
+    void* gwork;
+    double* evals;
+    void* coef;
+    void* dots;
+    double* theta;
+    double* theta_s;
+    int32_t* sel;
+    double* resid;
+    int* status;
+    void* gscratch;
+    size_t gscratch_bytes;
+    // host mirrors
+    std::vector<double> h_theta, h_resid;
+    int64_t applies = 0, applies_low = 0;
+
+    char* vec(char* base, int i) const { return base + (size_t)i * vbytes; }
+
+    mb_status hop(const void* c, void* y, void* sy, int n, int prec) {
+        LZ_TRY(apply_h(p, ik, c, y, sy, n, ld, prec, s));
+        applies += n;
+        if (prec != 0) applies_low += n;
+        return MB_OK;
+    }
+
+    mb_status check_status() {
+        int st = 0;
+        MB_HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+        MB_HIP_TRY(hipStreamSynchronize(s));
+        if (st != 0) return set_error(MB_ERR_NONFINITE, "non-finite value in a projected eigenproblem");
+        return MB_OK;
+    }
+
+    // global Rayleigh-Ritz over the first n vectors of X (n = M or NG): keep M lowest
+    mb_status global_rr(int n) {
+        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tHX, n, n, 1, K, Hp, gscratch, gscratch_bytes, s));
+        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tSX, n, n, 1, K, Sp, gscratch, gscratch_bytes, s));
+        LZ_TRY(dense_geneig(Hp, Sp, n, 1, evals, Y, gwork, status, s));
+        LZ_TRY(dense_copy_cols(Y, n, M, n, W, s));
+        LZ_TRY(dense_combo((const void* const*)tX, tXn, W, n, M, 1, K, 1.0, 0.0, s));
+        LZ_TRY(dense_combo((const void* const*)tHX, tHXn, W, n, M, 1, K, 1.0, 0.0, s));
+        LZ_TRY(dense_combo((const void* const*)tSX, tSXn, W, n, M, 1, K, 1.0, 0.0, s));
+        MB_HIP_TRY(hipMemcpyAsync(X, Xn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(HX, HXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(SX, SXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(theta, evals, (size_t)M * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return check_status();
+    }
+
+    mb_status residuals() {
+        LZ_TRY(dense_resid((const void* const*)tHX, (const void* const*)tSX, theta, M, K, resid, s));
+        MB_HIP_TRY(hipMemcpyAsync(h_resid.data(), resid, M * sizeof(double), hipMemcpyDeviceToHost, s));
+        MB_HIP_TRY(hipMemcpyAsync(h_theta.data(), theta, M * sizeof(double), hipMemcpyDeviceToHost, s));
+        MB_HIP_TRY(hipStreamSynchronize(s));
+        for (int j = 0; j < M; ++j)
+            if (!std::isfinite(h_resid[j]) || !std::isfinite(h_theta[j]))
+                return set_error(MB_ERR_NONFINITE, "non-finite residual or eigenvalue");
+        return MB_OK;
+    }
+
+    // S-orthonormalise Krylov slot j (nbl vectors) against X[0..M) and K[0..j)
+    mb_status orthonormalise_k(int j) {
+        void** tKj = tK + (size_t)j * nbl;
+        void** tSKj = tSK + (size_t)j * nbl;
+        char* Kj = vec(Kv, j * nbl);
+        char* SKj = vec(SK, j * nbl);
+        for (int pass = 0; pass < 2; ++pass) {
+            // against all trial vectors: C = (S X)^H K_j, K_j -= X C
+            LZ_TRY(dense_gram((const void* const*)tSX, (const void* const*)tKj, M, nbl, 1, K, coef, gscratch,
+                              gscratch_bytes, s));
+            LZ_TRY(dense_combo((const void* const*)tX, tKj, coef, M, nbl, 1, K, -1.0, 1.0, s));
+            // against the block's earlier Krylov vectors
+            for (int i = 0; i < j; ++i) {
+                LZ_TRY(dense_dots((const void* const*)(tSK + (size_t)i * nbl), (const void* const*)tKj, nbl, K, dots, s));
+                LZ_TRY(dense_axpy(tKj, (const void* const*)(tK + (size_t)i * nbl), dots, -1.0, nbl, K, s));
+            }
+        }
+        LZ_TRY(launch_spsi(p, ik, Kj, SKj, nbl, ld, 0, s));
+        LZ_TRY(dense_dots((const void* const*)tKj, (const void* const*)tSKj, nbl, K, dots, s));
+        LZ_TRY(dense_normalize(tKj, tSKj, dots, nbl, K, s));
+        return MB_OK;
+    }
+
+    mb_status block_cycle(int prec) {
+        // seeds: block member with the largest residual
+        std::vector<int32_t> seeds(nbl);
+        std::vector<double> th(nbl);
+        for (int z = 0; z < nbl; ++z) {
+            int best = z * b;
+            for (int a = 1; a < b; ++a)
+                if (h_resid[z * b + a] > h_resid[best]) best = z * b + a;
+            seeds[z] = best;
+            th[z] = h_theta[best];
+        }
+        MB_HIP_TRY(hipMemcpyAsync(sel, seeds.data(), nbl * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(theta_s, th.data(), nbl * sizeof(double), hipMemcpyHostToDevice, s));
+        MB_HIP_TRY(hipStreamSynchronize(s));
+        // K_1 = P (H x_s - theta_s S x_s)
+        LZ_TRY(launch_prec_apply(p, ik, HX, SX, theta_s, sel, vec(Kv, 0), nbl, ld, s));
+        for (int j = 0; j < m; ++j) {
+            LZ_TRY(orthonormalise_k(j));
+            LZ_TRY(hop(vec(Kv, j * nbl), vec(HK, j * nbl), nullptr, nbl, prec));
+            if (j + 1 < m)
+                LZ_TRY(launch_prec_apply(p, ik, vec(HK, j * nbl), vec(SK, j * nbl), theta_s, nullptr,
+                                         vec(Kv, (j + 1) * nbl), nbl, ld, s));
+        }
+        // per-block Rayleigh-Ritz
+        LZ_TRY(dense_gram((const void* const*)tQ, (const void* const*)tHQ, NR, NR, nbl, K, Hp, gscratch, gscratch_bytes, s));
+        LZ_TRY(dense_gram((const void* const*)tQ, (const void* const*)tSQ, NR, NR, nbl, K, Sp, gscratch, gscratch_bytes, s));
+        LZ_TRY(dense_geneig(Hp, Sp, NR, nbl, evals, Y, gwork, status, s));
+        LZ_TRY(dense_select(Y, evals, NR, b, W, theta, nbl, s));
+        LZ_TRY(dense_combo((const void* const*)tQ, tXn, W, NR, b, nbl, K, 1.0, 0.0, s));
+        LZ_TRY(dense_combo((const void* const*)tHQ, tHXn, W, NR, b, nbl, K, 1.0, 0.0, s));
+        LZ_TRY(dense_combo((const void* const*)tSQ, tSXn, W, NR, b, nbl, K, 1.0, 0.0, s));
+        MB_HIP_TRY(hipMemcpyAsync(X, Xn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(HX, HXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        MB_HIP_TRY(hipMemcpyAsync(SX, SXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
+        return check_status();
+    }
+
+    mb_status global_cycle(int prec) {
+        if (mA == 0) return global_rr(M);
+        int v = 0;
+        for (int j = 1; j < M; ++j)
+            if (h_resid[j] > h_resid[v]) v = j;
+        // Krylov vectors in X[M .. M+mA)
+        LZ_TRY(launch_prec_apply(p, ik, vec(HX, v), vec(SX, v), theta + v, nullptr, vec(X, M), 1, ld, s));
+        for (int j = 0; j < mA; ++j) {
+            int slot = M + j;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int i = 0; i < j; ++i) {
+                    LZ_TRY(dense_dots((const void* const*)(tSX + M + i), (const void* const*)(tX + slot), 1, K, dots, s));
+                    LZ_TRY(dense_axpy(tX + slot, (const void* const*)(tX + M + i), dots, -1.0, 1, K, s));
+                }
+            LZ_TRY(launch_spsi(p, ik, vec(X, slot), vec(SX, slot), 1, ld, 0, s));
+            LZ_TRY(dense_dots((const void* const*)(tX + slot), (const void* const*)(tSX + slot), 1, K, dots, s));
+            LZ_TRY(dense_normalize(tX + slot, tSX + slot, dots, 1, K, s));
+            LZ_TRY(hop(vec(X, slot), vec(HX, slot), nullptr, 1, prec));
+            if (j + 1 < mA)
+                LZ_TRY(launch_prec_apply(p, ik, vec(HX, slot), vec(SX, slot), theta + v, nullptr, vec(X, slot + 1), 1,
+                                         ld, s));
+        }
+        return global_rr(NG);
+    }
+};
+
+mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_lanczos_opts& o, const void* x0,
+                       double* eig, void* xout, mb_lanczos_info* info, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const KPoint& kp = p->kp[ik];
+    Solver S{};
+    S.p = p;
+    S.ik = ik;
+    S.s = s;
+    S.M = nev;
+    S.b = std::max(1, std::min(o.block, nev));
+    while (nev % S.b) --S.b;
+    S.nbl = nev / S.b;
+    S.m = std::max(1, o.krylov);
+    S.mA = std::max(0, o.krylov_global);
+    S.NG = nev + S.mA;
+    S.NR = S.b + S.m;
+    S.ld = kp.ld;
+    S.K = (int64_t)p->nb * kp.ld;
+    S.vbytes = (size_t)S.K * 16;
+    if (S.NG > 256 || S.NR > 64 || S.b > 32)
+        return set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: nev + krylov_global must be <= 256, block + krylov <= 64");
+    if ((int64_t)nev > (int64_t)kp.ng * p->nb) return set_error(MB_ERR_INVALID_ARG, "nev exceeds the basis size");
+
+    // vector workspace
+    size_t nvec = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl;
+    LZ_TRY(ensure_ws(p->ws_lz, nvec * S.vbytes));
+    char* base = (char*)p->ws_lz.ptr;
+    auto take = [&](int n) {
+        char* r = base;
+        base += (size_t)n * S.vbytes;
+        return r;
+    };
+    S.X = take(S.NG);
+    S.HX = take(S.NG);
+    S.SX = take(S.NG);
+    S.Xn = take(S.M);
+    S.HXn = take(S.M);
+    S.SXn = take(S.M);
+    S.Kv = take(S.m * S.nbl);
+    S.HK = take(S.m * S.nbl);
+    S.SK = take(S.m * S.nbl);
+
+    // small workspace
+    const size_t NN = std::max((size_t)S.NG * S.NG, (size_t)S.nbl * S.NR * S.NR);
+    const size_t ntab = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl + 3 * (size_t)S.nbl * S.NR;
+    S.gscratch_bytes = (size_t)32 << 20;
+    size_t small = ntab * sizeof(void*) + 3 * NN * 16 + (size_t)S.NG * S.M * 16 + 3 * NN * 16 +
+                   NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 + (size_t)S.nbl * 16 +
+                   (3 * (size_t)S.M + S.nbl + 64) * 8 + S.gscratch_bytes + 4096;
+    LZ_TRY(ensure_ws(p->ws_small, small));
+    char* sb = (char*)p->ws_small.ptr;
+    auto stake = [&](size_t bytes) {
+        char* r = sb;
+        sb += (bytes + 255) / 256 * 256;
+        return (void*)r;
+    };
+    std::vector<void*> htab;
+    auto add_tab = [&](char* vbase, int n) {
+        size_t off = htab.size();
+        for (int i = 0; i < n; ++i) htab.push_back(vbase + (size_t)i * S.vbytes);
+        return off;
+    };
+    size_t oX = add_tab(S.X, S.NG), oHX = add_tab(S.HX, S.NG), oSX = add_tab(S.SX, S.NG);
+    size_t oXn = add_tab(S.Xn, S.M), oHXn = add_tab(S.HXn, S.M), oSXn = add_tab(S.SXn, S.M);
+    size_t oK = add_tab(S.Kv, S.m * S.nbl), oHK = add_tab(S.HK, S.m * S.nbl), oSK = add_tab(S.SK, S.m * S.nbl);
+    size_t oQ = htab.size();
+    for (int which = 0; which < 3; ++which) {
+        char* xb = which == 0 ? S.X : which == 1 ? S.HX : S.SX;
+        char* kb = which == 0 ? S.Kv : which == 1 ? S.HK : S.SK;
+        for (int z = 0; z < S.nbl; ++z) {
+            for (int a = 0; a < S.b; ++a) htab.push_back(xb + (size_t)(z * S.b + a) * S.vbytes);
+            for (int j = 0; j < S.m; ++j) htab.push_back(kb + (size_t)(j * S.nbl + z) * S.vbytes);
+        }
+    }
+    void** dtab = (void**)stake(htab.size() * sizeof(void*));
+    MB_HIP_TRY(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+    S.tX = dtab + oX; S.tHX = dtab + oHX; S.tSX = dtab + oSX;
+    S.tXn = dtab + oXn; S.tHXn = dtab + oHXn; S.tSXn = dtab + oSXn;
+    S.tK = dtab + oK; S.tHK = dtab + oHK; S.tSK = dtab + oSK;
+    size_t qn = (size_t)S.nbl * S.NR;
+    S.tQ = dtab + oQ; S.tHQ = dtab + oQ + qn; S.tSQ = dtab + oQ + 2 * qn;
+    S.Hp = stake(NN * 16);
+    S.Sp = stake(NN * 16);
+    S.Y = stake(NN * 16);
+    S.W = stake(std::max((size_t)S.NG * S.M, (size_t)S.nbl * S.NR * S.b) * 16);
+    S.gwork = stake(3 * NN * 16);
+    S.evals = (double*)stake(NN * sizeof(double));
+    S.coef = stake((size_t)S.M * std::max(S.nbl, S.NG) * 16);
+    S.dots = stake((size_t)std::max(S.nbl, 1) * 16);
+    S.theta = (double*)stake(S.NG * sizeof(double));
+    S.theta_s = (double*)stake(S.nbl * sizeof(double));
+    S.sel = (int32_t*)stake(S.nbl * sizeof(int32_t));
+    S.resid = (double*)stake(S.M * sizeof(double));
+    S.status = (int*)stake(64);
+    S.gscratch = stake(S.gscratch_bytes);
+    if ((size_t)(sb - (char*)p->ws_small.ptr) > p->ws_small.bytes) return set_error(MB_ERR_INVALID_ARG, "small workspace layout");
+    MB_HIP_TRY(hipMemsetAsync(S.status, 0, sizeof(int), s));
+    S.h_theta.assign(S.M, 0.0);
+    S.h_resid.assign(S.M, 0.0);
+
+    LZ_TRY(launch_prec_factor(p, ik, o.sigma, s));
+
+    // start vectors
+    if (x0) MB_HIP_TRY(hipMemcpyAsync(S.X, x0, (size_t)S.M * S.vbytes, hipMemcpyDeviceToDevice, s));
+    else LZ_TRY(dense_random(S.X, S.M, p->nb, S.ld, kp.ng, o.seed, s));
+    int cur = prec == MB_FP64 ? 0 : 2;
+    LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, cur));
+    LZ_TRY(S.global_rr(S.M));
+
+    mb_status result = MB_ERR_NOT_CONVERGED;
+    int it = 0, it_low = 0;
+    double best = 1e300;
+    int stall = 0;
+    for (; it < o.max_iter; ++it) {
+        LZ_TRY(S.residuals());
+        double mx = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+        if (cur != 0) {
+            if (mx < 0.9 * best) { best = mx; stall = 0; } else ++stall;
+            if (mx <= o.switch_tol || stall >= 4) {
+                // continue in FP64: refresh H X at full precision
+                cur = 0;
+                LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, 0));
+                LZ_TRY(S.global_rr(S.M));
+                LZ_TRY(S.residuals());
+                mx = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+            }
+        }
+        if (cur == 0 && mx <= o.tol) {
+            result = MB_OK;
+            break;
+        }
+        if (cur != 0) ++it_low;
+        LZ_TRY(S.block_cycle(cur));
+        // residual estimates for the seed of the global cycle
+        LZ_TRY(dense_resid((const void* const*)S.tHX, (const void* const*)S.tSX, S.theta, S.M, S.K, S.resid, s));
+        MB_HIP_TRY(hipMemcpyAsync(S.h_resid.data(), S.resid, S.M * sizeof(double), hipMemcpyDeviceToHost, s));
+        MB_HIP_TRY(hipStreamSynchronize(s));
+        LZ_TRY(S.global_cycle(cur));
+    }
+    if (result != MB_OK) {
+        LZ_TRY(S.residuals());
+        set_error(MB_ERR_NOT_CONVERGED, "lanczos_lowest: max_iter reached");
+    }
+    if (xout) MB_HIP_TRY(hipMemcpyAsync(xout, S.X, (size_t)S.M * S.vbytes, hipMemcpyDeviceToDevice, s));
+    MB_HIP_TRY(hipStreamSynchronize(s));
+    if (eig) std::memcpy(eig, S.h_theta.data(), S.M * sizeof(double));
+    if (info) {
+        info->iters = it;
+        info->iters_low = it_low;
+        info->h_applies = S.applies;
+        info->h_applies_low = S.applies_low;
+        info->max_resid = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+        info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return result;
+}
+
+}  // namespace
+}  // namespace mb
 
 extern "C" void mb_lanczos_default_opts(mb_lanczos_opts* o) {
     if (!o) return;
     o->block = 1;
-    o->krylov = 2;
+    o->krylov = 4;
     o->krylov_global = 2;
-    o->max_iter = 200;
+    o->max_iter = 300;
     o->tol = 1e-7;
     o->sigma = 1.0;
     o->switch_tol = 1e-4;
     o->seed = 14064960ull;
 }
 
-extern "C" mb_status lanczos_lowest(mb_problem*, int, int, mb_precision, const mb_lanczos_opts*, const void*,
-                                    double*, void*, mb_lanczos_info*, void*) {
-    return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: not built yet");
+extern "C" mb_status lanczos_lowest(mb_problem* h, int ik, int nev, mb_precision prec, const mb_lanczos_opts* opts,
+                                    const void* x0, double* eig, void* x, mb_lanczos_info* info, void* stream) {
+    mb::Problem* p = mb::problem_of(h);
+    if (!p) return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: problem is NULL");
+    if (p->device < 0) return mb::set_error(MB_ERR_NO_DEVICE, "lanczos_lowest: host-only problem");
+    if (ik < 0 || ik >= (int)p->kp.size()) return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: ik out of range");
+    if (nev < 1) return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: nev < 1");
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: unknown precision");
+    if (p->order != 4) return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: GPU kernels support order 4 only");
+    mb_lanczos_opts o;
+    mb_lanczos_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_iter < 1 || o.krylov < 1 || o.block < 1 || o.krylov_global < 0 || !(o.tol > 0))
+        return mb::set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: bad options");
+    return mb::lanczos_impl(p, ik, nev, prec, o, x0, eig, x, info, (hipStream_t)stream);
 }
