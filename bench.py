@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed-basis eigen-search hot path on one MI355X.
+
+Workload: the graphene-like slab (hexagonal a = 4.65 bohr, 36x36 in-plane grid,
+~483 G per k-point, 80 graded cubic B-splines on [-20, 20] with 5 Gauss points
+per interval, 2 atoms with Gaussian local parts and 4 Kleinman-Bylander
+projectors each, 2x2 Monkhorst-Pack k-points, 32 bands; n = 38,640 per k),
+synthetic and seeded.
+
+One step = lanczos_lowest for the 32 lowest eigenpairs of every k-point from a
+seeded random start, in the headline precision (mixed: FP32 local / nonlocal
+parts of H until the residual reaches 1e-4, then FP64; FP64 orthonormalisation,
+Krylov coefficients and projected problems throughout), to residual 1e-7.
+
+Printed JSON line:
+  value            H band-vectors applied per second over the timed steps
+  ms_per_step      time to the 4 x 32 eigenpairs (all k-points)
+  fp64             the same step in plain FP64 (time, eigenvalue errors)
+  hpsi             pure hpsi_apply throughput (32 bands x 4 k per call) in FP64 / FP32
+  roofline         the fused local-potential kernel (dominant kernel)
+  cpu_baseline     the CPU FP64 oracle's matrix-free H application, bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def local_model(p, ik, csz_in, csz):
+    """Algorithmic flops and bytes per band-vector of the fused local kernel
+    (B-spline evaluate, inverse FFT, V multiply, forward FFT, project)."""
+    dm = p.dims(ik)
+    N1, N2 = p.desc["grid"]
+    N = N1 * N2
+    nzq, ng, nb = dm["nzq"], dm["ng"], dm["nb"]
+    nint = len(p.desc["breakpoints"]) - 1
+    flops = nzq * (32 * ng + 10 * N * math.log2(N) + 2 * N)
+    bytes_ = nb * ng * csz_in + 4 * nint * ng * csz
+    vbytes = nzq * N * (csz // 2)
+    return flops, bytes_, vbytes
+
+
+def traffic_record(name):
+    """HBM traffic per launch measured with rocprofv3 counters, if the kernel
+    source has not changed since (compared by hash)."""
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1406_4960_amd", "csrc", "k_local.hip"), "rb").read()
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec
+
+
+def cpu_baseline(desc, budget_s=15.0):
+    """Oracle matrix-free FP64 H application on the same workload (k-point 0),
+    bounded sample: blocks of 8 band-vectors until ~budget_s seconds."""
+    from oracle import matfree
+    from paper_1406_4960_amd import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    mf = matfree.MatFree(desc, 0)
+    x = workloads.random_block(99, 8, mf.ng, mf.nb)
+    mf.apply(x[:1])  # warm
+    done, t0 = 0, time.perf_counter()
+    while True:
+        mf.apply(x)
+        done += x.shape[0]
+        el = time.perf_counter() - t0
+        if el > budget_s:
+            break
+    return {"value": done / el, "unit": "band-vectors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} band-vectors of H (k-point 0, FP64 matrix-free oracle) in {el:.1f} s; "
+                      f"potential tables built before timing"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="graphene")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
+                    help="reduced precision of the headline step (fp32 = mixed FP32/FP64)")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--hpsi-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device-to-device copy of BYTES (counter calibration) and exit")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1406_4960_amd import mbks, workloads
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n}))
+        return 0
+
+    desc = workloads.CONFIGS[args.workload]()
+    nk = len(desc["kpts"])
+    M = desc["nbands"]
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    p = mbks.Problem(desc, device=0)
+    dims = [p.dims(ik) for ik in range(nk)]
+    log("workload", desc["name"], dims[0])
+
+    # ---- pure H application throughput (inputs resident in HBM) ---------------
+    hp = {}
+    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+        xs, ys = [], []
+        for ik in range(nk):
+            x = workloads.random_block(ik, M, dims[ik]["nb"], dims[ik]["ng"])
+            xt = torch.zeros((M, dims[ik]["nb"], dims[ik]["ld"]), dtype=ct, device=dev)
+            xt[:, :, :dims[ik]["ng"]] = torch.from_numpy(x).to(dev).to(ct)
+            xs.append(xt)
+            ys.append(torch.empty_like(xt))
+        for _ in range(3):
+            for ik in range(nk):
+                p.hpsi(ik, xs[ik], ys[ik], prec)
+        torch.cuda.synchronize()
+        mbks.timer_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.hpsi_reps):
+            for ik in range(nk):
+                p.hpsi(ik, xs[ik], ys[ik], prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = mbks.timer_read()
+        mbks.timer_enable(False)
+        hp[prec] = {"band_vectors_per_s": args.hpsi_reps * nk * M / (ms * 1e-3),
+                    "ms_per_call": ms / (args.hpsi_reps * nk),
+                    "stages_ms": {k: round(v[0], 4) for k, v in st.items() if v[1]}}
+        log("hpsi", prec, hp[prec])
+        del xs, ys
+
+    # ---- eigen-search steps --------------------------------------------------
+    def solve_all(prec):
+        eigs, infos = [], []
+        for ik in range(nk):
+            eig, x, info, stc = p.lanczos_lowest(ik, M, prec)
+            eigs.append(eig)
+            infos.append(info)
+            del x
+        return eigs, infos
+
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_eigs.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath))
+
+    def errors(eigs):
+        if golden is None:
+            return None
+        errs = [float(np.max(np.abs(eigs[ik] - np.array(golden["kpoints"][str(ik)]["eps"]))))
+                for ik in range(nk) if str(ik) in golden["kpoints"]]
+        return max(errs) if errs else None
+
+    head = args.prec
+    for _ in range(args.warmup):
+        solve_all(head)
+    torch.cuda.synchronize()
+    mbks.timer_enable(True)
+    t0 = time.perf_counter()
+    applies = 0
+    infos_all = []
+    eigs = None
+    for _ in range(args.steps):
+        eigs, infos = solve_all(head)
+        applies += sum(i["h_applies"] for i in infos)
+        infos_all += infos
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    stages = mbks.timer_read()
+    mbks.timer_enable(False)
+    ms_per_step = 1e3 * t_steps / args.steps
+    head_err = errors(eigs)
+    head_res = max(i["max_resid"] for i in infos_all)
+    log("step", head, ms_per_step, "ms; applies/step", applies / args.steps, "err", head_err)
+
+    # plain FP64 form of the same step
+    fp64 = None
+    if head != "fp64" and args.fp64_steps > 0:
+        solve_all("fp64")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        a64 = 0
+        for _ in range(args.fp64_steps):
+            e64, i64 = solve_all("fp64")
+            a64 += sum(i["h_applies"] for i in i64)
+        torch.cuda.synchronize()
+        t64 = 1e3 * (time.perf_counter() - t1) / args.fp64_steps
+        fp64 = {"ms_per_step": t64, "h_applies_per_step": a64 / args.fp64_steps,
+                "max_eig_err_vs_oracle": errors(e64), "max_resid": max(i["max_resid"] for i in i64),
+                "speedup_mixed_vs_fp64": t64 / ms_per_step}
+        log("fp64 step", fp64)
+
+    # ---- roofline of the dominant kernel (fused local-potential kernel) -------
+    tot = {k: v for k, v in stages.items() if v[1]}
+    dominant = max(tot, key=lambda k: tot[k][0])
+    lname = "local32" if stages["local32"][0] >= stages["local"][0] else "local"
+    lms, lcount, lunits = stages[lname]
+    csz = 8 if lname == "local32" else 16
+    flops_b, bytes_b, vbytes = local_model(p, 0, 16, csz)
+    flops = flops_b * lunits
+    avg_ms = lms / max(lcount, 1)
+    achieved = flops / (lms * 1e-3) / 1e12 if lms > 0 else 0.0
+    peak = PEAK_FP32_TFLOPS if lname == "local32" else PEAK_FP64_TFLOPS
+    tr = traffic_record(f"k_local_{args.workload}_traffic")
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": (tr["bytes_per_launch"] if tr else None),
+                "kernel": f"k_local ({'FP32' if lname == 'local32' else 'FP64'} arithmetic, c128 vectors)",
+                "avg_launch_ms": round(avg_ms, 5), "launches": lcount,
+                "flops_per_band_vector": flops_b, "algorithmic_bytes_per_band_vector": bytes_b,
+                "hbm_gbs_algorithmic": round((bytes_b * lunits + vbytes * lcount) / (lms * 1e-3) / 1e9, 1)
+                if lms > 0 else None,
+                "dominant_stage": dominant,
+                "stage_ms": {k: round(v[0], 3) for k, v in tot.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(desc)
+        except Exception as exc:  # report, do not fail the benchmark line
+            cpu = {"value": None, "unit": "band-vectors/s", "cores": None, "kind": "oracle",
+                   "sample": f"failed: {exc}"}
+
+    value = applies / t_steps
+    out = {
+        "metric": "Hψ band-vectors/s + time to N eigenpairs at 1e-6 Ha: mixed/batched vs FP64",
+        "value": round(value, 1),
+        "unit": "band-vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc["name"], "kpoints": nk, "bands": M, "n_per_k": dims[0]["ng"] * dims[0]["nb"],
+                   "grid": desc["grid"], "splines": dims[0]["nb"], "projectors": dims[0]["np"],
+                   "tol_resid": 1e-7},
+        "time_to_eigenpairs_ms": round(ms_per_step, 2),
+        "max_eig_err_vs_oracle": head_err,
+        "max_resid": head_res,
+        "h_applies_per_step": applies / args.steps,
+        "fp64": fp64,
+        "hpsi": hp,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    p.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -198,6 +198,32 @@ mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
                          const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
                          mb_lanczos_info* info, void* stream);
 
+/* Stage timer for measurement runs: while enabled, every kernel launch of the
+ * library is bracketed by HIP events recorded on the stream it is launched on.
+ * mb_timer_enable(1) clears earlier records; mb_timer_read synchronises the
+ * recorded events of one stage and returns the summed kernel time (ms) and the
+ * number of launches.  Stages: MB_STAGE_LOCAL (fused evaluate / FFT / V / FFT /
+ * project, FP64 arithmetic), MB_STAGE_NL_PROJECT, MB_STAGE_COMBINE, MB_STAGE_SPSI, MB_STAGE_SSOLVE,
+ * MB_STAGE_PRECOND, MB_STAGE_GRAM, MB_STAGE_COMBO, MB_STAGE_SMALLEIG, MB_STAGE_OTHER,
+ * MB_STAGE_LOCAL32.
+ * Not thread safe; enable only in single-threaded measurement code. */
+#define MB_STAGE_LOCAL 0
+#define MB_STAGE_NL_PROJECT 1
+#define MB_STAGE_COMBINE 2
+#define MB_STAGE_SPSI 3
+#define MB_STAGE_SSOLVE 4
+#define MB_STAGE_PRECOND 5
+#define MB_STAGE_GRAM 6
+#define MB_STAGE_COMBO 7
+#define MB_STAGE_SMALLEIG 8
+#define MB_STAGE_OTHER 9
+#define MB_STAGE_LOCAL32 10  /* the local-potential kernel with FP32 arithmetic */
+#define MB_NSTAGE 11
+mb_status mb_timer_enable(int on);
+/* total_ms: summed kernel time; count: launches; units (may be NULL): summed band
+ * count of the launches (vectors processed) */
+mb_status mb_timer_read(int stage, double* total_ms, int64_t* count, int64_t* units);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* mb_last_error(void);
 

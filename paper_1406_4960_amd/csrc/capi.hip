@@ -86,7 +86,46 @@ mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void
     return MB_OK;
 }
 
+struct TimerState {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MB_NSTAGE];
+    double done_ms[MB_NSTAGE] = {0};
+    int64_t done_n[MB_NSTAGE] = {0};
+    int64_t units[MB_NSTAGE] = {0};
+};
+TimerState g_timer;
+
+void timer_clear() {
+    for (int k = 0; k < MB_NSTAGE; ++k) {
+        for (auto& pr : g_timer.ev[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        g_timer.ev[k].clear();
+        g_timer.done_ms[k] = 0;
+        g_timer.done_n[k] = 0;
+        g_timer.units[k] = 0;
+    }
+}
+
 }  // namespace
+
+StageScope::StageScope(int st, hipStream_t str, int64_t u) : stage(st), s(str), units(u) {
+    if (!g_timer.on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    ev0 = (void*)e;
+}
+
+StageScope::~StageScope() {
+    if (!ev0) return;
+    hipEvent_t e1;
+    if (hipEventCreate(&e1) != hipSuccess) return;
+    (void)hipEventRecord(e1, s);
+    g_timer.ev[stage].emplace_back((hipEvent_t)ev0, e1);
+    g_timer.units[stage] += units;
+}
 
 mb_status set_error(mb_status s, const std::string& msg) {
     g_last_error = msg;
@@ -177,6 +216,31 @@ using mb::set_error;
 extern "C" {
 
 const char* mb_last_error(void) { return mb::g_last_error.c_str(); }
+
+mb_status mb_timer_enable(int on) {
+    mb::timer_clear();
+    mb::g_timer.on = on != 0;
+    return MB_OK;
+}
+
+mb_status mb_timer_read(int stage, double* total_ms, int64_t* count, int64_t* units) {
+    if (stage < 0 || stage >= MB_NSTAGE) return set_error(MB_ERR_INVALID_ARG, "mb_timer_read: stage");
+    auto& v = mb::g_timer.ev[stage];
+    for (auto& pr : v) {
+        MB_HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        MB_HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        mb::g_timer.done_ms[stage] += ms;
+        mb::g_timer.done_n[stage] += 1;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    v.clear();
+    if (total_ms) *total_ms = mb::g_timer.done_ms[stage];
+    if (count) *count = mb::g_timer.done_n[stage];
+    if (units) *units = mb::g_timer.units[stage];
+    return MB_OK;
+}
 
 mb_status mb_problem_create(const mb_desc* desc, int device, mb_problem** out) {
     if (!out) return set_error(MB_ERR_INVALID_ARG, "out is NULL");

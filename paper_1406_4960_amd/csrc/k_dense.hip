@@ -478,6 +478,7 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     kchunk = (kchunk + GK - 1) / GK * GK;
     nchunk = (int)((K + kchunk - 1) / kchunk);
     dim3 grid(nchunk, tiles_m * tiles_n, nz);
+    StageScope ts_(MB_STAGE_GRAM, s);
     hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk,
                        nchunk, tiles_n, (zc*)scratch);
     MB_HIP_TRY(hipGetLastError());
@@ -494,6 +495,7 @@ mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int
     size_t lds = (size_t)MI * CN * sizeof(zc);
     if (lds > 65536) return set_error(MB_ERR_INVALID_ARG, "combination with too many inputs");
     dim3 grid((unsigned)((K + 255) / 256), (NO + CN - 1) / CN, nz);
+    StageScope ts_(MB_STAGE_COMBO, s);
     hipLaunchKernelGGL(k_combo, grid, dim3(256), lds, s, (const zc* const*)tx, (zc* const*)ty, (const zc*)W, MI, NO,
                        K, alpha, beta);
     MB_HIP_TRY(hipGetLastError());
@@ -501,6 +503,7 @@ mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int
 }
 
 mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
     hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, K, (zc*)out);
     MB_HIP_TRY(hipGetLastError());
@@ -509,6 +512,7 @@ mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int
 
 mb_status dense_resid(const void* const* th, const void* const* ts, const double* theta, int nvec, int64_t K,
                       double* out, hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
     hipLaunchKernelGGL(k_resid, dim3(nvec), dim3(256), 0, s, (const zc* const*)th, (const zc* const*)ts, theta, K,
                        out);
@@ -518,6 +522,7 @@ mb_status dense_resid(const void* const* th, const void* const* ts, const double
 
 mb_status dense_axpy(void* const* ty, const void* const* tx, const void* coef, double sign, int nvec, int64_t K,
                      hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
     dim3 grid((unsigned)((K + 255) / 256), nvec);
     hipLaunchKernelGGL(k_axpy_tab, grid, dim3(256), 0, s, (zc* const*)ty, (const zc* const*)tx, (const zc*)coef, sign,
@@ -527,6 +532,7 @@ mb_status dense_axpy(void* const* ty, const void* const* tx, const void* coef, d
 }
 
 mb_status dense_normalize(void* const* t1, void* const* t2, const void* d, int nvec, int64_t K, hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
     dim3 grid((unsigned)((K + 255) / 256), nvec);
     hipLaunchKernelGGL(k_normalize_tab, grid, dim3(256), 0, s, (zc* const*)t1, (zc* const*)t2, (const zc*)d, K);
@@ -535,6 +541,7 @@ mb_status dense_normalize(void* const* t1, void* const* t2, const void* d, int n
 }
 
 mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed, hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     int64_t tot = (int64_t)nvec * nb * ld;
     hipLaunchKernelGGL(k_random, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (zc*)x, nvec, nb, ld, ng, seed);
     MB_HIP_TRY(hipGetLastError());
@@ -548,6 +555,7 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
     int use_lds = lds <= 131072 ? 1 : 0;
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
     const size_t dyn = use_lds ? lds : 0;
+    StageScope ts_(MB_STAGE_SMALLEIG, s);
     if (N <= 48) {
         if (dyn > 65536)
             MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
@@ -565,6 +573,7 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
 
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
                        hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     if (b > 32 || nr > 64) return set_error(MB_ERR_INVALID_ARG, "block too large for selection");
     hipLaunchKernelGGL(k_select, dim3((nblocks + 63) / 64), dim3(64), 0, s, (const zc*)Y, ev, nr, b, (zc*)C, theta,
                        nblocks);
@@ -573,6 +582,7 @@ mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, 
 }
 
 mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* out, hipStream_t s) {
+    StageScope ts_(MB_STAGE_OTHER, s);
     int tot = nrows * ncols;
     hipLaunchKernelGGL(k_copy_cols, dim3((tot + 255) / 256), dim3(256), 0, s, (const zc*)Y, ldy, ncols, nrows,
                        (zc*)out);

@@ -252,6 +252,7 @@ mb_status run_local(const LocalArgs<TI, T>& a, size_t lds, hipStream_t s) {
     if (lds > 65536)
         MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned nblocks = (unsigned)a.nbands * (unsigned)a.nint;
+    StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, a.nbands);
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;

@@ -50,6 +50,7 @@ mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int n
     if (p->np == 0) return MB_OK;
     const KPoint& kp = p->kp[ik];
     dim3 grid(p->np, nbands);
+    StageScope ts_(MB_STAGE_NL_PROJECT, s, nbands);
     if (prec == 0)
         hipLaunchKernelGGL((k_nl_project<double, double, 256>), grid, dim3(256), 0, s, (const cx<double>*)c,
                            (const cx<double>*)kp.d_F64, p->d_Z, p->d_E, p->d_zwin, (cx<double>*)proj, nbands,

@@ -249,6 +249,7 @@ mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, cons
     if (p->np == 0) a.proj = nullptr;
     int nchunk = (p->nb + CH - 1) / CH;
     dim3 grid((ld + 255) / 256, nbands * nchunk);
+    StageScope ts_(y ? MB_STAGE_COMBINE : MB_STAGE_SPSI, s, nbands);
     hipLaunchKernelGGL((k_combine<TI, T>), grid, dim3(256), 0, s, a);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -272,6 +273,7 @@ mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, in
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s) {
     const KPoint& kp = p->kp[ik];
     dim3 grid((ld + 255) / 256, nbands);
+    StageScope ts_(MB_STAGE_SSOLVE, s, nbands);
     if (prec == 1)
         hipLaunchKernelGGL(k_ssolve<float>, grid, dim3(256), 0, s, (const cx<float>*)r, (cx<float>*)x,
                            p->d_lband, nbands, kp.ng, p->nb, ld);
@@ -308,6 +310,7 @@ mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, c
     const KPoint& kp = p->kp[ik];
     if (!kp.d_pfac || ld != kp.ld) return set_error(MB_ERR_INVALID_ARG, "preconditioner not built for this ld");
     dim3 grid((ld + 255) / 256, nvec);
+    StageScope ts_(MB_STAGE_PRECOND, s, nvec);
     hipLaunchKernelGGL(k_prec_apply, grid, dim3(256), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
                        sel, (cx<double>*)x, kp.d_pfac, nvec, kp.ng, p->nb, ld);
     MB_HIP_TRY(hipGetLastError());

@@ -101,6 +101,16 @@ struct Problem {
     Workspace ws_conv;    // precision conversion buffers
 };
 
+// stage timer: brackets one kernel launch with events when enabled
+struct StageScope {
+    int stage;
+    hipStream_t s;
+    int64_t units;
+    void* ev0 = nullptr;
+    StageScope(int stage, hipStream_t s, int64_t units = 0);
+    ~StageScope();
+};
+
 // status helpers
 mb_status set_error(mb_status s, const std::string& msg);
 #define MB_HIP_TRY(call)                                                               \

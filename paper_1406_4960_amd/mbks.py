@@ -26,7 +26,7 @@ MB_MAX_GAUSS = 4
 EXPORTS = ("mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
            "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
-           "mb_last_error")
+           "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
 class MbError(RuntimeError):
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.mb_lanczos_default_opts.restype = None
     lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
                                    POINTER(LanczosInfo), vp]
+    lib.mb_timer_enable.argtypes = [c_int]
+    lib.mb_timer_read.argtypes = [c_int, POINTER(c_double), POINTER(c_int64), POINTER(c_int64)]
     lib.mb_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("mb_lanczos_default_opts", "mb_last_error"):
@@ -117,6 +119,24 @@ def _stream(stream):
 
 def _ptr(t):
     return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+STAGES = ("local", "nl_project", "combine", "spsi", "ssolve", "precond", "gram", "combo", "smalleig", "other",
+          "local32")
+
+
+def timer_enable(on: bool = True):
+    _check(load().mb_timer_enable(int(on)))
+
+
+def timer_read():
+    """{stage: (total_ms, launches, units)} of the kernels recorded since timer_enable."""
+    out = {}
+    for k, name in enumerate(STAGES):
+        ms, n, u = c_double(), c_int64(), c_int64()
+        _check(load().mb_timer_read(k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+        out[name] = (ms.value, n.value, u.value)
+    return out
 
 
 class Problem:
