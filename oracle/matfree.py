@@ -40,23 +40,32 @@ class MatFree:
             vt = vtilde_grid(desc, potential_on_grid(desc, self.zb.zq, vfunc))
             d1 = (self.m[:, None, 0] - self.m[None, :, 0]) % N1
             d2 = (self.m[:, None, 1] - self.m[None, :, 1]) % N2
-            self.Vpl = vt[:, d1, d2]  # (Nq, NG, NG): Vt(G - G', z_q)
+            self.Vpl = np.ascontiguousarray(vt[:, d1, d2])  # (Nq, NG, NG): Vt(G - G', z_q)
         else:
             self.Vpl = None
         self.F, self.Z, self.E = projector_factors(desc, ik, self.zb)
 
     # vectors as [nvec][G][i]
+    def apply_s(self, x: np.ndarray) -> np.ndarray:
+        return x @ self.Sz
+
     def apply(self, x: np.ndarray):
         """(H x, S x) for x of shape (nvec, NG, Nb)."""
+        nv = x.shape[0]
         Sx = x @ self.Sz
         Hx = 0.5 * (x @ self.Dz) + 0.5 * self.kg2[None, :, None] * Sx
         if self.Vpl is not None:
-            psi = np.einsum("qj,vgj->qgv", self.zb.B, x)          # (Nq, NG, nvec)
-            vpsi = np.matmul(self.Vpl, psi)                      # per plane: Vt @ psi
-            Hx = Hx + np.einsum("qi,qgv->vgi", self.zb.B * self.zb.wq[:, None], vpsi)
+            # psi(G', z_q) = sum_j B_j(z_q) x(G', j), as (Nq, NG, nvec)
+            psi = (x.reshape(nv * self.ng, self.nb) @ self.zb.B.T).reshape(nv, self.ng, -1)
+            psi = np.ascontiguousarray(np.transpose(psi, (2, 1, 0)))
+            vpsi = np.matmul(self.Vpl, psi)                      # per plane: Vt(G - G') psi(G')
+            wb = self.zb.B * self.zb.wq[:, None]                 # (Nq, Nb)
+            out = np.transpose(vpsi, (2, 1, 0)).reshape(nv * self.ng, -1) @ wb
+            Hx = Hx + out.reshape(nv, self.ng, self.nb)
         if len(self.E):
-            proj = np.einsum("pg,pi,vgi->pv", self.F.conj(), self.Z, x)
-            Hx = Hx + np.einsum("p,pg,pi,pv->vgi", self.E, self.F, self.Z, proj)
+            FZ = (self.F[:, :, None] * self.Z[:, None, :]).reshape(len(self.E), -1)  # <G,i|beta_p>
+            proj = FZ.conj() @ x.reshape(nv, -1).T               # (Np, nvec)
+            Hx = Hx + ((FZ.T * self.E[None, :]) @ proj).T.reshape(nv, self.ng, self.nb)
         return Hx, Sx
 
     def _linop(self, which: str):
@@ -65,30 +74,28 @@ class MatFree:
         def mv(v):
             v2 = np.asarray(v).reshape(n, -1)
             x = v2.T.reshape(-1, ng, nb)
-            h, s = self.apply(x)
-            out = h if which == "H" else s
+            out = self.apply(x)[0] if which == "H" else self.apply_s(x)
             return out.reshape(x.shape[0], n).T
 
         return scipy.sparse.linalg.LinearOperator((n, n), matvec=mv, matmat=mv, dtype=np.complex128)
 
     def _precond(self, sigma: float = 1.0):
-        facs = []
+        # (T + sigma S)^{-1} per G, as explicit inverses applied in one batched product
+        inv = np.empty((self.ng, self.nb, self.nb))
         for g in range(self.ng):
             A = 0.5 * self.Dz + (0.5 * self.kg2[g] + sigma) * self.Sz
-            facs.append(scipy.linalg.cho_factor(A))
+            inv[g] = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), np.eye(self.nb))
         ng, nb, n = self.ng, self.nb, self.n
 
         def mv(v):
             v2 = np.asarray(v).reshape(n, -1)
             x = v2.T.reshape(-1, ng, nb)
-            out = np.empty_like(x)
-            for g in range(ng):
-                out[:, g, :] = scipy.linalg.cho_solve(facs[g], x[:, g, :].T).T
+            out = np.matmul(inv[None, :, :, :], x[:, :, :, None])[..., 0]
             return out.reshape(x.shape[0], n).T
 
         return scipy.sparse.linalg.LinearOperator((n, n), matvec=mv, matmat=mv, dtype=np.complex128)
 
-    def lowest(self, nev: int, extra: int = 8, tol: float = 1e-10, maxiter: int = 2000, seed: int = 0):
+    def lowest(self, nev: int, extra: int = 8, tol: float = 1e-9, maxiter: int = 200, seed: int = 0):
         """Lowest nev eigenpairs: (eps, C [nev][NG][Nb] S-orthonormal, residual norms)."""
         rng = np.random.default_rng(seed)
         k = nev + extra

@@ -11,7 +11,9 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
 // Y_{z,n} = alpha sum_m W_z[m][n] X_{z,m} + beta Y_{z,n}; W_z is MI x NO row-major.
 mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
                       double alpha, double beta, hipStream_t s);
-mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, hipStream_t s);
+// scratch: at least 64 * nvec complex doubles
+mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, void* scratch,
+                     hipStream_t s);
 mb_status dense_resid(const void* const* th, const void* const* ts, const double* theta, int nvec, int64_t K,
                       double* out, hipStream_t s);
 mb_status dense_axpy(void* const* ty, const void* const* tx, const void* coef, double sign, int nvec, int64_t K,

@@ -56,14 +56,24 @@ __global__ __launch_bounds__(256) void k_gram(const zc* const* ta, const zc* con
     if (m < MA && n < NB) part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = acc;
 }
 
-__global__ void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
-    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t per = (size_t)MA * NB;
+// one wave per output element: lanes stride over the chunks, then a shuffle tree
+__global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
+    const size_t per = (size_t)MA * NB;
+    const size_t idx = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int lane = threadIdx.x % 64;
     if (idx >= per * nz) return;
-    size_t z = idx / per, e = idx % per;
-    zc s = mk<double>(0, 0);
-    for (int c = 0; c < nchunk; ++c) s = cadd(s, part[(z * nchunk + c) * per + e]);
-    out[idx] = s;
+    const size_t z = idx / per, e = idx % per;
+    double re = 0.0, im = 0.0;
+    for (int c = lane; c < nchunk; c += 64) {
+        zc v = part[(z * nchunk + c) * per + e];
+        re += v.x;
+        im += v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) out[idx] = mk<double>(re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,23 +104,30 @@ __global__ __launch_bounds__(256) void k_combo(const zc* const* tx, zc* const* t
 #pragma unroll
         for (int j = 0; j < CN; ++j) cfma(acc[j], Ws[m * CN + j], x);
     }
-    for (int j = 0; j < nn; ++j) {
-        zc* yp = ty[(size_t)z * NO + n0 + j] + k;
-        zc o = cscale(acc[j], alpha);
-        if (beta != 0.0) o = cadd(o, cscale(*yp, beta));
-        *yp = o;
+#pragma unroll
+    for (int j = 0; j < CN; ++j) {
+        if (j < nn) {
+            zc* yp = ty[(size_t)z * NO + n0 + j] + k;
+            zc o = cscale(acc[j], alpha);
+            if (beta != 0.0) o = cadd(o, cscale(*yp, beta));
+            *yp = o;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// batched dots d_v = sum_k conj(A_v[k]) B_v[k]; one block per vector
+// batched dots d_v = sum_k conj(A_v[k]) B_v[k], split over k chunks; partials
+// part[v][chunk] reduced in fixed order by k_dots_reduce
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dots(const zc* const* ta, const zc* const* tb, int64_t K, zc* out) {
-    const int v = blockIdx.x;
+__global__ __launch_bounds__(256) void k_dots(const zc* const* ta, const zc* const* tb, int64_t K, int64_t kchunk,
+                                              int nchunk, zc* part) {
+    const int v = blockIdx.y;
+    const int c = blockIdx.x;
     const zc* a = ta[v];
     const zc* b = tb[v];
+    const int64_t k0 = (int64_t)c * kchunk, k1 = min(K, k0 + kchunk);
     zc acc = mk<double>(0, 0);
-    for (int64_t k = threadIdx.x; k < K; k += 256) cfmac(acc, a[k], b[k]);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) cfmac(acc, a[k], b[k]);
     __shared__ zc red[256];
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -118,7 +135,24 @@ __global__ __launch_bounds__(256) void k_dots(const zc* const* ta, const zc* con
         if ((int)threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[v] = red[0];
+    if (threadIdx.x == 0) part[(size_t)v * nchunk + c] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_dots_reduce(const zc* part, int nchunk, int nvec, zc* out) {
+    const int v = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const int lane = threadIdx.x % 64;
+    if (v >= nvec) return;
+    double re = 0.0, im = 0.0;
+    for (int c = lane; c < nchunk; c += 64) {
+        zc x = part[(size_t)v * nchunk + c];
+        re += x.x;
+        im += x.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) out[v] = mk<double>(re, im);
 }
 
 // residual norms r_v = || h_v - theta_v s_v ||_2 and finiteness
@@ -206,9 +240,11 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     const size_t NN = (size_t)N * N;
     const zc* H = Hs + z * NN;
     const zc* S = Ss + z * NN;
-    zc* Lg = gwork + z * 3 * NN;  // global copy of L
-    zc* P1 = use_lds ? reinterpret_cast<zc*>(sm) : Lg + NN;
-    zc* P2 = use_lds ? P1 + NN : Lg + 2 * NN;
+    // three N x N work matrices: in LDS when they fit, else in global scratch
+    zc* W0 = use_lds ? reinterpret_cast<zc*>(sm) : gwork + z * 3 * NN;
+    zc* Lg = W0;            // Cholesky factor L
+    zc* P1 = W0 + NN;
+    zc* P2 = W0 + 2 * NN;
     const int tid = threadIdx.x;
     __shared__ int bad;
     __shared__ double s_off, s_norm;
@@ -314,7 +350,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         atomicAdd(&s_off, off);
         atomicAdd(&s_norm, nrm);
         __syncthreads();
-        if (s_off <= 1e-30 * s_norm || s_off == 0.0) break;
+        if (s_off <= 1e-28 * s_norm || s_off == 0.0) break;
         for (int r = 0; r < Np - 1; ++r) {
             for (int pi = tid; pi < npair; pi += NT) {
                 int p, q;
@@ -325,14 +361,14 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
                 if (q < N) {
                     zc apq = P1[(size_t)p * N + q];
                     double rabs = sqrt(apq.x * apq.x + apq.y * apq.y);
-                    if (rabs > 1e-300) {
-                        double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
+                    double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
+                    if (rabs > 1e-300 && rabs > 1e-18 * (fabs(app) + fabs(aqq))) {
                         double tau = (aqq - app) / (2.0 * rabs);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
-                        double s = t * c;
-                        sr = s * apq.x / rabs;  // s e^{i phi}
-                        si = s * apq.y / rabs;
+                        double sn = t * c;
+                        sr = sn * apq.x / rabs;  // s e^{i phi}
+                        si = sn * apq.y / rabs;
                     }
                 }
                 rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
@@ -342,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
             for (int e = tid; e < npair * N; e += NT) {
                 int pi = e / N, j = e % N;
                 int p = rp[pi], q = rq[pi];
-                if (q >= N) continue;
+                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
                 double c = rc[pi];
                 zc se = mk<double>(rsr[pi], rsi[pi]);
                 zc sec = mk<double>(rsr[pi], -rsi[pi]);
@@ -355,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
             for (int e = tid; e < npair * N; e += NT) {
                 int pi = e / N, i = e % N;
                 int p = rp[pi], q = rq[pi];
-                if (q >= N) continue;
+                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
                 double c = rc[pi];
                 zc se = mk<double>(rsr[pi], rsi[pi]);
                 zc sec = mk<double>(rsr[pi], -rsi[pi]);
@@ -466,8 +502,8 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
     int tiles_m = (MA + GT - 1) / GT, tiles_n = (NB + GT - 1) / GT;
     int ntiles = tiles_m * tiles_n * nz;
-    int64_t maxchunk = (K + 511) / 512;
-    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 2048 / std::max(1, ntiles)));
+    int64_t maxchunk = (K + 255) / 256;
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 1024 / std::max(1, ntiles)));
     size_t need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
     while (need > scratch_bytes && nchunk > 1) {
         nchunk /= 2;
@@ -483,7 +519,7 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
                        nchunk, tiles_n, (zc*)scratch);
     MB_HIP_TRY(hipGetLastError());
     size_t tot = (size_t)MA * NB * nz;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (const zc*)scratch,
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot * 64 + 255) / 256)), dim3(256), 0, s, (const zc*)scratch,
                        (zc*)out, MA, NB, nchunk, nz);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -502,10 +538,19 @@ mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int
     return MB_OK;
 }
 
-mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, hipStream_t s) {
+mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, void* scratch,
+                     hipStream_t s) {
     StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
-    hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, K, (zc*)out);
+    // about 1024 blocks in total, at least 4096 elements per block
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((K + 4095) / 4096, 1024 / nvec));
+    nchunk = std::min(nchunk, 64);
+    int64_t kchunk = (K + nchunk - 1) / nchunk;
+    hipLaunchKernelGGL(k_dots, dim3(nchunk, nvec), dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, K,
+                       kchunk, nchunk, (zc*)scratch);
+    MB_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_dots_reduce, dim3((nvec * 64 + 255) / 256), dim3(256), 0, s, (const zc*)scratch, nchunk,
+                       nvec, (zc*)out);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -551,12 +596,12 @@ mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed,
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
                        int* status, hipStream_t s) {
     if (N <= 0 || nz <= 0) return MB_OK;
-    size_t lds = 2 * (size_t)N * N * sizeof(zc);
-    int use_lds = lds <= 131072 ? 1 : 0;
+    size_t lds = 3 * (size_t)N * N * sizeof(zc);
+    int use_lds = lds <= 150000 ? 1 : 0;
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
     const size_t dyn = use_lds ? lds : 0;
     StageScope ts_(MB_STAGE_SMALLEIG, s);
-    if (N <= 48) {
+    if (N <= 12) {
         if (dyn > 65536)
             MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
         hipLaunchKernelGGL(k_geneig<64>, dim3(nz), dim3(64), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,

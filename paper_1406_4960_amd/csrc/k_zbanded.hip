@@ -17,7 +17,7 @@ namespace mb {
 namespace {
 
 constexpr int KORD = 4;
-constexpr int CH = 16;  // rows per thread in the combine kernel
+constexpr int CH = 8;  // rows per thread in the combine kernel
 
 template <typename TI, typename T>
 struct CombineArgs {
@@ -168,7 +168,7 @@ __device__ inline void band_solve(const cx<TI>* r, cx<TI>* x, const double* lf, 
 }
 
 template <typename TI>
-__global__ __launch_bounds__(256) void k_ssolve(const cx<TI>* r, cx<TI>* x, const double* lband, int nbands,
+__global__ __launch_bounds__(64) void k_ssolve(const cx<TI>* r, cx<TI>* x, const double* lband, int nbands,
                                                 int ng, int nb, int ld) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
@@ -208,7 +208,7 @@ __global__ void k_prec_factor(double* pf, const double* sband, const double* dba
     }
 }
 
-__global__ __launch_bounds__(256) void k_prec_apply(const cx<double>* h, const cx<double>* sv,
+__global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx<double>* sv,
                                                     const double* theta, const int32_t* sel, cx<double>* x,
                                                     const double* pf, int nvec, int ng, int nb, int ld) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -272,13 +272,13 @@ mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, in
 
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s) {
     const KPoint& kp = p->kp[ik];
-    dim3 grid((ld + 255) / 256, nbands);
+    dim3 grid((ld + 63) / 64, nbands);
     StageScope ts_(MB_STAGE_SSOLVE, s, nbands);
     if (prec == 1)
-        hipLaunchKernelGGL(k_ssolve<float>, grid, dim3(256), 0, s, (const cx<float>*)r, (cx<float>*)x,
+        hipLaunchKernelGGL(k_ssolve<float>, grid, dim3(64), 0, s, (const cx<float>*)r, (cx<float>*)x,
                            p->d_lband, nbands, kp.ng, p->nb, ld);
     else
-        hipLaunchKernelGGL(k_ssolve<double>, grid, dim3(256), 0, s, (const cx<double>*)r, (cx<double>*)x,
+        hipLaunchKernelGGL(k_ssolve<double>, grid, dim3(64), 0, s, (const cx<double>*)r, (cx<double>*)x,
                            p->d_lband, nbands, kp.ng, p->nb, ld);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -309,9 +309,9 @@ mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, c
                             const int32_t* sel, void* x, int nvec, int ld, hipStream_t s) {
     const KPoint& kp = p->kp[ik];
     if (!kp.d_pfac || ld != kp.ld) return set_error(MB_ERR_INVALID_ARG, "preconditioner not built for this ld");
-    dim3 grid((ld + 255) / 256, nvec);
+    dim3 grid((ld + 63) / 64, nvec);
     StageScope ts_(MB_STAGE_PRECOND, s, nvec);
-    hipLaunchKernelGGL(k_prec_apply, grid, dim3(256), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
+    hipLaunchKernelGGL(k_prec_apply, grid, dim3(64), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
                        sel, (cx<double>*)x, kp.d_pfac, nvec, kp.ng, p->nb, ld);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;

@@ -71,6 +71,9 @@ struct Solver {
     void** tQ;
     void** tHQ;
     void** tSQ;
+    // per Krylov depth j >= 1: block-batched Gram-Schmidt tables (see orthonormalise_k)
+    std::vector<void**> tGA, tGB, tGX, tGO;
+    void* dscratch;
     // small device arrays
     void* Hp;
     void* Sp;
@@ -135,7 +138,8 @@ struct Solver {
         return MB_OK;
     }
 
-    // S-orthonormalise Krylov slot j (nbl vectors) against X[0..M) and K[0..j)
+    // S-orthonormalise Krylov slot j (nbl vectors) against X[0..M) and, block by
+    // block, against the block's K[0..j): classical Gram-Schmidt, two passes
     mb_status orthonormalise_k(int j) {
         void** tKj = tK + (size_t)j * nbl;
         void** tSKj = tSK + (size_t)j * nbl;
@@ -146,14 +150,15 @@ struct Solver {
             LZ_TRY(dense_gram((const void* const*)tSX, (const void* const*)tKj, M, nbl, 1, K, coef, gscratch,
                               gscratch_bytes, s));
             LZ_TRY(dense_combo((const void* const*)tX, tKj, coef, M, nbl, 1, K, -1.0, 1.0, s));
-            // against the block's earlier Krylov vectors
-            for (int i = 0; i < j; ++i) {
-                LZ_TRY(dense_dots((const void* const*)(tSK + (size_t)i * nbl), (const void* const*)tKj, nbl, K, dots, s));
-                LZ_TRY(dense_axpy(tKj, (const void* const*)(tK + (size_t)i * nbl), dots, -1.0, nbl, K, s));
+            if (j > 0) {
+                // d[z*j + i] = <K_i^z|S|K_j^z>, then K_j^z -= sum_i d[z*j + i] K_i^z
+                LZ_TRY(dense_dots((const void* const*)tGA[j], (const void* const*)tGB[j], nbl * j, K, dots,
+                                  dscratch, s));
+                LZ_TRY(dense_combo((const void* const*)tGX[j], tGO[j], dots, j, 1, nbl, K, -1.0, 1.0, s));
             }
         }
         LZ_TRY(launch_spsi(p, ik, Kj, SKj, nbl, ld, 0, s));
-        LZ_TRY(dense_dots((const void* const*)tKj, (const void* const*)tSKj, nbl, K, dots, s));
+        LZ_TRY(dense_dots((const void* const*)tKj, (const void* const*)tSKj, nbl, K, dots, dscratch, s));
         LZ_TRY(dense_normalize(tKj, tSKj, dots, nbl, K, s));
         return MB_OK;
     }
@@ -206,11 +211,13 @@ struct Solver {
             int slot = M + j;
             for (int pass = 0; pass < 2; ++pass)
                 for (int i = 0; i < j; ++i) {
-                    LZ_TRY(dense_dots((const void* const*)(tSX + M + i), (const void* const*)(tX + slot), 1, K, dots, s));
+                    LZ_TRY(dense_dots((const void* const*)(tSX + M + i), (const void* const*)(tX + slot), 1, K, dots,
+                                      dscratch, s));
                     LZ_TRY(dense_axpy(tX + slot, (const void* const*)(tX + M + i), dots, -1.0, 1, K, s));
                 }
             LZ_TRY(launch_spsi(p, ik, vec(X, slot), vec(SX, slot), 1, ld, 0, s));
-            LZ_TRY(dense_dots((const void* const*)(tX + slot), (const void* const*)(tSX + slot), 1, K, dots, s));
+            LZ_TRY(dense_dots((const void* const*)(tX + slot), (const void* const*)(tSX + slot), 1, K, dots, dscratch,
+                              s));
             LZ_TRY(dense_normalize(tX + slot, tSX + slot, dots, 1, K, s));
             LZ_TRY(hop(vec(X, slot), vec(HX, slot), nullptr, 1, prec));
             if (j + 1 < mA)
@@ -265,11 +272,13 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
 
     // small workspace
     const size_t NN = std::max((size_t)S.NG * S.NG, (size_t)S.nbl * S.NR * S.NR);
-    const size_t ntab = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl + 3 * (size_t)S.nbl * S.NR;
+    const size_t ntab = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl + 3 * (size_t)S.nbl * S.NR +
+                        (size_t)S.nbl * (3 * (size_t)S.m * S.m / 2 + S.m + 1);
     S.gscratch_bytes = (size_t)32 << 20;
-    size_t small = ntab * sizeof(void*) + 3 * NN * 16 + (size_t)S.NG * S.M * 16 + 3 * NN * 16 +
-                   NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 + (size_t)S.nbl * 16 +
-                   (3 * (size_t)S.M + S.nbl + 64) * 8 + S.gscratch_bytes + 4096;
+    size_t small = ntab * sizeof(void*) + 3 * NN * 16 + (size_t)S.NG * S.M * 16 + (size_t)S.nbl * S.NR * S.b * 16 +
+                   3 * NN * 16 + NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 +
+                   (size_t)S.nbl * S.m * 16 + (size_t)64 * std::max(S.nbl * S.m, S.NG) * 16 +
+                   (3 * (size_t)S.M + S.NG + 2 * S.nbl + 64) * 8 + S.gscratch_bytes + 64 * 256;
     LZ_TRY(ensure_ws(p->ws_small, small));
     char* sb = (char*)p->ws_small.ptr;
     auto stake = [&](size_t bytes) {
@@ -295,6 +304,20 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
             for (int j = 0; j < S.m; ++j) htab.push_back(kb + (size_t)(j * S.nbl + z) * S.vbytes);
         }
     }
+    std::vector<size_t> oGA(S.m, 0), oGB(S.m, 0), oGX(S.m, 0), oGO(S.m, 0);
+    for (int j = 1; j < S.m; ++j) {
+        oGA[j] = htab.size();
+        for (int z = 0; z < S.nbl; ++z)
+            for (int i = 0; i < j; ++i) htab.push_back(S.SK + (size_t)(i * S.nbl + z) * S.vbytes);
+        oGB[j] = htab.size();
+        for (int z = 0; z < S.nbl; ++z)
+            for (int i = 0; i < j; ++i) htab.push_back(S.Kv + (size_t)(j * S.nbl + z) * S.vbytes);
+        oGX[j] = htab.size();
+        for (int z = 0; z < S.nbl; ++z)
+            for (int i = 0; i < j; ++i) htab.push_back(S.Kv + (size_t)(i * S.nbl + z) * S.vbytes);
+        oGO[j] = htab.size();
+        for (int z = 0; z < S.nbl; ++z) htab.push_back(S.Kv + (size_t)(j * S.nbl + z) * S.vbytes);
+    }
     void** dtab = (void**)stake(htab.size() * sizeof(void*));
     MB_HIP_TRY(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(void*), hipMemcpyHostToDevice, s));
     S.tX = dtab + oX; S.tHX = dtab + oHX; S.tSX = dtab + oSX;
@@ -302,6 +325,10 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.tK = dtab + oK; S.tHK = dtab + oHK; S.tSK = dtab + oSK;
     size_t qn = (size_t)S.nbl * S.NR;
     S.tQ = dtab + oQ; S.tHQ = dtab + oQ + qn; S.tSQ = dtab + oQ + 2 * qn;
+    S.tGA.assign(S.m, nullptr); S.tGB.assign(S.m, nullptr); S.tGX.assign(S.m, nullptr); S.tGO.assign(S.m, nullptr);
+    for (int j = 1; j < S.m; ++j) {
+        S.tGA[j] = dtab + oGA[j]; S.tGB[j] = dtab + oGB[j]; S.tGX[j] = dtab + oGX[j]; S.tGO[j] = dtab + oGO[j];
+    }
     S.Hp = stake(NN * 16);
     S.Sp = stake(NN * 16);
     S.Y = stake(NN * 16);
@@ -309,7 +336,8 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.gwork = stake(3 * NN * 16);
     S.evals = (double*)stake(NN * sizeof(double));
     S.coef = stake((size_t)S.M * std::max(S.nbl, S.NG) * 16);
-    S.dots = stake((size_t)std::max(S.nbl, 1) * 16);
+    S.dots = stake((size_t)std::max(S.nbl * S.m, 1) * 16);
+    S.dscratch = stake((size_t)64 * std::max(S.nbl * S.m, S.NG) * 16);
     S.theta = (double*)stake(S.NG * sizeof(double));
     S.theta_s = (double*)stake(S.nbl * sizeof(double));
     S.sel = (int32_t*)stake(S.nbl * sizeof(int32_t));
