@@ -12,6 +12,8 @@
 // potential in the mixed basis (Sec. II.B.1) with the in-plane transform taken
 // on the grid (circular convolution), applied without forming the matrix.
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "cplx.h"
 #include "mbks_internal.h"
@@ -337,6 +339,12 @@ __global__ void k_vgrid(double* V, float* Vf, const VTerm* terms, int nterms, in
 mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
                        hipStream_t s) {
     if (p->order != KORD) return set_error(MB_ERR_INVALID_ARG, "GPU kernels support order 4 only");
+    // line-per-thread kernel for small grids unless MBKS_LOCAL_KERNEL=generic
+    const char* sel = getenv("MBKS_LOCAL_KERNEL");
+    if (!sel || std::string(sel) != "generic") {
+        mb_status st = launch_local_lines(p, ik, c, part, nbands, ld, prec, s);
+        if (st != MB_ERR_INVALID_ARG) return st;
+    }
     if (prec == 0) return local_impl<double, double>(p, ik, c, part, nbands, ld, s);
     if (prec == 1) return local_impl<float, float>(p, ik, c, part, nbands, ld, s);
     return local_impl<double, float>(p, ik, c, part, nbands, ld, s);

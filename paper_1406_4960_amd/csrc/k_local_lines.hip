@@ -1,0 +1,384 @@
+// Local-potential part of H c for in-plane grids small enough that one thread
+// can hold a whole FFT line in registers (same operation as k_local.hip):
+//   evaluate psi(G, z_q) = sum_t B_{s-1+t}(z_q) c(G, s-1+t) for a group of Gauss
+//   planes of interval s, scatter, inverse 2D FFT, multiply by V(rho, z_q),
+//   forward 2D FFT, gather, project onto the kappa spline rows of interval s
+//   (local-potential matrix elements of Sec. II.B.1, taken on the grid).
+// Each workgroup owns one band and one knot interval and keeps a group of planes
+// in LDS (row stride N2 + 1).  Transforms run line by line: a thread loads a row
+// or a column, runs a compile-time mixed-radix Stockham FFT in registers and
+// stores it back, so a plane costs four passes through LDS instead of one per
+// radix stage.  The column pass fuses inverse FFT, V multiply and forward FFT.
+#include <cmath>
+
+#include "cplx.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+constexpr int KORD = 4;
+
+struct RadixPlan {
+    int nr;
+    int rad[12];
+};
+
+constexpr RadixPlan make_plan(int n) {
+    RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    const int order[4] = {4, 2, 3, 5};
+    for (int k = 0; k < 4; ++k)
+        while (n % order[k] == 0) {
+            p.rad[p.nr++] = order[k];
+            n /= order[k];
+        }
+    return p;
+}
+
+template <int N>
+struct LinePlan {
+    static constexpr RadixPlan p = make_plan(N);
+};
+
+// y_k = sum_r v_r exp(sign 2 pi i r k / R), R in {2, 3, 4, 5}
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void bfly(cx<T>* v) {
+    constexpr T s = (T)SIGN;
+    if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        cx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        cx<T> t2 = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        cx<T> t3 = mk<T>(-s * d.y, s * d.x);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    } else if constexpr (R == 3) {
+        const T c3 = (T)-0.5;
+        const T s3 = (T)0.86602540378443864676;
+        cx<T> t = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        cx<T> a = mk<T>(v[0].x + c3 * t.x, v[0].y + c3 * t.y);
+        const T ss = s * s3;
+        cx<T> b = mk<T>(-ss * d.y, ss * d.x);
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(a, b);
+        v[2] = csub(a, b);
+    } else {
+        const T c1 = (T)0.30901699437494742410;
+        const T c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212;
+        const T s2 = (T)0.58778525229247312917;
+        cx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        cx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        cx<T> a1 = mk<T>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        cx<T> a2 = mk<T>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        cx<T> e1 = mk<T>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+        cx<T> e2 = mk<T>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+        cx<T> b1 = mk<T>(-s * e1.y, s * e1.x);
+        cx<T> b2 = mk<T>(-s * e2.y, s * e2.x);
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+}
+
+// One Stockham stage in registers: in -> out, span NS so far, radix R.
+// tw[m] = exp(+2 pi i m / N) in LDS (read with constant offsets).
+template <typename T, int N, int NS, int R, int SIGN>
+__device__ __forceinline__ void line_stage(const cx<T>* in, cx<T>* out, const cx<T>* tw) {
+    constexpr int NBF = N / R;
+    constexpr int TS = N / (NS * R);
+#pragma unroll
+    for (int j = 0; j < NBF; ++j) {
+        const int k = j % NS;
+        cx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * NBF];
+        if (k != 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> w = tw[r * k * TS];
+                if (SIGN < 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+        bfly<T, R, SIGN>(v);
+        const int o = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[o + r * NS] = v[r];
+    }
+}
+
+template <typename T, int N, int S, int NS, int SIGN>
+__device__ __forceinline__ void line_fft_rec(cx<T>* a, cx<T>* b, const cx<T>* tw) {
+    constexpr RadixPlan P = LinePlan<N>::p;
+    if constexpr (S < P.nr) {
+        constexpr int R = P.rad[S];
+        line_stage<T, N, NS, R, SIGN>(a, b, tw);
+        line_fft_rec<T, N, S + 1, NS * R, SIGN>(b, a, tw);
+    }
+}
+
+// in-place transform of v[N] (result back in v)
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void line_fft(cx<T>* v, const cx<T>* tw) {
+    cx<T> tmp[N];
+    line_fft_rec<T, N, 0, 1, SIGN>(v, tmp, tw);
+    constexpr RadixPlan P = LinePlan<N>::p;
+    if constexpr (P.nr % 2 == 1) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) v[e] = tmp[e];
+    }
+}
+
+template <typename TI, typename T>
+struct LineArgs {
+    const cx<TI>* c;
+    cx<T>* part;
+    const T* bval;
+    const T* wbval;
+    const T* V;
+    const int32_t* gmap;
+    const int32_t* rows;
+    const cx<T>* tw1;
+    const cx<T>* tw2;
+    int nbands, ld, ng, nint, nq, nb, nrows, qp;
+    T inv_n;
+};
+
+template <typename TI, typename T, int N1, int N2, int NT, int MAXG>
+__global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a) {
+    constexpr int P2 = N2 + 1;          // padded row stride
+    constexpr int PLANE = N1 * P2;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* tw1 = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* tw2 = tw1 + N1;
+    int32_t* rows = reinterpret_cast<int32_t*>(tw2 + N2);
+    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256);
+
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int b = (int)(L % (unsigned)a.nbands);
+    const int s = (int)(L / (unsigned)a.nbands);
+    if (s >= a.nint) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
+    for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
+    for (int e = tid; e < a.nrows; e += NT) rows[e] = a.rows[e];
+
+    const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
+    cx<T> acc[KORD][MAXG];
+#pragma unroll
+    for (int t = 0; t < KORD; ++t)
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) acc[t][k] = mk<T>(0, 0);
+
+    for (int q0 = 0; q0 < a.nq; q0 += a.qp) {
+        const int np = min(a.qp, a.nq - q0);
+        // zero the planes of this group
+        for (int e = tid; e < np * PLANE; e += NT) grid[e] = mk<T>(0, 0);
+        __syncthreads();
+        // evaluate and scatter: c rows s-1 .. s+2 read once for all planes of the group
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) {
+            const int g = tid + k * NT;
+            if (g < a.ng) {
+                cx<T> cv[KORD];
+#pragma unroll
+                for (int t = 0; t < KORD; ++t) {
+                    const int row = s - 1 + t;
+                    if (row >= 0 && row < a.nb) {
+                        cx<TI> v = cb[(size_t)row * a.ld + g];
+                        cv[t] = mk<T>((T)v.x, (T)v.y);
+                    } else {
+                        cv[t] = mk<T>(0, 0);
+                    }
+                }
+                const int gm = a.gmap[g];
+                const int off = (gm / N2) * P2 + (gm % N2);
+                for (int jq = 0; jq < np; ++jq) {
+                    const T* bv = a.bval + (size_t)(s * a.nq + q0 + jq) * KORD;
+                    cx<T> psi = mk<T>(0, 0);
+#pragma unroll
+                    for (int t = 0; t < KORD; ++t) {
+                        psi.x = fma(bv[t], cv[t].x, psi.x);
+                        psi.y = fma(bv[t], cv[t].y, psi.y);
+                    }
+                    grid[jq * PLANE + off] = psi;
+                }
+            }
+        }
+        __syncthreads();
+        // inverse transform along rows that hold G
+        for (int line = tid; line < np * a.nrows; line += NT) {
+            const int jq = line / a.nrows;
+            cx<T>* base = grid + jq * PLANE + rows[line - jq * a.nrows] * P2;
+            cx<T> v[N2];
+#pragma unroll
+            for (int e = 0; e < N2; ++e) v[e] = base[e];
+            line_fft<T, N2, +1>(v, tw2);
+#pragma unroll
+            for (int e = 0; e < N2; ++e) base[e] = v[e];
+        }
+        __syncthreads();
+        // columns: inverse FFT, multiply by V(rho, z_q), forward FFT
+        for (int line = tid; line < np * N2; line += NT) {
+            const int jq = line / N2;
+            const int j2 = line - jq * N2;
+            cx<T>* base = grid + jq * PLANE + j2;
+            const T* Vq = a.V + (size_t)(s * a.nq + q0 + jq) * (N1 * N2) + j2;
+            cx<T> v[N1];
+#pragma unroll
+            for (int e = 0; e < N1; ++e) v[e] = base[e * P2];
+            line_fft<T, N1, +1>(v, tw1);
+#pragma unroll
+            for (int e = 0; e < N1; ++e) {
+                const T w = Vq[e * N2];
+                v[e] = mk<T>(v[e].x * w, v[e].y * w);
+            }
+            line_fft<T, N1, -1>(v, tw1);
+#pragma unroll
+            for (int e = 0; e < N1; ++e) base[e * P2] = v[e];
+        }
+        __syncthreads();
+        // forward transform along rows that hold G
+        for (int line = tid; line < np * a.nrows; line += NT) {
+            const int jq = line / a.nrows;
+            cx<T>* base = grid + jq * PLANE + rows[line - jq * a.nrows] * P2;
+            cx<T> v[N2];
+#pragma unroll
+            for (int e = 0; e < N2; ++e) v[e] = base[e];
+            line_fft<T, N2, -1>(v, tw2);
+#pragma unroll
+            for (int e = 0; e < N2; ++e) base[e] = v[e];
+        }
+        __syncthreads();
+        // gather and project onto the kappa rows of the interval
+#pragma unroll
+        for (int k = 0; k < MAXG; ++k) {
+            const int g = tid + k * NT;
+            if (g < a.ng) {
+                const int gm = a.gmap[g];
+                const int off = (gm / N2) * P2 + (gm % N2);
+                for (int jq = 0; jq < np; ++jq) {
+                    const cx<T> u = grid[jq * PLANE + off];
+                    const T* wb = a.wbval + (size_t)(s * a.nq + q0 + jq) * KORD;
+#pragma unroll
+                    for (int t = 0; t < KORD; ++t) {
+                        const T w = wb[t] * a.inv_n;
+                        acc[t][k].x = fma(w, u.x, acc[t][k].x);
+                        acc[t][k].y = fma(w, u.y, acc[t][k].y);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    cx<T>* pb = a.part + ((size_t)b * a.nint + s) * KORD * a.ld;
+#pragma unroll
+    for (int k = 0; k < MAXG; ++k) {
+        const int g = tid + k * NT;
+        if (g < a.ng) {
+#pragma unroll
+            for (int t = 0; t < KORD; ++t) pb[(size_t)t * a.ld + g] = acc[t][k];
+        }
+    }
+}
+
+template <typename TI, typename T, int N1, int N2, int NT, int MAXG>
+mb_status run_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s, int qp,
+                    size_t lds) {
+    const KPoint& kp = p->kp[ik];
+    const bool dbl = sizeof(T) == 8;
+    LineArgs<TI, T> a;
+    a.c = (const cx<TI>*)c;
+    a.part = (cx<T>*)part;
+    a.bval = (const T*)(dbl ? (const void*)p->d_bval : (const void*)p->d_bvalf);
+    a.wbval = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
+    a.V = (const T*)(dbl ? (const void*)p->d_V : (const void*)p->d_Vf);
+    a.gmap = kp.d_gmap;
+    a.rows = kp.d_rows;
+    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
+    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
+    a.nbands = nbands;
+    a.ld = ld;
+    a.ng = kp.ng;
+    a.nint = p->nint;
+    a.nq = p->nq;
+    a.nb = p->nb;
+    a.nrows = (int)kp.rows.size();
+    a.qp = qp;
+    a.inv_n = (T)(1.0 / ((double)N1 * N2));
+    auto kern = k_local_lines<TI, T, N1, N2, NT, MAXG>;
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    unsigned nblocks = (unsigned)nbands * (unsigned)p->nint;
+    StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, nbands);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+// planes per group: all Gauss planes of an interval when they fit in `budget` bytes of LDS
+template <typename TI, typename T, int N1, int N2>
+mb_status lines_dispatch(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s,
+                         size_t budget) {
+    const size_t hdr = ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256;
+    const size_t plane = sizeof(cx<T>) * (size_t)N1 * (N2 + 1);
+    int qp = p->nq;
+    while (qp > 1 && hdr + qp * plane > budget) --qp;
+    const size_t lds = hdr + qp * plane;
+    if (lds > 163840) return MB_ERR_INVALID_ARG;
+    // accumulator slots for G sets up to half the grid; larger sets use the generic kernel
+    constexpr int MAXG = (N1 * N2 / 2 + 255) / 256;
+    if (p->kp[ik].ng > 256 * MAXG) return MB_ERR_INVALID_ARG;
+    return run_lines<TI, T, N1, N2, 256, MAXG>(p, ik, c, part, nbands, ld, s, qp, lds);
+}
+
+template <typename TI, typename T>
+mb_status lines_by_size(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
+    if (p->N1 != p->N2) return MB_ERR_INVALID_ARG;
+    const size_t budget = 110 * 1024;
+    switch (p->N1) {
+        case 16: return lines_dispatch<TI, T, 16, 16>(p, ik, c, part, nbands, ld, s, budget);
+        case 24: return lines_dispatch<TI, T, 24, 24>(p, ik, c, part, nbands, ld, s, budget);
+        case 25: return lines_dispatch<TI, T, 25, 25>(p, ik, c, part, nbands, ld, s, budget);
+        case 27: return lines_dispatch<TI, T, 27, 27>(p, ik, c, part, nbands, ld, s, budget);
+        case 30: return lines_dispatch<TI, T, 30, 30>(p, ik, c, part, nbands, ld, s, budget);
+        case 32: return lines_dispatch<TI, T, 32, 32>(p, ik, c, part, nbands, ld, s, budget);
+        case 36: return lines_dispatch<TI, T, 36, 36>(p, ik, c, part, nbands, ld, s, budget);
+        case 40: return lines_dispatch<TI, T, 40, 40>(p, ik, c, part, nbands, ld, s, budget);
+        default: break;
+    }
+    if constexpr (sizeof(T) == 4) {
+        switch (p->N1) {
+            case 45: return lines_dispatch<TI, T, 45, 45>(p, ik, c, part, nbands, ld, s, budget);
+            case 48: return lines_dispatch<TI, T, 48, 48>(p, ik, c, part, nbands, ld, s, budget);
+            case 50: return lines_dispatch<TI, T, 50, 50>(p, ik, c, part, nbands, ld, s, budget);
+            case 54: return lines_dispatch<TI, T, 54, 54>(p, ik, c, part, nbands, ld, s, budget);
+            case 60: return lines_dispatch<TI, T, 60, 60>(p, ik, c, part, nbands, ld, s, budget);
+            case 64: return lines_dispatch<TI, T, 64, 64>(p, ik, c, part, nbands, ld, s, budget);
+            default: break;
+        }
+    }
+    return MB_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+// Returns MB_OK if a line kernel handled the grid, MB_ERR_INVALID_ARG if the grid
+// has no line kernel (the caller then uses the generic one).
+mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
+                             hipStream_t s) {
+    if (p->order != KORD) return MB_ERR_INVALID_ARG;
+    if (prec == 0) return lines_by_size<double, double>(p, ik, c, part, nbands, ld, s);
+    if (prec == 1) return lines_by_size<float, float>(p, ik, c, part, nbands, ld, s);
+    return lines_by_size<double, float>(p, ik, c, part, nbands, ld, s);
+}
+
+}  // namespace mb

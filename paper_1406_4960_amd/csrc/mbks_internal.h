@@ -133,6 +133,9 @@ mb_status ensure_ws(Workspace& w, size_t bytes);
 mb_status launch_vgrid(Problem* p, hipStream_t s);
 mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
                        int prec, hipStream_t s);
+// line-per-thread variant for small grids; MB_ERR_INVALID_ARG = no variant for this grid
+mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
+                             int prec, hipStream_t s);
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
                             int prec, hipStream_t s);
 // y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null

@@ -150,3 +150,19 @@ def test_zero_bands_and_bad_args():
         bad = torch.zeros((2, dm["nb"], dm["ng"] - 1), dtype=torch.complex128, device=DEV)
         p.hpsi(0, bad, bad.clone())  # ld < N_G
     p.close()
+
+
+@pytest.mark.parametrize("cfg,prec", [("graphene", "fp64"), ("graphene", "fp32"), ("tiny", "fp64")])
+def test_line_kernel_matches_generic_kernel(cfg, prec, monkeypatch):
+    # the line-per-thread local kernel and the generic LDS-stage kernel compute the
+    # same operator; both are separately checked against the oracle above
+    d = workloads.CONFIGS[cfg]()
+    p, dm, _ = _setup(d, 0)
+    x = random_lib_block(31, 6, dm["nb"], dm["ng"], dm["ld"])
+    y_lines = _run(p, "hpsi", 0, x, prec)
+    monkeypatch.setenv("MBKS_LOCAL_KERNEL", "generic")
+    y_gen = _run(p, "hpsi", 0, x, prec)
+    monkeypatch.delenv("MBKS_LOCAL_KERNEL")
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_err(y_lines, y_gen) < tol
+    p.close()
