@@ -105,6 +105,13 @@ typedef struct {
 
 typedef struct mb_problem mb_problem;
 
+/* Initialise the HIP runtime this library links and report the number of GPUs it
+ * sees (0 on a machine without one; not an error).  Optional: GPU entry points
+ * initialise on first use.  A process that also loads another HIP runtime (for
+ * example a framework's bundled copy) should call it right after loading the
+ * library, before the other runtime initialises. */
+mb_status mb_init(int* ndevices);
+
 /* Build every table of the problem on the host (knots, Gauss rule, B-spline
  * values, banded S_z / D_z and the Cholesky factor of S_z, G sets, grid maps,
  * projector factors) and upload them to `device`, where the local potential is
@@ -197,6 +204,19 @@ void mb_lanczos_default_opts(mb_lanczos_opts* opts);
 mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
                          const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
                          mb_lanczos_info* info, void* stream);
+
+/* The projected-eigenproblem step of lanczos_lowest on its own (Rayleigh-Ritz with
+ * the Jacobi method, Sec. II.C): nz independent generalized Hermitian problems
+ * H y = theta S y of size N (1..256), H and S row-major N x N complex128 each
+ * (2*N*N doubles, interleaved re/im), S positive definite.  S = L L^H is reduced
+ * by a Cholesky factor, A = L^{-1} H L^{-H} is diagonalised by cyclic Jacobi
+ * sweeps with the round-robin parallel ordering, Y = L^{-H} V.  Outputs: evals
+ * (nz x N, ascending per problem), Y (nz x N x N complex128, column j = vector of
+ * evals[j], Y^H S Y = I), sweeps (nz ints, may be NULL).  Host buffers; allocates
+ * device memory internally and synchronises `stream`.  Directions of S that are
+ * numerically dependent are deflated to theta = 1e30. */
+mb_status mb_small_geneig(const double* H, const double* S, int N, int nz, double* evals, double* Y,
+                          int* sweeps, void* stream);
 
 /* Stage timer for measurement runs: while enabled, every kernel launch of the
  * library is bracketed by HIP events recorded on the stream it is launched on.

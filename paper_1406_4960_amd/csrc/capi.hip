@@ -217,6 +217,16 @@ extern "C" {
 
 const char* mb_last_error(void) { return mb::g_last_error.c_str(); }
 
+mb_status mb_init(int* ndevices) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        n = 0;
+    }
+    if (ndevices) *ndevices = n;
+    return MB_OK;
+}
+
 mb_status mb_timer_enable(int on) {
     mb::timer_clear();
     mb::g_timer.on = on != 0;

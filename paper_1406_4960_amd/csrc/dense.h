@@ -22,7 +22,7 @@ mb_status dense_normalize(void* const* t1, void* const* t2, const void* d, int n
 mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed, hipStream_t s);
 // nz problems of size N: H, S, Y row-major N x N each, evals N each; gwork 3 N^2 complex per problem
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
-                       int* status, hipStream_t s);
+                       int* status, hipStream_t s, int* sweeps = nullptr);
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
                        hipStream_t s);
 mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* out, hipStream_t s);

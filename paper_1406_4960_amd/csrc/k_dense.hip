@@ -4,6 +4,8 @@
 // cyclic Jacobi method.  Vectors are addressed through device tables of
 // pointers so one launch serves every block of the block cycle.
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "cplx.h"
 #include "dense.h"
@@ -234,10 +236,11 @@ __device__ inline int rr_pair(int r, int k, int Np) {
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
-                                               zc* gwork, int use_lds, int max_sweeps, int* status) {
+                                               zc* gwork, int use_lds, int max_sweeps, int* status, int* sweeps_out) {
     extern __shared__ unsigned char sm[];
     const int z = blockIdx.x;
     const size_t NN = (size_t)N * N;
+    const int NNi = N * N;  // 32-bit element index: no 64-bit division in the loops
     const zc* H = Hs + z * NN;
     const zc* S = Ss + z * NN;
     // three N x N work matrices: in LDS when they fit, else in global scratch
@@ -250,10 +253,10 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     __shared__ double s_off, s_norm;
     __shared__ unsigned char dead[256];  // directions numerically in the span of earlier ones
     if (tid == 0) bad = 0;
-    // 1. Cholesky of S in P1; a pivot that lost all but 1e-13 of its diagonal marks a
+    // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
     //    dependent direction: it is taken out of the reduction (unit pivot, zero column)
     //    and later pinned at the top of the spectrum so it is never selected
-    for (size_t e = tid; e < NN; e += NT) P1[e] = S[e];
+    for (int e = tid; e < NNi; e += NT) P1[e] = S[e];
     __syncthreads();
     for (int j = 0; j < N; ++j) {
         if (tid == 0) {
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
             if (!isfinite(d) || !isfinite(d0)) {
                 bad = 2;
                 d = 1.0;
-            } else if (!(d > 1e-13 * d0) || !(d0 > 0.0)) {
+            } else if (!(d > 1e-8 * d0) || !(d0 > 0.0)) {
                 dead[j] = 1;
                 d = 1.0;
             }
@@ -285,16 +288,17 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         }
         __syncthreads();
     }
-    for (size_t e = tid; e < NN; e += NT) {
+    for (int e = tid; e < NNi; e += NT) {
         int i = (int)(e / N), k = (int)(e % N);
         Lg[e] = (k <= i) ? P1[e] : mk<double>(0, 0);
     }
     // 2. B = L^{-1} H in P2 (column-wise forward substitution)
-    for (size_t e = tid; e < NN; e += NT) P2[e] = H[e];
+    for (int e = tid; e < NNi; e += NT) P2[e] = H[e];
     __syncthreads();
     for (int col = tid; col < N; col += NT) {
         for (int i = 0; i < N; ++i) {
             zc v = P2[(size_t)i * N + col];
+#pragma unroll 8
             for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P2[(size_t)k * N + col]));
             P2[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
         }
@@ -305,13 +309,14 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         for (int i = 0; i < N; ++i) {
             zc b = P2[(size_t)col * N + i];
             zc v = mk<double>(b.x, -b.y);
+#pragma unroll 8
             for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P1[(size_t)k * N + col]));
             P1[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
         }
     }
     __syncthreads();
     // 4. Hermitian part of A; V = I
-    for (size_t e = tid; e < NN; e += NT) {
+    for (int e = tid; e < NNi; e += NT) {
         int i = (int)(e / N), k = (int)(e % N);
         if (k < i) {
             zc a = P1[(size_t)i * N + k], b = P1[(size_t)k * N + i];
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         P2[e] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    for (size_t e = tid; e < NN; e += NT) {
+    for (int e = tid; e < NNi; e += NT) {
         int i = (int)(e / N), k = (int)(e % N);
         if (dead[i] || dead[k]) P1[e] = mk<double>(i == k ? 1e30 : 0.0, 0.0);
     }
@@ -335,102 +340,132 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     __shared__ double rc[128], rsr[128], rsi[128];  // c, s e^{i phi} per pair (npair <= 128 in LDS mode)
     __shared__ int rp[128], rq[128];
     double* gc = nullptr;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        // off-diagonal norm
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        // off-diagonal norm: per-thread partials, wave shuffle tree, one atomic per wave
         if (tid == 0) { s_off = 0.0; s_norm = 0.0; }
         __syncthreads();
         double off = 0.0, nrm = 0.0;
-        for (size_t e = tid; e < NN; e += NT) {
+        for (int e = tid; e < NNi; e += NT) {
             int i = (int)(e / N), k = (int)(e % N);
+            if (dead[i] || dead[k]) continue;  // deflated directions are already decoupled
             zc a = P1[e];
             double m2 = a.x * a.x + a.y * a.y;
             nrm += m2;
             if (i != k) off += m2;
         }
-        atomicAdd(&s_off, off);
-        atomicAdd(&s_norm, nrm);
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_down(off, o, 64);
+            nrm += __shfl_down(nrm, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&s_off, off);
+            atomicAdd(&s_norm, nrm);
+        }
         __syncthreads();
         if (s_off <= 1e-28 * s_norm || s_off == 0.0) break;
+        const int wave = tid / 64, lane = tid % 64, nwave = NT / 64;
         for (int r = 0; r < Np - 1; ++r) {
-            for (int pi = tid; pi < npair; pi += NT) {
+            // rows: one wave per pair.  The wave reads its pair's pivots a_pp, a_qq,
+            // a_pq (rows p and q are touched by no other pair this round), derives
+            // the rotation, then its lanes rotate the two rows:
+            //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
+            for (int pi = wave; pi < npair; pi += nwave) {
                 int p, q;
                 if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
                 else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
                 if (p > q) { int t = p; p = q; q = t; }
                 double c = 1.0, sr = 0.0, si = 0.0;
                 if (q < N) {
-                    zc apq = P1[(size_t)p * N + q];
-                    double rabs = sqrt(apq.x * apq.x + apq.y * apq.y);
-                    double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
-                    if (rabs > 1e-300 && rabs > 1e-18 * (fabs(app) + fabs(aqq))) {
-                        double tau = (aqq - app) / (2.0 * rabs);
-                        double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        double sn = t * c;
-                        sr = sn * apq.x / rabs;  // s e^{i phi}
-                        si = sn * apq.y / rabs;
+                    const zc apq = P1[(size_t)p * N + q];
+                    const double r2 = apq.x * apq.x + apq.y * apq.y;
+                    const double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
+                    const double scale = fabs(app) + fabs(aqq);
+                    if (r2 > 1e-300 && r2 > 1e-36 * scale * scale) {
+                        // tan of the rotation angle: t = 2|a_pq| sgn(d) / (|d| + sqrt(d^2 + 4|a_pq|^2)),
+                        // d = a_qq - a_pp; c = 1/sqrt(1 + t^2); phase a_pq / |a_pq|
+                        const double d = aqq - app;
+                        const double inv_r = rsqrt(r2);
+                        const double rabs = r2 * inv_r;
+                        const double t = (d >= 0 ? 2.0 : -2.0) * rabs / (fabs(d) + sqrt(d * d + 4.0 * r2));
+                        c = rsqrt(1.0 + t * t);
+                        const double sn = t * c * inv_r;
+                        sr = sn * apq.x;  // s e^{i phi}
+                        si = sn * apq.y;
                     }
                 }
-                rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
+                // every lane of the wave holds the pivots in registers before any lane writes
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) { rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q; }
+                if (q < N && (sr != 0.0 || si != 0.0)) {
+                    const zc se = mk<double>(sr, si);
+                    const zc sec = mk<double>(sr, -si);
+                    for (int j = lane; j < N; j += 64) {
+                        zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
+                        P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
+                        P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
+                    }
+                }
             }
             __syncthreads();
-            // rows: a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
-            for (int e = tid; e < npair * N; e += NT) {
-                int pi = e / N, j = e % N;
-                int p = rp[pi], q = rq[pi];
+            // columns of A and V, one wave per pair:
+            //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
+            for (int pi = wave; pi < npair; pi += nwave) {
+                const int p = rp[pi], q = rq[pi];
                 if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                double c = rc[pi];
-                zc se = mk<double>(rsr[pi], rsi[pi]);
-                zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
-                P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
-                P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
-            }
-            __syncthreads();
-            // columns of A and V: a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
-            for (int e = tid; e < npair * N; e += NT) {
-                int pi = e / N, i = e % N;
-                int p = rp[pi], q = rq[pi];
-                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                double c = rc[pi];
-                zc se = mk<double>(rsr[pi], rsi[pi]);
-                zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
-                P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
-                P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
-                zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
-                P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
-                P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+                const double c = rc[pi];
+                const zc se = mk<double>(rsr[pi], rsi[pi]);
+                const zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                for (int i = lane; i < N; i += 64) {
+                    zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
+                    P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
+                    P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
+                    zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
+                    P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
+                    P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+                }
             }
             __syncthreads();
         }
     }
     (void)gc;
-    // 6. order and back-transform: column rank(j) of Y = L^{-H} V[:, j]
-    double* ev = evals + (size_t)z * N;
-    zc* Y = Ys + z * NN;
+    // 6. order and back-transform in LDS: Yl = L^{-H} V (into P1 once the eigenvalues
+    //    are saved), then column j of Yl goes to column rank(j) of Y
+    __shared__ double evs[256];
+    __shared__ int rk[256];
+    for (int j = tid; j < N; j += NT) evs[j] = P1[(size_t)j * N + j].x;
+    __syncthreads();
     for (int j = tid; j < N; j += NT) {
-        double dj = P1[(size_t)j * N + j].x;
+        const double dj = evs[j];
         int rank = 0;
         for (int i = 0; i < N; ++i) {
-            double di = P1[(size_t)i * N + i].x;
+            const double di = evs[i];
             if (di < dj || (di == dj && i < j)) ++rank;
         }
-        ev[rank] = dj;
+        rk[j] = rank;
         if (!isfinite(dj)) bad = 2;
-        // L^H y = v, back substitution
+        // L^H y = v, back substitution down the column
         for (int i = N - 1; i >= 0; --i) {
             zc v = P2[(size_t)i * N + j];
+#pragma unroll 8
             for (int k = i + 1; k < N; ++k) {
-                zc l = Lg[(size_t)k * N + i];
-                zc yk = Y[(size_t)k * N + rank];
+                const zc l = Lg[(size_t)k * N + i];
+                const zc yk = P1[(size_t)k * N + j];
                 v = csub(v, mk<double>(l.x * yk.x + l.y * yk.y, l.x * yk.y - l.y * yk.x));  // conj(l) yk
             }
-            Y[(size_t)i * N + rank] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+            P1[(size_t)i * N + j] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
         }
     }
     __syncthreads();
+    double* ev = evals + (size_t)z * N;
+    zc* Y = Ys + z * NN;
+    for (int j = tid; j < N; j += NT) ev[rk[j]] = evs[j];
+    for (int e = tid; e < NNi; e += NT) {
+        const int i = (int)(e / N), j = (int)(e % N);
+        Y[(size_t)i * N + rk[j]] = P1[e];
+    }
     if (tid == 0 && bad) atomicMax(status, bad);
+    if (tid == 0 && sweeps_out) sweeps_out[z] = sweep;
 }
 
 // ---------------------------------------------------------------------------
@@ -594,23 +629,30 @@ mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed,
 }
 
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
-                       int* status, hipStream_t s) {
+                       int* status, hipStream_t s, int* sweeps) {
     if (N <= 0 || nz <= 0) return MB_OK;
     size_t lds = 3 * (size_t)N * N * sizeof(zc);
     int use_lds = lds <= 150000 ? 1 : 0;
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
     const size_t dyn = use_lds ? lds : 0;
     StageScope ts_(MB_STAGE_SMALLEIG, s);
-    if (N <= 12) {
-        if (dyn > 65536)
-            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_geneig<64>, dim3(nz), dim3(64), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, use_lds, 60, status);
-    } else {
+    int nt = N <= 12 ? 64 : 1024;
+    if (const char* e = getenv("MBKS_GENEIG_NT")) nt = atoi(e);
+    if (nt == 256) {
         if (dyn > 65536)
             MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
         hipLaunchKernelGGL(k_geneig<256>, dim3(nz), dim3(256), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, use_lds, 60, status);
+                           (zc*)gwork, use_lds, 60, status, sweeps);
+    } else if (nt == 64) {
+        if (dyn > 65536)
+            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_geneig<64>, dim3(nz), dim3(64), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
+                           (zc*)gwork, use_lds, 60, status, sweeps);
+    } else {
+        if (dyn > 65536)
+            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(k_geneig<1024>, dim3(nz), dim3(1024), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
+                           (zc*)gwork, use_lds, 60, status, sweeps);
     }
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -636,3 +678,60 @@ mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* ou
 }
 
 }  // namespace mb
+
+extern "C" mb_status mb_small_geneig(const double* H, const double* S, int N, int nz, double* evals, double* Y,
+                                     int* sweeps, void* stream) {
+    using namespace mb;
+    if (!H || !S || !evals || !Y || N < 1 || N > 256 || nz < 1 || nz > 4096)
+        return set_error(MB_ERR_INVALID_ARG, "mb_small_geneig: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nn = (size_t)N * N * nz;
+    void *dH = nullptr, *dS = nullptr, *dY = nullptr, *dW = nullptr;
+    double* dE = nullptr;
+    int *dst = nullptr, *dsw = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(dH); (void)hipFree(dS); (void)hipFree(dY); (void)hipFree(dW);
+        (void)hipFree(dE); (void)hipFree(dst); (void)hipFree(dsw);
+    };
+    {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+            (void)hipGetLastError();
+            return set_error(MB_ERR_NO_DEVICE, "mb_small_geneig: no GPU");
+        }
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        (void)hipSetDevice(dev);
+        (void)hipGetLastError();
+    }
+    void** bufs[] = {&dH, &dS, &dY, &dW, (void**)&dE, (void**)&dst, (void**)&dsw};
+    const size_t sizes[] = {nn * 16, nn * 16, nn * 16, 3 * nn * 16, (size_t)N * nz * 8, 64, (size_t)nz * 4 + 64};
+    for (int k = 0; k < 7; ++k) {
+        hipError_t e = hipMalloc(bufs[k], sizes[k]);
+        if (e != hipSuccess) {
+            cleanup();
+            return set_error(MB_ERR_OOM, std::string("mb_small_geneig: hipMalloc: ") + hipGetErrorString(e));
+        }
+    }
+    mb_status st = MB_OK;
+    int status = 0;
+    if (hipMemcpy(dH, H, nn * 16, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dS, S, nn * 16, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(dst, 0, 4) != hipSuccess) {
+        cleanup();
+        return set_error(MB_ERR_HIP, "mb_small_geneig: upload failed");
+    }
+    st = dense_geneig(dH, dS, N, nz, dE, dY, dW, dst, s, dsw);
+    if (st == MB_OK) {
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipMemcpy(evals, dE, (size_t)N * nz * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(Y, dY, nn * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&status, dst, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            (sweeps && hipMemcpy(sweeps, dsw, (size_t)nz * 4, hipMemcpyDeviceToHost) != hipSuccess))
+            st = set_error(MB_ERR_HIP, "mb_small_geneig: download failed");
+        else if (status)
+            st = set_error(MB_ERR_NONFINITE, "mb_small_geneig: non-finite input or result");
+    }
+    cleanup();
+    return st;
+}

@@ -23,10 +23,10 @@ STATUS = {0: "MB_OK", -1: "MB_ERR_INVALID_ARG", -2: "MB_ERR_NOT_SPD", -3: "MB_ER
 MB_MAX_GAUSS = 4
 
 # every symbol the C header declares
-EXPORTS = ("mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
+EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
            "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
-           "mb_timer_enable", "mb_timer_read", "mb_last_error")
+           "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
 class MbError(RuntimeError):
@@ -73,8 +73,17 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libmbks.so not found at {path}; run `python -m paper_1406_4960_amd.build`")
+    # torch bundles its own HIP runtime; load its libraries before this one so that
+    # both runtimes are present before either initialises (the order that works)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp = c_void_p
+    # initialise the library's HIP runtime before torch's bundled runtime does
+    lib.mb_init.argtypes = [POINTER(c_int)]
+    lib.mb_init.restype = c_int
+    ndev = c_int(0)
+    lib.mb_init(ctypes.byref(ndev))
+    lib.ndevices = ndev.value
     lib.mb_problem_create.argtypes = [POINTER(MbDesc), c_int, POINTER(vp)]
     lib.mb_problem_destroy.argtypes = [vp]
     lib.mb_problem_dims.argtypes = [vp, c_int] + [POINTER(c_int64)] * 5
@@ -89,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.mb_lanczos_default_opts.restype = None
     lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
                                    POINTER(LanczosInfo), vp]
+    lib.mb_small_geneig.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp]
     lib.mb_timer_enable.argtypes = [c_int]
     lib.mb_timer_read.argtypes = [c_int, POINTER(c_double), POINTER(c_int64), POINTER(c_int64)]
     lib.mb_last_error.restype = ctypes.c_char_p
@@ -137,6 +147,21 @@ def timer_read():
         _check(load().mb_timer_read(k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
         out[name] = (ms.value, n.value, u.value)
     return out
+
+
+def small_geneig(H: np.ndarray, S: np.ndarray, stream=None):
+    """Batched projected eigenproblems on the GPU: H, S of shape (nz, N, N) complex.
+    Returns (evals (nz, N), Y (nz, N, N), sweeps (nz,))."""
+    H = np.ascontiguousarray(H, dtype=np.complex128)
+    S = np.ascontiguousarray(S, dtype=np.complex128)
+    nz, N, _ = H.shape
+    ev = np.zeros((nz, N))
+    Y = np.zeros((nz, N, N), dtype=np.complex128)
+    sw = np.zeros(nz, dtype=np.int32)
+    _check(load().mb_small_geneig(c_void_p(H.ctypes.data), c_void_p(S.ctypes.data), N, nz,
+                                  c_void_p(ev.ctypes.data), c_void_p(Y.ctypes.data), c_void_p(sw.ctypes.data),
+                                  _stream(stream)))
+    return ev, Y, sw
 
 
 class Problem:
