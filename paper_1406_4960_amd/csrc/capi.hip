@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation, device upload of the set-up tables and
 // composition of the operator kernels on the caller's stream.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -57,7 +58,8 @@ void free_all(Problem* p) {
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
                     p->d_V, p->d_Vf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->ws_part.ptr,
-                    p->ws_proj.ptr, p->ws_lz.ptr, p->ws_small.ptr, p->ws_conv.ptr};
+                    p->ws_proj.ptr, p->ws_lz.ptr, p->ws_small.ptr, p->ws_conv.ptr, p->d_gwin,
+                    p->ws_nlpart.ptr};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& kp : p->kp) {
@@ -195,17 +197,23 @@ mb_status upload(Problem* p) {
 // y = H c (sy = S c if non-null).  prec: 0 FP64, 1 FP32 (c64), 2 c128 vectors with FP32 local/nonlocal.
 mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec, hipStream_t s) {
     if (nbands == 0) return MB_OK;
-    size_t csz = prec == 0 ? sizeof(cx<double>) : sizeof(cx<float>);
+    const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;  // local / combine precision
+    size_t csz = lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>);
     size_t part_bytes = (size_t)nbands * p->nint * 4 * ld * csz;
     MB_TRY(ensure_ws(p->ws_part, part_bytes));
     void* proj = nullptr;
     if (p->np > 0) {
         MB_TRY(ensure_ws(p->ws_proj, (size_t)nbands * p->np * csz));
         proj = p->ws_proj.ptr;
-        MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, prec, s));
+        const char* sel = getenv("MBKS_NL_KERNEL");
+        const bool vector_path = lp == 0 || (sel && std::string(sel) == "vector" && prec < 3);
+        if (vector_path)
+            MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, lp, s));
+        else
+            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : 1, lp == 2, s));
     }
-    MB_TRY(launch_local(p, ik, c, p->ws_part.ptr, nbands, ld, prec, s));
-    MB_TRY(launch_combine(p, ik, c, p->ws_part.ptr, proj, y, sy, nbands, ld, prec, s));
+    MB_TRY(launch_local(p, ik, c, p->ws_part.ptr, nbands, ld, lp, s));
+    MB_TRY(launch_combine(p, ik, c, p->ws_part.ptr, proj, y, sy, nbands, ld, lp, s));
     return MB_OK;
 }
 
@@ -366,8 +374,8 @@ mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
     size_t bytes = (size_t)nbands * h->p.nb * ld * (prec == MB_FP64 ? 16 : 8);
     if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply: c and y overlap");
-    return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1,
-                       (hipStream_t)stream);
+    return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld,
+                       prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream);
 }
 
 mb_status spsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,

@@ -354,7 +354,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     // start vectors
     if (x0) MB_HIP_TRY(hipMemcpyAsync(S.X, x0, (size_t)S.M * S.vbytes, hipMemcpyDeviceToDevice, s));
     else LZ_TRY(dense_random(S.X, S.M, p->nb, S.ld, kp.ng, o.seed, s));
-    int cur = prec == MB_FP64 ? 0 : 2;
+    int cur = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 2 : 4;
     LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, cur));
     LZ_TRY(S.global_rr(S.M));
 

@@ -90,12 +90,14 @@ struct Problem {
     double* d_Z = nullptr;     float* d_Zf = nullptr;
     double* d_E = nullptr;     float* d_Ef = nullptr;
     int32_t* d_zwin = nullptr;
+    int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors (built on first use)
     double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
     void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)
     void* d_tw2 = nullptr; void* d_tw2f = nullptr;
 
     Workspace ws_part;    // local-potential partial projections
     Workspace ws_proj;    // projections <beta|c>
+    Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
     Workspace ws_lz;      // eigensolver vectors
     Workspace ws_small;   // eigensolver small matrices
     Workspace ws_conv;    // precision conversion buffers
@@ -138,6 +140,9 @@ mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int 
                              int prec, hipStream_t s);
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
                             int prec, hipStream_t s);
+// matrix-core projections: mode 1 FP32 MFMA, mode 2 BF16x3 MFMA; vin64 = complex128 vectors
+mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
+                                 bool vin64, hipStream_t s);
 // y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
                          void* y, void* sy, int nbands, int ld, int prec, hipStream_t s);
@@ -151,7 +156,9 @@ mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s);
 mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta,
                             const int32_t* sel, void* x, int nvec, int ld, hipStream_t s);
 
-// composite operator (capi.hip): y = H c (and sy = S c if non-null), FP64 or FP32
+// composite operator (capi.hip): y = H c (and sy = S c if non-null).
+// prec: 0 FP64; 1 FP32 (complex64 vectors); 2 complex128 vectors with FP32 local and
+// nonlocal arithmetic; 3 = 1 and 4 = 2 with BF16x3 projector contractions.
 mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec,
                   hipStream_t s);
 

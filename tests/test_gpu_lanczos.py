@@ -106,7 +106,7 @@ def _golden(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("ik,prec,tol", [(0, "fp64", 1e-8), (3, "fp32", 1e-6)])
+@pytest.mark.parametrize("ik,prec,tol", [(0, "fp64", 1e-8), (3, "fp32", 1e-6), (2, "bf16x3", 1e-6)])
 def test_lanczos_graphene_full(ik, prec, tol):
     g = _golden("graphene")
     if str(ik) not in g["kpoints"]:

@@ -166,3 +166,37 @@ def test_line_kernel_matches_generic_kernel(cfg, prec, monkeypatch):
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert rel_err(y_lines, y_gen) < tol
     p.close()
+
+
+@pytest.mark.parametrize("name", ["micro-nl", "micro-25"])
+def test_hpsi_bf16x3_vs_dense(name):
+    # BF16x3 projector products: each FP32 operand is split into two bf16 parts
+    # (representation error <= 2^-18 relative), the lo*lo term is dropped; about
+    # 1e-5 relative per product, accumulated in FP32: 1e-4 of the largest entry
+    d = CASES[name]()
+    p, dm, perm = _setup(d)
+    prob = operators.Problem(d, 0)
+    H = prob.hamiltonian()
+    x = random_lib_block(41, 5, dm["nb"], dm["ng"], dm["ld"])
+    xo = lib_to_oracle(x, dm["ng"], perm)
+    y = _run(p, "hpsi", 0, x, "bf16x3")
+    ref = oracle_to_lib((H @ xo.T).T, dm["nb"], dm["ng"], dm["ld"], perm)
+    assert rel_err(y, ref) < 1e-4
+    p.close()
+
+
+@pytest.mark.parametrize("cfg", ["graphene", "graphene_2x2"])
+def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
+    # FP32 projections on the matrix cores and on the vector units (same operator,
+    # different summation order in FP32)
+    d = workloads.CONFIGS[cfg]()
+    p, dm, _ = _setup(d, 1)
+    x = random_lib_block(42, 17, dm["nb"], dm["ng"], dm["ld"])
+    y_mfma = _run(p, "hpsi", 1, x, "fp32")
+    monkeypatch.setenv("MBKS_NL_KERNEL", "vector")
+    y_vec = _run(p, "hpsi", 1, x, "fp32")
+    monkeypatch.delenv("MBKS_NL_KERNEL")
+    assert rel_err(y_mfma, y_vec) < 2e-5
+    y_bf = _run(p, "hpsi", 1, x, "bf16x3")
+    assert rel_err(y_bf, y_vec) < 1e-4
+    p.close()
