@@ -205,6 +205,43 @@ mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
                          const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
                          mb_lanczos_info* info, void* stream);
 
+/* ---- many independent problems at once -------------------------------------
+ * A batch is a fixed list of (problem, k-point) items, of different cells, grids,
+ * B-spline counts, G sets and band counts.  Items of one problem share its
+ * tables; the batch owns its own workspaces.  Destroying a problem before a batch
+ * that names it is an error of the caller. */
+typedef struct mb_batch mb_batch;
+
+/* items t = 0..nitems-1 are (probs[t], iks[t]); every problem must be on the same
+ * device.  Host arrays, copied.  Returns MB_ERR_INVALID_ARG for a NULL or host-only
+ * problem, a k index out of range, nitems < 1 or > 65536. */
+mb_status mb_batch_create(mb_problem* const* probs, const int* iks, int nitems, mb_batch** out);
+mb_status mb_batch_destroy(mb_batch* b);
+
+/* y_t = H_t c_t for every item t: the operator of hpsi_apply (Sec. II.B), with the
+ * in-plane FFT work of all items sharing one launch per grid size, one launch for
+ * the banded combine over all items and per-item projector contractions.
+ * c, y: host arrays of nitems device pointers, vectors [nbands[t]][N_b][ld[t]]
+ * (complex128 for MB_FP64, complex64 for MB_FP32 / MB_BF16X3); ld may be NULL
+ * (then each item's recommended ld).  nbands[t] = 0 skips the item.  c_t and y_t
+ * must not overlap, and no y_t may overlap another item's c or y.
+ * Stream-ordered: the small descriptor tables of the launches are staged through
+ * pinned host memory owned by the batch, so successive calls on one batch must
+ * be issued on one stream (or be synchronised in between).  Not capturable into
+ * a graph (it copies from host memory that later calls reuse). */
+mb_status hpsi_apply_batched(mb_batch* b, const void* const* c, void* const* y, const int64_t* nbands,
+                             const int64_t* ld, mb_precision prec, void* stream);
+
+/* lanczos_lowest for every item t (nev[t] eigenpairs, eig[t] host nev[t] doubles,
+ * x[t] device complex128 [nev[t]][N_b][ld_t] with the item's recommended ld_t,
+ * info[t] filled; info may be NULL).  Items of different problems are solved
+ * concurrently on streams of their own, items of one problem one after another;
+ * `stream` waits for all of them.  opts as for lanczos_lowest (NULL: defaults),
+ * x0 = NULL start for every item.  Returns the first error, or
+ * MB_ERR_NOT_CONVERGED when some item did not converge (all outputs filled). */
+mb_status lanczos_lowest_batched(mb_batch* b, const int* nev, mb_precision prec, const mb_lanczos_opts* opts,
+                                 double* const* eig, void* const* x, mb_lanczos_info* info, void* stream);
+
 /* The projected-eigenproblem step of lanczos_lowest on its own (Rayleigh-Ritz with
  * the Jacobi method, Sec. II.C): nz independent generalized Hermitian problems
  * H y = theta S y of size N (1..256), H and S row-major N x N complex128 each

@@ -69,25 +69,6 @@ void free_all(Problem* p) {
     }
 }
 
-bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
-    const char* x = (const char*)a;
-    const char* y = (const char*)b;
-    return x < y + nb && y < x + na;
-}
-
-mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void* out, int64_t nbands, int64_t ld,
-                         const char* what) {
-    if (!h) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": problem is NULL");
-    const Problem& p = h->p;
-    if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, std::string(what) + ": host-only problem");
-    if (ik < 0 || ik >= (int)p.kp.size()) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ik out of range");
-    if (nbands < 0 || nbands > (1 << 20)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": nbands");
-    if (ld < p.kp[ik].ng || ld > (1 << 24)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ld < N_G");
-    if (nbands > 0 && (!in || !out)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": NULL vector");
-    if (p.order != 4) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": GPU kernels support order 4 only");
-    return MB_OK;
-}
-
 struct TimerState {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[MB_NSTAGE];
@@ -112,6 +93,8 @@ void timer_clear() {
 
 }  // namespace
 
+bool timer_enabled() { return g_timer.on; }
+
 StageScope::StageScope(int st, hipStream_t str, int64_t u) : stage(st), s(str), units(u) {
     if (!g_timer.on) return;
     hipEvent_t e;
@@ -132,6 +115,25 @@ StageScope::~StageScope() {
 mb_status set_error(mb_status s, const std::string& msg) {
     g_last_error = msg;
     return s;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void* out, int64_t nbands, int64_t ld,
+                         const char* what) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": problem is NULL");
+    const Problem& p = h->p;
+    if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, std::string(what) + ": host-only problem");
+    if (ik < 0 || ik >= (int)p.kp.size()) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ik out of range");
+    if (nbands < 0 || nbands > (1 << 20)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": nbands");
+    if (ld < p.kp[ik].ng || ld > (1 << 24)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ld < N_G");
+    if (nbands > 0 && (!in || !out)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": NULL vector");
+    if (p.order != 4) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": GPU kernels support order 4 only");
+    return MB_OK;
 }
 
 mb_status ensure_ws(Workspace& w, size_t bytes) {

@@ -1,6 +1,8 @@
 // Interleaved complex type used by the kernels (FP64 or FP32 parts).
 #pragma once
 
+#include <cstdint>
+
 #include <hip/hip_runtime.h>
 
 namespace mb {
@@ -55,6 +57,17 @@ __device__ inline unsigned xcd_logical(unsigned b, unsigned nblocks) {
     // XCD x owns base + (x < rem) blocks; logical start of XCD x
     unsigned start = x * base + (x < rem ? x : rem);
     return start + k;
+}
+
+// Work units of a batch: item t owns units [unit_begin[t], unit_begin[t+1]);
+// returns the item that owns unit u (unit_begin ascending, unit_begin[0] = 0).
+__device__ inline int batch_item_of(const int32_t* unit_begin, int n, unsigned u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if ((unsigned)unit_begin[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 }  // namespace mb

@@ -11,9 +11,12 @@
 // spline row without atomics.  These are the matrix elements of a local
 // potential in the mixed basis (Sec. II.B.1) with the in-plane transform taken
 // on the grid (circular convolution), applied without forming the matrix.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <string>
+#include <vector>
 
 #include "cplx.h"
 #include "mbks_internal.h"
@@ -151,19 +154,27 @@ __device__ void fft_axis(cx<T>* buf, const cx<T>* tw, const FftPlan& pl, int nli
     }
 }
 
+// items == nullptr: one problem described by a0; otherwise a batch (item t owns work
+// units [unit_begin[t], unit_begin[t+1]))
 template <typename TI, typename T, int NT, int MAXG>
-__global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a) {
+__global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a0, const LocalArgs<TI, T>* items,
+                                              const int32_t* unit_begin, int nitems) {
     extern __shared__ unsigned char smem_raw[];
+    unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    LocalArgs<TI, T> a = a0;
+    if (items) {
+        const int it = batch_item_of(unit_begin, nitems, L);
+        a = items[it];
+        L -= (unsigned)unit_begin[it];
+    }
+    const int b = (int)(L % (unsigned)a.nbands);
+    const int s = (int)(L / (unsigned)a.nbands);
+    if (s >= a.nint) return;
     cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw);
     const int npts = a.N1 * a.N2;
     cx<T>* tw1 = grid + npts;
     cx<T>* tw2 = tw1 + a.N1;
     int32_t* rows = reinterpret_cast<int32_t*>(tw2 + a.N2);
-
-    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
-    const int b = (int)(L % (unsigned)a.nbands);
-    const int s = (int)(L / (unsigned)a.nbands);
-    if (s >= a.nint) return;
 
     for (int e = threadIdx.x; e < a.N1; e += NT) tw1[e] = a.tw1[e];
     for (int e = threadIdx.x; e < a.N2; e += NT) tw2[e] = a.tw2[e];
@@ -255,13 +266,65 @@ mb_status run_local(const LocalArgs<TI, T>& a, size_t lds, hipStream_t s) {
         MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned nblocks = (unsigned)a.nbands * (unsigned)a.nint;
     StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, a.nbands);
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a, (const LocalArgs<TI, T>*)nullptr,
+                       (const int32_t*)nullptr, 0);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
 
 template <typename TI, typename T>
-mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
+LocalArgs<TI, T> make_local_args(Problem* p, int ik, const void* c, void* part, int nbands, int ld);
+
+template <typename TI, typename T, int NT, int MAXG>
+mb_status run_local_batch(const std::vector<LocalArgs<TI, T>>& args, const std::vector<int32_t>& begin, int units,
+                          size_t lds, int64_t tot_bands, TableUploader& up, hipStream_t s) {
+    void *ha, *da, *hb, *db;
+    if (!up.reserve(args.size() * sizeof(args[0]), &ha, &da) || !up.reserve(begin.size() * 4, &hb, &db))
+        return set_error(MB_ERR_OOM, "batch descriptor table full");
+    std::memcpy(ha, args.data(), args.size() * sizeof(args[0]));
+    std::memcpy(hb, begin.data(), begin.size() * 4);
+    MB_HIP_TRY(hipMemcpyAsync(da, ha, args.size() * sizeof(args[0]), hipMemcpyHostToDevice, s));
+    MB_HIP_TRY(hipMemcpyAsync(db, hb, begin.size() * 4, hipMemcpyHostToDevice, s));
+    auto kern = k_local<TI, T, NT, MAXG>;
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, tot_bands);
+    hipLaunchKernelGGL(kern, dim3((unsigned)units), dim3(NT), lds, s, args[0], (const LocalArgs<TI, T>*)da,
+                       (const int32_t*)db, (int)args.size());
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status local_batch_impl(const std::vector<BatchItem>& items, TableUploader& up, hipStream_t s) {
+    std::vector<LocalArgs<TI, T>> args;
+    std::vector<int32_t> begin;
+    size_t lds = 0;
+    int units = 0, work = 0, ngmax = 0;
+    int64_t tot_bands = 0;
+    for (const auto& it : items) {
+        if (it.p->order != KORD) return MB_ERR_INVALID_ARG;
+        LocalArgs<TI, T> a = make_local_args<TI, T>(it.p, it.ik, it.c, it.part, it.nbands, it.ld);
+        size_t l = sizeof(cx<T>) * ((size_t)a.N1 * a.N2 + a.N1 + a.N2) + sizeof(int32_t) * a.nrows;
+        lds = std::max(lds, l);
+        work = std::max(work, std::max(max_stage_work(a.p2, a.nrows), max_stage_work(a.p1, a.N2)));
+        ngmax = std::max(ngmax, a.ng);
+        args.push_back(a);
+        begin.push_back(units);
+        units += it.nbands * a.nint;
+        tot_bands += it.nbands;
+    }
+    if (units == 0) return MB_OK;
+    if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
+    if (work <= 256 * MAXB && ngmax <= 256 * 4) return run_local_batch<TI, T, 256, 4>(args, begin, units, lds, tot_bands, up, s);
+    if (work <= 512 * MAXB && ngmax <= 512 * 4) return run_local_batch<TI, T, 512, 4>(args, begin, units, lds, tot_bands, up, s);
+    if (work <= 1024 * MAXB && ngmax <= 1024 * 4) return run_local_batch<TI, T, 1024, 4>(args, begin, units, lds, tot_bands, up, s);
+    if (work <= 1024 * MAXB && ngmax <= 1024 * 8) return run_local_batch<TI, T, 1024, 8>(args, begin, units, lds, tot_bands, up, s);
+    return set_error(MB_ERR_INVALID_ARG, "in-plane grid or G set too large for the local kernel");
+}
+
+template <typename TI, typename T>
+LocalArgs<TI, T> make_local_args(Problem* p, int ik, const void* c, void* part, int nbands, int ld) {
     const KPoint& kp = p->kp[ik];
     LocalArgs<TI, T> a;
     a.c = (const cx<TI>*)c;
@@ -286,6 +349,13 @@ mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, 
     a.inv_n = (T)(1.0 / ((double)p->N1 * p->N2));
     a.p1 = p->plan1;
     a.p2 = p->plan2;
+    return a;
+}
+
+template <typename TI, typename T>
+mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    LocalArgs<TI, T> a = make_local_args<TI, T>(p, ik, c, part, nbands, ld);
     size_t lds = sizeof(cx<T>) * ((size_t)p->N1 * p->N2 + p->N1 + p->N2) + sizeof(int32_t) * a.nrows;
     if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
     int work = std::max(max_stage_work(p->plan2, a.nrows), max_stage_work(p->plan1, p->N2));
@@ -391,4 +461,13 @@ mb_status launch_vgrid(Problem* p, hipStream_t s) {
     return MB_OK;
 }
 
+}  // namespace mb
+
+namespace mb {
+mb_status launch_local_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s) {
+    if (items.empty()) return MB_OK;
+    if (prec == 0) return local_batch_impl<double, double>(items, up, s);
+    if (prec == 1) return local_batch_impl<float, float>(items, up, s);
+    return local_batch_impl<double, float>(items, up, s);
+}
 }  // namespace mb

@@ -9,7 +9,10 @@
 // or a column, runs a compile-time mixed-radix Stockham FFT in registers and
 // stores it back, so a plane costs four passes through LDS instead of one per
 // radix stage.  The column pass fuses inverse FFT, V multiply and forward FFT.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "cplx.h"
 #include "mbks_internal.h"
@@ -152,8 +155,12 @@ struct LineArgs {
     T inv_n;
 };
 
+// item of a batched launch holding flat work unit u (unit_begin ascending, n items)
+// items == nullptr: one problem described by a0; otherwise a batch of problems with the
+// same grid, item t owning work units [unit_begin[t], unit_begin[t+1]).
 template <typename TI, typename T, int N1, int N2, int NT, int MAXG>
-__global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a) {
+__global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const LineArgs<TI, T>* items,
+                                                    const int32_t* unit_begin, int nitems) {
     constexpr int P2 = N2 + 1;          // padded row stride
     constexpr int PLANE = N1 * P2;
     extern __shared__ unsigned char smem_raw[];
@@ -162,7 +169,13 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a) {
     int32_t* rows = reinterpret_cast<int32_t*>(tw2 + N2);
     cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256);
 
-    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    LineArgs<TI, T> a = a0;
+    if (items) {
+        const int it = batch_item_of(unit_begin, nitems, L);
+        a = items[it];
+        L -= (unsigned)unit_begin[it];
+    }
     const int b = (int)(L % (unsigned)a.nbands);
     const int s = (int)(L / (unsigned)a.nbands);
     if (s >= a.nint) return;
@@ -290,6 +303,43 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a) {
     }
 }
 
+template <typename TI, typename T, int N1, int N2>
+LineArgs<TI, T> make_line_args(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int qp) {
+    const KPoint& kp = p->kp[ik];
+    const bool dbl = sizeof(T) == 8;
+    LineArgs<TI, T> a;
+    a.c = (const cx<TI>*)c;
+    a.part = (cx<T>*)part;
+    a.bval = (const T*)(dbl ? (const void*)p->d_bval : (const void*)p->d_bvalf);
+    a.wbval = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
+    a.V = (const T*)(dbl ? (const void*)p->d_V : (const void*)p->d_Vf);
+    a.gmap = kp.d_gmap;
+    a.rows = kp.d_rows;
+    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
+    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
+    a.nbands = nbands;
+    a.ld = ld;
+    a.ng = kp.ng;
+    a.nint = p->nint;
+    a.nq = p->nq;
+    a.nb = p->nb;
+    a.nrows = (int)kp.rows.size();
+    a.qp = qp;
+    a.inv_n = (T)(1.0 / ((double)N1 * N2));
+    return a;
+}
+
+// planes per group: all Gauss planes of an interval when they fit in the LDS budget
+template <typename T, int N1, int N2>
+int planes_per_group(int nq, size_t budget, size_t* lds_out) {
+    const size_t hdr = ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256;
+    const size_t plane = sizeof(cx<T>) * (size_t)N1 * (N2 + 1);
+    int qp = nq;
+    while (qp > 1 && hdr + qp * plane > budget) --qp;
+    *lds_out = hdr + qp * plane;
+    return qp;
+}
+
 template <typename TI, typename T, int N1, int N2, int NT, int MAXG>
 mb_status run_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s, int qp,
                     size_t lds) {
@@ -319,7 +369,8 @@ mb_status run_lines(Problem* p, int ik, const void* c, void* part, int nbands, i
         MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned nblocks = (unsigned)nbands * (unsigned)p->nint;
     StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, nbands);
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), lds, s, a, (const LineArgs<TI, T>*)nullptr,
+                       (const int32_t*)nullptr, 0);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -334,8 +385,8 @@ mb_status lines_dispatch(Problem* p, int ik, const void* c, void* part, int nban
     while (qp > 1 && hdr + qp * plane > budget) --qp;
     const size_t lds = hdr + qp * plane;
     if (lds > 163840) return MB_ERR_INVALID_ARG;
-    // accumulator slots for G sets up to half the grid; larger sets use the generic kernel
-    constexpr int MAXG = (N1 * N2 / 2 + 255) / 256;
+    // accumulator slots for G sets up to 0.55 of the grid; larger sets use the generic kernel
+    constexpr int MAXG = (N1 * N2 * 11 / 20 + 255) / 256;
     if (p->kp[ik].ng > 256 * MAXG) return MB_ERR_INVALID_ARG;
     return run_lines<TI, T, N1, N2, 256, MAXG>(p, ik, c, part, nbands, ld, s, qp, lds);
 }
@@ -369,6 +420,72 @@ mb_status lines_by_size(Problem* p, int ik, const void* c, void* part, int nband
     return MB_ERR_INVALID_ARG;
 }
 
+template <typename TI, typename T, int N1, int N2>
+mb_status lines_batch_impl(const std::vector<BatchItem>& items, TableUploader& up, hipStream_t s) {
+    constexpr int MAXG = (N1 * N2 * 11 / 20 + 255) / 256;
+    const size_t budget = 110 * 1024;
+    std::vector<LineArgs<TI, T>> args;
+    std::vector<int32_t> begin;
+    size_t lds = 0;
+    int units = 0;
+    for (const auto& it : items) {
+        if (it.p->kp[it.ik].ng > 256 * MAXG || it.p->order != KORD) return MB_ERR_INVALID_ARG;
+        size_t l = 0;
+        const int qp = planes_per_group<T, N1, N2>(it.p->nq, budget, &l);
+        lds = std::max(lds, l);
+        args.push_back(make_line_args<TI, T, N1, N2>(it.p, it.ik, it.c, it.part, it.nbands, it.ld, qp));
+        begin.push_back(units);
+        units += it.nbands * it.p->nint;
+    }
+    if (units == 0) return MB_OK;
+    void *ha, *da, *hb, *db;
+    if (!up.reserve(args.size() * sizeof(args[0]), &ha, &da) || !up.reserve(begin.size() * 4, &hb, &db))
+        return set_error(MB_ERR_OOM, "batch descriptor table full");
+    std::memcpy(ha, args.data(), args.size() * sizeof(args[0]));
+    std::memcpy(hb, begin.data(), begin.size() * 4);
+    MB_HIP_TRY(hipMemcpyAsync(da, ha, args.size() * sizeof(args[0]), hipMemcpyHostToDevice, s));
+    MB_HIP_TRY(hipMemcpyAsync(db, hb, begin.size() * 4, hipMemcpyHostToDevice, s));
+    auto kern = k_local_lines<TI, T, N1, N2, 256, MAXG>;
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int64_t tot_bands = 0;
+    for (const auto& it : items) tot_bands += it.nbands;
+    StageScope ts_(sizeof(T) == 8 ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, tot_bands);
+    hipLaunchKernelGGL(kern, dim3((unsigned)units), dim3(256), lds, s, args[0], (const LineArgs<TI, T>*)da,
+                       (const int32_t*)db, (int)items.size());
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status lines_batch_by_size(const std::vector<BatchItem>& items, TableUploader& up, hipStream_t s) {
+    const Problem* p0 = items[0].p;
+    if (p0->N1 != p0->N2) return MB_ERR_INVALID_ARG;
+    switch (p0->N1) {
+        case 16: return lines_batch_impl<TI, T, 16, 16>(items, up, s);
+        case 24: return lines_batch_impl<TI, T, 24, 24>(items, up, s);
+        case 25: return lines_batch_impl<TI, T, 25, 25>(items, up, s);
+        case 27: return lines_batch_impl<TI, T, 27, 27>(items, up, s);
+        case 30: return lines_batch_impl<TI, T, 30, 30>(items, up, s);
+        case 32: return lines_batch_impl<TI, T, 32, 32>(items, up, s);
+        case 36: return lines_batch_impl<TI, T, 36, 36>(items, up, s);
+        case 40: return lines_batch_impl<TI, T, 40, 40>(items, up, s);
+        default: break;
+    }
+    if constexpr (sizeof(T) == 4) {
+        switch (p0->N1) {
+            case 45: return lines_batch_impl<TI, T, 45, 45>(items, up, s);
+            case 48: return lines_batch_impl<TI, T, 48, 48>(items, up, s);
+            case 50: return lines_batch_impl<TI, T, 50, 50>(items, up, s);
+            case 54: return lines_batch_impl<TI, T, 54, 54>(items, up, s);
+            case 60: return lines_batch_impl<TI, T, 60, 60>(items, up, s);
+            case 64: return lines_batch_impl<TI, T, 64, 64>(items, up, s);
+            default: break;
+        }
+    }
+    return MB_ERR_INVALID_ARG;
+}
+
 }  // namespace
 
 // Returns MB_OK if a line kernel handled the grid, MB_ERR_INVALID_ARG if the grid
@@ -381,4 +498,15 @@ mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int 
     return lines_by_size<double, float>(p, ik, c, part, nbands, ld, s);
 }
 
+}  // namespace mb
+
+namespace mb {
+// items must share the in-plane grid; prec as for launch_local_lines
+mb_status launch_local_lines_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up,
+                                   hipStream_t s) {
+    if (items.empty()) return MB_OK;
+    if (prec == 0) return lines_batch_by_size<double, double>(items, up, s);
+    if (prec == 1) return lines_batch_by_size<float, float>(items, up, s);
+    return lines_batch_by_size<double, float>(items, up, s);
+}
 }  // namespace mb

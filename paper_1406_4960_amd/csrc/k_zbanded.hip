@@ -8,6 +8,8 @@
 // Kleinman-Bylander expansion leave in one pass.  s_solve and the
 // preconditioner are forward / back substitutions with banded Cholesky factors.
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "cplx.h"
 #include "mbks_internal.h"
@@ -35,13 +37,25 @@ struct CombineArgs {
     int nbands, ld, ng, nb, nint, np;
 };
 
+// One block per (band, chunk of CH rows, 256 columns); items == nullptr: one
+// problem described by a0, else a batch (item t owns blocks [unit_begin[t], unit_begin[t+1])).
 template <typename TI, typename T>
-__global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const CombineArgs<TI, T>* items,
+                                                 const int32_t* unit_begin, int nitems) {
+    unsigned L = blockIdx.x;
+    CombineArgs<TI, T> a = a0;
+    if (items) {
+        const int it = batch_item_of(unit_begin, nitems, L);
+        a = items[it];
+        L -= (unsigned)unit_begin[it];
+    }
+    const unsigned ncol = (unsigned)(a.ld + 255) / 256;
+    const int g = (int)(L % ncol) * 256 + threadIdx.x;
+    const int row = (int)(L / ncol);
     const int nchunk = (a.nb + CH - 1) / CH;
-    const int b = blockIdx.y / nchunk;
-    const int i0 = (blockIdx.y - b * nchunk) * CH;
-    if (g >= a.ld) return;
+    const int b = row / nchunk;
+    const int i0 = (row - b * nchunk) * CH;
+    if (g >= a.ld || b >= a.nbands) return;
     const size_t vb = (size_t)b * a.nb * a.ld;
     const int i1 = min(i0 + CH, a.nb);
     if (g >= a.ng) {
@@ -224,8 +238,8 @@ __global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx
 }
 
 template <typename TI, typename T>
-mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
-                       void* sy, int nbands, int ld, hipStream_t s) {
+CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const void* part, const void* proj,
+                                     void* y, void* sy, int nbands, int ld) {
     const KPoint& kp = p->kp[ik];
     CombineArgs<TI, T> a;
     const bool dbl = sizeof(T) == 8;
@@ -247,10 +261,50 @@ mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, cons
     a.nint = p->nint;
     a.np = p->np;
     if (p->np == 0) a.proj = nullptr;
-    int nchunk = (p->nb + CH - 1) / CH;
-    dim3 grid((ld + 255) / 256, nbands * nchunk);
+    return a;
+}
+
+inline int64_t combine_blocks(int nb, int ld, int nbands) {
+    return (int64_t)((ld + 255) / 256) * nbands * ((nb + CH - 1) / CH);
+}
+
+template <typename TI, typename T>
+mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
+                       void* sy, int nbands, int ld, hipStream_t s) {
+    CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld);
+    const int64_t nblk = combine_blocks(p->nb, ld, nbands);
+    if (nblk == 0) return MB_OK;
+    if (nblk > (int64_t)1 << 24) return set_error(MB_ERR_INVALID_ARG, "block too large for the combine kernel");
     StageScope ts_(y ? MB_STAGE_COMBINE : MB_STAGE_SPSI, s, nbands);
-    hipLaunchKernelGGL((k_combine<TI, T>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_combine<TI, T>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status combine_batch_impl(const std::vector<BatchItem>& items, TableUploader& up, hipStream_t s) {
+    std::vector<CombineArgs<TI, T>> args;
+    std::vector<int32_t> begin;
+    int64_t units = 0, tot_bands = 0;
+    for (const auto& it : items) {
+        args.push_back(make_combine_args<TI, T>(it.p, it.ik, it.c, it.part, it.proj, it.y, nullptr, it.nbands,
+                                                it.ld));
+        begin.push_back((int32_t)units);
+        units += combine_blocks(it.p->nb, it.ld, it.nbands);
+        tot_bands += it.nbands;
+    }
+    if (units == 0) return MB_OK;
+    if (units > (int64_t)1 << 24) return set_error(MB_ERR_INVALID_ARG, "batch too large for the combine kernel");
+    void *ha, *da, *hb, *db;
+    if (!up.reserve(args.size() * sizeof(args[0]), &ha, &da) || !up.reserve(begin.size() * 4, &hb, &db))
+        return set_error(MB_ERR_OOM, "batch descriptor table full");
+    std::memcpy(ha, args.data(), args.size() * sizeof(args[0]));
+    std::memcpy(hb, begin.data(), begin.size() * 4);
+    MB_HIP_TRY(hipMemcpyAsync(da, ha, args.size() * sizeof(args[0]), hipMemcpyHostToDevice, s));
+    MB_HIP_TRY(hipMemcpyAsync(db, hb, begin.size() * 4, hipMemcpyHostToDevice, s));
+    StageScope ts_(MB_STAGE_COMBINE, s, tot_bands);
+    hipLaunchKernelGGL((k_combine<TI, T>), dim3((unsigned)units), dim3(256), 0, s, args[0],
+                       (const CombineArgs<TI, T>*)da, (const int32_t*)db, (int)args.size());
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -263,6 +317,13 @@ mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, co
     if (prec == 0) return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s);
     if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
     return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
+}
+
+mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s) {
+    if (items.empty()) return MB_OK;
+    if (prec == 0) return combine_batch_impl<double, double>(items, up, s);
+    if (prec == 1) return combine_batch_impl<float, float>(items, up, s);
+    return combine_batch_impl<double, float>(items, up, s);
 }
 
 mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec, hipStream_t s) {

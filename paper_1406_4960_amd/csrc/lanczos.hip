@@ -228,6 +228,8 @@ struct Solver {
     }
 };
 
+}  // namespace
+
 mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_lanczos_opts& o, const void* x0,
                        double* eig, void* xout, mb_lanczos_info* info, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
@@ -406,7 +408,6 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     return result;
 }
 
-}  // namespace
 }  // namespace mb
 
 extern "C" void mb_lanczos_default_opts(mb_lanczos_opts* o) {

@@ -128,6 +128,11 @@ bool fft_plan(int n, FftPlan* plan);
 int recommended_ld(int ng);
 
 // device upload (capi.hip)
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb);
+// validation shared by the vector entry points; sets the error message
+mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void* out, int64_t nbands, int64_t ld,
+                         const char* what);
+Problem* problem_of(mb_problem* h);
 mb_status upload(Problem* p);
 mb_status ensure_ws(Workspace& w, size_t bytes);
 
@@ -155,6 +160,47 @@ mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s);
 // sel: optional device index list mapping output j to input vector sel[j]
 mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta,
                             const int32_t* sel, void* x, int nvec, int ld, hipStream_t s);
+
+// ---- batched application over many (problem, k-point) items ------------------
+struct BatchItem {
+    Problem* p;
+    int ik;
+    const void* c;
+    void* y;
+    void* part;        // local partial rows of this item
+    void* proj;        // projections of this item
+    int nbands;
+    int ld;
+};
+
+// Copies small descriptor tables to the device in stream order through a pinned
+// host buffer; callers wait on `done` before refilling the host buffer.
+struct TableUploader {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    // reserve bytes (256-aligned); returns host and device addresses
+    bool reserve(size_t bytes, void** h, void** d) {
+        size_t off = (used + 255) / 256 * 256;
+        if (off + bytes > cap) return false;
+        *h = host + off;
+        *d = dev + off;
+        used = off + bytes;
+        return true;
+    }
+};
+
+// each returns MB_ERR_INVALID_ARG (without a message) when it cannot take the items
+mb_status launch_local_lines_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up,
+                                   hipStream_t s);
+mb_status launch_local_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s);
+mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s);
+
+// eigensolver (lanczos.hip): arguments already validated
+mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_lanczos_opts& o, const void* x0,
+                       double* eig, void* x, mb_lanczos_info* info, hipStream_t s);
+bool timer_enabled();
 
 // composite operator (capi.hip): y = H c (and sy = S c if non-null).
 // prec: 0 FP64; 1 FP32 (complex64 vectors); 2 complex128 vectors with FP32 local and

@@ -26,6 +26,7 @@ MB_MAX_GAUSS = 4
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
            "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
+           "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
@@ -98,6 +99,10 @@ def load(path: str = LIB_PATH):
     lib.mb_lanczos_default_opts.restype = None
     lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
                                    POINTER(LanczosInfo), vp]
+    lib.mb_batch_create.argtypes = [vp, vp, c_int, POINTER(vp)]
+    lib.mb_batch_destroy.argtypes = [vp]
+    lib.hpsi_apply_batched.argtypes = [vp, vp, vp, vp, vp, c_int, vp]
+    lib.lanczos_lowest_batched.argtypes = [vp, vp, c_int, POINTER(LanczosOpts), vp, vp, vp, vp]
     lib.mb_small_geneig.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp]
     lib.mb_timer_enable.argtypes = [c_int]
     lib.mb_timer_read.argtypes = [c_int, POINTER(c_double), POINTER(c_int64), POINTER(c_int64)]
@@ -320,3 +325,72 @@ class Problem:
             _check(st)
         inf = {f: getattr(info, f) for f, _ in LanczosInfo._fields_}
         return eig, x, inf, st
+
+
+class Batch:
+    """A fixed list of (Problem, k-point) items applied or solved together."""
+
+    def __init__(self, items):
+        self.items = [(pr, int(ik)) for pr, ik in items]
+        n = len(self.items)
+        probs = (c_void_p * n)(*[pr.h for pr, _ in self.items])
+        iks = (c_int * n)(*[ik for _, ik in self.items])
+        h = c_void_p()
+        _check(load().mb_batch_create(ctypes.cast(probs, c_void_p), ctypes.cast(iks, c_void_p), n,
+                                      ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().mb_batch_destroy(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def hpsi(self, cs, ys, prec="fp64", stream=None):
+        """ys[t] = H_t cs[t]; tensors [nbands_t][N_b][ld_t] (None or 0 bands: skipped)."""
+        n = len(self.items)
+        if len(cs) != n or len(ys) != n:
+            raise ValueError("one input and one output block per item")
+        cp = (c_void_p * n)(*[c.data_ptr() if c is not None else 0 for c in cs])
+        yp = (c_void_p * n)(*[y.data_ptr() if y is not None else 0 for y in ys])
+        nb = (c_int64 * n)(*[c.shape[0] if c is not None else 0 for c in cs])
+        ld = (c_int64 * n)(*[c.shape[2] if c is not None else self.items[t][0].dims(self.items[t][1])["ld"]
+                             for t, c in enumerate(cs)])
+        _check(load().hpsi_apply_batched(self.h, ctypes.cast(cp, c_void_p), ctypes.cast(yp, c_void_p),
+                                         ctypes.cast(nb, c_void_p), ctypes.cast(ld, c_void_p), _prec(prec),
+                                         _stream(stream)))
+
+    def lanczos_lowest(self, nev, prec="fp64", opts=None, stream=None, raise_not_converged=True):
+        """nev: list of eigenpair counts per item.  Returns (eigs list, xs list of torch tensors,
+        infos list of dicts, status)."""
+        import torch
+        n = len(self.items)
+        eigs, xs = [], []
+        for (pr, ik), k in zip(self.items, nev):
+            dm = pr.dims(ik)
+            eigs.append(np.zeros(max(k, 1)))
+            xs.append(torch.zeros((max(k, 1), dm["nb"], dm["ld"]), dtype=torch.complex128,
+                                  device=f"cuda:{pr.device}"))
+        ne = (c_int * n)(*[int(k) for k in nev])
+        ep = (c_void_p * n)(*[e.ctypes.data for e in eigs])
+        xp = (c_void_p * n)(*[x.data_ptr() for x in xs])
+        infos = (LanczosInfo * n)()
+        o = opts if opts is not None else Problem.default_opts()
+        st = load().lanczos_lowest_batched(self.h, ctypes.cast(ne, c_void_p), _prec(prec), ctypes.byref(o),
+                                           ctypes.cast(ep, c_void_p), ctypes.cast(xp, c_void_p),
+                                           ctypes.cast(infos, c_void_p), _stream(stream))
+        if st != 0 and not (st == -3 and not raise_not_converged):
+            _check(st)
+        inf = [{f: getattr(infos[t], f) for f, _ in LanczosInfo._fields_} for t in range(n)]
+        return [e[:k] for e, k in zip(eigs, nev)], [x[:k] for x, k in zip(xs, nev)], inf, st
