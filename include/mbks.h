@@ -27,9 +27,10 @@
  * the library never frees them.  `stream` is a hipStream_t (NULL = default
  * stream); apply/solve calls are enqueued on it and return without
  * synchronising.  lanczos_lowest synchronises `stream` (it returns host
- * eigenvalues).  A problem handle owns its device tables and work buffers; one
- * handle must not be used from two host threads at the same time, and calls on
- * different streams that share a handle's work buffers must not overlap.
+ * eigenvalues).  A problem handle owns its device tables and one set of work
+ * buffers per k-point.  Calls on different k-points of one handle may run
+ * concurrently (from different host threads, on different streams); calls on
+ * the same k-point must not overlap (issue them on one stream from one thread).
  *
  * Errors: every entry point returns an mb_status; arguments are validated
  * before anything is enqueued.  mb_last_error() returns a thread-local message
@@ -234,8 +235,9 @@ mb_status hpsi_apply_batched(mb_batch* b, const void* const* c, void* const* y, 
 
 /* lanczos_lowest for every item t (nev[t] eigenpairs, eig[t] host nev[t] doubles,
  * x[t] device complex128 [nev[t]][N_b][ld_t] with the item's recommended ld_t,
- * info[t] filled; info may be NULL).  Items of different problems are solved
- * concurrently on streams of their own, items of one problem one after another;
+ * info[t] filled; info may be NULL).  Items are solved concurrently on streams of
+ * their own (up to 16 at a time); items naming the same (problem, k-point) one
+ * after another;
  * `stream` waits for all of them.  opts as for lanczos_lowest (NULL: defaults),
  * x0 = NULL start for every item.  Returns the first error, or
  * MB_ERR_NOT_CONVERGED when some item did not converge (all outputs filled). */

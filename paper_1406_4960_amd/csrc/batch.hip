@@ -172,7 +172,7 @@ mb_status apply_batched(mb_batch* b, const void* const* c, void* const* y, const
 }
 
 struct SolveJob {
-    std::vector<int> items;  // of one problem, solved in order
+    std::vector<int> items;  // of one (problem, k-point), solved in order
 };
 
 }  // namespace
@@ -257,15 +257,16 @@ mb_status lanczos_lowest_batched(mb_batch* b, const int* nev, mb_precision prec,
             return set_error(MB_ERR_INVALID_ARG, "lanczos_lowest_batched: NULL output");
     }
     hipStream_t caller = (hipStream_t)stream;
-    // items of one problem share its workspaces: one job per problem
+    // calls on one k-point of a problem share its workspaces: one job per (problem, k-point)
     std::vector<mb::SolveJob> jobs;
     {
-        std::map<mb::Problem*, int> idx;
+        std::map<std::pair<mb::Problem*, int>, int> idx;
         for (int t = 0; t < n; ++t) {
             if (nev[t] == 0) continue;
-            auto f = idx.find(b->items[t].p);
+            const std::pair<mb::Problem*, int> key{b->items[t].p, b->items[t].ik};
+            auto f = idx.find(key);
             if (f == idx.end()) {
-                idx[b->items[t].p] = (int)jobs.size();
+                idx[key] = (int)jobs.size();
                 jobs.push_back({{t}});
             } else {
                 jobs[f->second].items.push_back(t);

@@ -57,13 +57,12 @@ void free_all(Problem* p) {
     if (p->device < 0) return;
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
-                    p->d_V, p->d_Vf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->ws_part.ptr,
-                    p->ws_proj.ptr, p->ws_lz.ptr, p->ws_small.ptr, p->ws_conv.ptr, p->d_gwin,
-                    p->ws_nlpart.ptr};
+                    p->d_V, p->d_Vf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& kp : p->kp) {
-        void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_F64, kp.d_F32, kp.d_pfac};
+        void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_F64, kp.d_F32, kp.d_pfac,
+                      kp.ws_part.ptr, kp.ws_proj.ptr, kp.ws_nlpart.ptr, kp.ws_lz.ptr, kp.ws_small.ptr};
         for (void* q : kq)
             if (q) (void)hipFree(q);
     }
@@ -170,6 +169,7 @@ mb_status upload(Problem* p) {
         MB_TRY(upload_vec(&p->d_E, p->Ep));
         MB_TRY(upload_f32(&p->d_Ef, p->Ep));
         MB_TRY(upload_vec(&p->d_zwin, p->zwin));
+        MB_TRY(upload_group_windows(p));
     }
     size_t nv = (size_t)p->nzq * p->N1 * p->N2;
     if (hipMalloc(&p->d_V, nv * sizeof(double)) != hipSuccess) return set_error(MB_ERR_OOM, "potential grid");
@@ -202,11 +202,12 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;  // local / combine precision
     size_t csz = lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>);
     size_t part_bytes = (size_t)nbands * p->nint * 4 * ld * csz;
-    MB_TRY(ensure_ws(p->ws_part, part_bytes));
+    KPoint& kp = p->kp[ik];
+    MB_TRY(ensure_ws(kp.ws_part, part_bytes));
     void* proj = nullptr;
     if (p->np > 0) {
-        MB_TRY(ensure_ws(p->ws_proj, (size_t)nbands * p->np * csz));
-        proj = p->ws_proj.ptr;
+        MB_TRY(ensure_ws(kp.ws_proj, (size_t)nbands * p->np * csz));
+        proj = kp.ws_proj.ptr;
         const char* sel = getenv("MBKS_NL_KERNEL");
         const bool vector_path = lp == 0 || (sel && std::string(sel) == "vector" && prec < 3);
         if (vector_path)
@@ -214,8 +215,8 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         else
             MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : 1, lp == 2, s));
     }
-    MB_TRY(launch_local(p, ik, c, p->ws_part.ptr, nbands, ld, lp, s));
-    MB_TRY(launch_combine(p, ik, c, p->ws_part.ptr, proj, y, sy, nbands, ld, lp, s));
+    MB_TRY(launch_local(p, ik, c, kp.ws_part.ptr, nbands, ld, lp, s));
+    MB_TRY(launch_combine(p, ik, c, kp.ws_part.ptr, proj, y, sy, nbands, ld, lp, s));
     return MB_OK;
 }
 

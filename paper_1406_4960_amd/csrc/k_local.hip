@@ -295,32 +295,46 @@ mb_status run_local_batch(const std::vector<LocalArgs<TI, T>>& args, const std::
     return MB_OK;
 }
 
+// kernel variant (threads, G values per thread) that the single-problem launch uses
+inline int local_variant(int work, int ng) {
+    if (work <= 256 * MAXB && ng <= 256 * 2) return 0;
+    if (work <= 256 * MAXB && ng <= 256 * 4) return 1;
+    if (work <= 512 * MAXB && ng <= 512 * 4) return 2;
+    if (work <= 1024 * MAXB && ng <= 1024 * 4) return 3;
+    if (work <= 1024 * MAXB && ng <= 1024 * 8) return 4;
+    return -1;
+}
+
+// one launch per kernel variant over the items that need it
 template <typename TI, typename T>
 mb_status local_batch_impl(const std::vector<BatchItem>& items, TableUploader& up, hipStream_t s) {
-    std::vector<LocalArgs<TI, T>> args;
-    std::vector<int32_t> begin;
-    size_t lds = 0;
-    int units = 0, work = 0, ngmax = 0;
-    int64_t tot_bands = 0;
+    std::vector<LocalArgs<TI, T>> args[5];
+    std::vector<int32_t> begin[5];
+    size_t lds[5] = {0, 0, 0, 0, 0};
+    int units[5] = {0, 0, 0, 0, 0};
+    int64_t bands[5] = {0, 0, 0, 0, 0};
     for (const auto& it : items) {
         if (it.p->order != KORD) return MB_ERR_INVALID_ARG;
+        if (it.nbands == 0) continue;
         LocalArgs<TI, T> a = make_local_args<TI, T>(it.p, it.ik, it.c, it.part, it.nbands, it.ld);
         size_t l = sizeof(cx<T>) * ((size_t)a.N1 * a.N2 + a.N1 + a.N2) + sizeof(int32_t) * a.nrows;
-        lds = std::max(lds, l);
-        work = std::max(work, std::max(max_stage_work(a.p2, a.nrows), max_stage_work(a.p1, a.N2)));
-        ngmax = std::max(ngmax, a.ng);
-        args.push_back(a);
-        begin.push_back(units);
-        units += it.nbands * a.nint;
-        tot_bands += it.nbands;
+        if (l > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
+        const int work = std::max(max_stage_work(a.p2, a.nrows), max_stage_work(a.p1, a.N2));
+        const int v = local_variant(work, a.ng);
+        if (v < 0) return set_error(MB_ERR_INVALID_ARG, "in-plane grid or G set too large for the local kernel");
+        lds[v] = std::max(lds[v], l);
+        args[v].push_back(a);
+        begin[v].push_back(units[v]);
+        units[v] += it.nbands * a.nint;
+        bands[v] += it.nbands;
     }
-    if (units == 0) return MB_OK;
-    if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
-    if (work <= 256 * MAXB && ngmax <= 256 * 4) return run_local_batch<TI, T, 256, 4>(args, begin, units, lds, tot_bands, up, s);
-    if (work <= 512 * MAXB && ngmax <= 512 * 4) return run_local_batch<TI, T, 512, 4>(args, begin, units, lds, tot_bands, up, s);
-    if (work <= 1024 * MAXB && ngmax <= 1024 * 4) return run_local_batch<TI, T, 1024, 4>(args, begin, units, lds, tot_bands, up, s);
-    if (work <= 1024 * MAXB && ngmax <= 1024 * 8) return run_local_batch<TI, T, 1024, 8>(args, begin, units, lds, tot_bands, up, s);
-    return set_error(MB_ERR_INVALID_ARG, "in-plane grid or G set too large for the local kernel");
+    mb_status st = MB_OK;
+    if (units[0] && st == MB_OK) st = run_local_batch<TI, T, 256, 2>(args[0], begin[0], units[0], lds[0], bands[0], up, s);
+    if (units[1] && st == MB_OK) st = run_local_batch<TI, T, 256, 4>(args[1], begin[1], units[1], lds[1], bands[1], up, s);
+    if (units[2] && st == MB_OK) st = run_local_batch<TI, T, 512, 4>(args[2], begin[2], units[2], lds[2], bands[2], up, s);
+    if (units[3] && st == MB_OK) st = run_local_batch<TI, T, 1024, 4>(args[3], begin[3], units[3], lds[3], bands[3], up, s);
+    if (units[4] && st == MB_OK) st = run_local_batch<TI, T, 1024, 8>(args[4], begin[4], units[4], lds[4], bands[4], up, s);
+    return st;
 }
 
 template <typename TI, typename T>
@@ -360,11 +374,14 @@ mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, 
     if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
     int work = std::max(max_stage_work(p->plan2, a.nrows), max_stage_work(p->plan1, p->N2));
     // smallest block that covers the FFT stages and the G set
-    if (work <= 256 * MAXB && kp.ng <= 256 * 2) return run_local<TI, T, 256, 2>(a, lds, s);
-    if (work <= 256 * MAXB && kp.ng <= 256 * 4) return run_local<TI, T, 256, 4>(a, lds, s);
-    if (work <= 512 * MAXB && kp.ng <= 512 * 4) return run_local<TI, T, 512, 4>(a, lds, s);
-    if (work <= 1024 * MAXB && kp.ng <= 1024 * 4) return run_local<TI, T, 1024, 4>(a, lds, s);
-    if (work <= 1024 * MAXB && kp.ng <= 1024 * 8) return run_local<TI, T, 1024, 8>(a, lds, s);
+    switch (local_variant(work, kp.ng)) {
+        case 0: return run_local<TI, T, 256, 2>(a, lds, s);
+        case 1: return run_local<TI, T, 256, 4>(a, lds, s);
+        case 2: return run_local<TI, T, 512, 4>(a, lds, s);
+        case 3: return run_local<TI, T, 1024, 4>(a, lds, s);
+        case 4: return run_local<TI, T, 1024, 8>(a, lds, s);
+        default: break;
+    }
     return set_error(MB_ERR_INVALID_ARG, "in-plane grid or G set too large for the local kernel");
 }
 

@@ -156,6 +156,26 @@ __global__ void k_nlproj_reduce(const cx<float>* partial, const int32_t* gwin, c
 }  // namespace
 
 // mode 1: FP32 MFMA, mode 2: BF16x3 MFMA; vin64: vectors are complex128
+// union z-window of every group of 16 projectors (set-up, once per problem)
+mb_status upload_group_windows(Problem* p) {
+    const int ngrp = (p->np + 15) / 16;
+    std::vector<int32_t> gw(2 * ngrp);
+    for (int gi = 0; gi < ngrp; ++gi) {
+        int lo = p->nb, hi = -1;
+        for (int q = gi * 16; q < std::min(p->np, gi * 16 + 16); ++q) {
+            if (p->zwin[2 * q + 1] < p->zwin[2 * q]) continue;
+            lo = std::min(lo, (int)p->zwin[2 * q]);
+            hi = std::max(hi, (int)p->zwin[2 * q + 1]);
+        }
+        if (hi < 0) { lo = 0; hi = -1; }
+        gw[2 * gi] = lo;
+        gw[2 * gi + 1] = hi;
+    }
+    MB_HIP_TRY(hipMalloc(&p->d_gwin, gw.size() * sizeof(int32_t)));
+    MB_HIP_TRY(hipMemcpy(p->d_gwin, gw.data(), gw.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return MB_OK;
+}
+
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
                                  bool vin64, hipStream_t s) {
     if (p->np == 0) return MB_OK;
@@ -163,29 +183,14 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
     const int ngrp = (p->np + 15) / 16;
     const int npad = ngrp * 16;
     const int nbpad = (nbands + 15) / 16 * 16;
-    if (!p->d_gwin) {
-        // union z-window of every group of 16 projectors
-        std::vector<int32_t> gw(2 * ngrp);
-        for (int gi = 0; gi < ngrp; ++gi) {
-            int lo = p->nb, hi = -1;
-            for (int q = gi * 16; q < std::min(p->np, gi * 16 + 16); ++q) {
-                if (p->zwin[2 * q + 1] < p->zwin[2 * q]) continue;
-                lo = std::min(lo, (int)p->zwin[2 * q]);
-                hi = std::max(hi, (int)p->zwin[2 * q + 1]);
-            }
-            if (hi < 0) { lo = 0; hi = -1; }
-            gw[2 * gi] = lo;
-            gw[2 * gi + 1] = hi;
-        }
-        MB_HIP_TRY(hipMalloc(&p->d_gwin, gw.size() * sizeof(int32_t)));
-        MB_HIP_TRY(hipMemcpy(p->d_gwin, gw.data(), gw.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
+    if (!p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
     size_t pbytes = (size_t)p->nb * npad * nbpad * sizeof(cx<float>);
-    mb_status st = ensure_ws(p->ws_nlpart, pbytes);
+    KPoint& kw = p->kp[ik];
+    mb_status st = ensure_ws(kw.ws_nlpart, pbytes);
     if (st != MB_OK) return st;
     StageScope ts_(MB_STAGE_NL_PROJECT, s, nbands);
     dim3 grid(p->nb, nbpad / 16, ngrp);
-    cx<float>* part = (cx<float>*)p->ws_nlpart.ptr;
+    cx<float>* part = (cx<float>*)kw.ws_nlpart.ptr;
     const cx<float>* F = (const cx<float>*)kp.d_F32;
     if (mode == 1) {
         if (vin64)

@@ -66,6 +66,28 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
         return;
     }
     const cx<TI>* cb = a.c + vb + g;
+    // projector expansion of the chunk's rows, sum_p F_p(G) Z_p(i) P'_p(b): each
+    // F_p(G) is loaded once for all CH rows
+    cx<T> nl[CH];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) nl[r] = mk<T>(0, 0);
+    if (a.y && a.proj) {
+        for (int p = 0; p < a.np; ++p) {
+            const int lo = max(a.zwin[2 * p], i0), hi = min(a.zwin[2 * p + 1], i1 - 1);
+            if (lo > hi) continue;
+            const cx<T> fp = cmul(a.F[(size_t)p * a.ld + g], a.proj[(size_t)b * a.np + p]);
+            const T* zp = a.Z + (size_t)p * a.nb;
+#pragma unroll
+            for (int r = 0; r < CH; ++r) {
+                const int i = i0 + r;
+                if (i >= lo && i <= hi) {
+                    const T z = zp[i];
+                    nl[r].x = fma(z, fp.x, nl[r].x);
+                    nl[r].y = fma(z, fp.y, nl[r].y);
+                }
+            }
+        }
+    }
     // sliding window of c rows i-3 .. i+3 in TI precision
     cx<TI> w[2 * KORD - 1];
 #pragma unroll
@@ -74,7 +96,10 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
         w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
     }
     const double kk = a.y ? 0.5 * a.kg2[g] : 0.0;
-    for (int i = i0; i < i1; ++i) {
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+        const int i = i0 + r;
+        if (i >= i1) break;
         // banded products with symmetric S_z, D_z
         double sr = 0, si = 0, tr = 0, ti = 0;
 #pragma unroll
@@ -109,16 +134,8 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
                 yr += (double)pr;
                 yi += (double)pi;
             }
-            if (a.proj) {
-                cx<T> acc = mk<T>(0, 0);
-                for (int p = 0; p < a.np; ++p) {
-                    if (i < a.zwin[2 * p] || i > a.zwin[2 * p + 1]) continue;
-                    cx<T> coef = cscale(a.proj[(size_t)b * a.np + p], a.Z[(size_t)p * a.nb + i]);
-                    cfma(acc, a.F[(size_t)p * a.ld + g], coef);
-                }
-                yr += (double)acc.x;
-                yi += (double)acc.y;
-            }
+            yr += (double)nl[r].x;
+            yi += (double)nl[r].y;
             a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
         }
         // slide the window
@@ -130,54 +147,85 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
 }
 
 // x = (L L^T)^{-1} r along i with a banded lower factor lf[i][d] = L[i][i-d]
-// (shared, pstride = 0) or per G (lf[(i*4+d)*ld + g], pstride = 1).
-template <typename TI>
+// (shared: lf[i*4+d], per_g = 0; or per G: lf[(i*4+d)*ld + g], per_g = 1).
+// The recurrence is sequential in i; the loads of each chunk of U rows are issued
+// together ahead of the chunk's arithmetic so their latencies overlap.  r may
+// equal x (rows are read before they are overwritten).
+template <typename TI, int U = 8>
 __device__ inline void band_solve(const cx<TI>* r, cx<TI>* x, const double* lf, int nb, int ld, int g,
                                   int per_g, double theta, const cx<TI>* sv) {
+    auto L = [&](int row, int d) -> double {
+        return per_g ? lf[((size_t)row * KORD + d) * ld + g] : lf[row * KORD + d];
+    };
     // forward: L w = r   (r - theta * sv when sv != null)
     cx<double> h1 = mk<double>(0, 0), h2 = h1, h3 = h1;  // w_{i-1}, w_{i-2}, w_{i-3}
-    for (int i = 0; i < nb; ++i) {
-        size_t o = (size_t)i * ld + g;
-        cx<TI> rv = r[o];
-        double vr = (double)rv.x, vi = (double)rv.y;
-        if (sv) {
-            cx<TI> s = sv[o];
-            vr -= theta * (double)s.x;
-            vi -= theta * (double)s.y;
+    for (int i0 = 0; i0 < nb; i0 += U) {
+        double vr[U], vi[U], l0[U], l1[U], l2[U], l3[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            if (i < nb) {
+                const size_t o = (size_t)i * ld + g;
+                const cx<TI> rv = r[o];
+                vr[u] = (double)rv.x;
+                vi[u] = (double)rv.y;
+                if (sv) {
+                    const cx<TI> sx = sv[o];
+                    vr[u] -= theta * (double)sx.x;
+                    vi[u] -= theta * (double)sx.y;
+                }
+                l0[u] = L(i, 0);
+                l1[u] = i >= 1 ? L(i, 1) : 0.0;
+                l2[u] = i >= 2 ? L(i, 2) : 0.0;
+                l3[u] = i >= 3 ? L(i, 3) : 0.0;
+            }
         }
-        auto L = [&](int row, int d) -> double {
-            return per_g ? lf[((size_t)row * KORD + d) * ld + g] : lf[row * KORD + d];
-        };
-        if (i >= 1) { double l = L(i, 1); vr -= l * h1.x; vi -= l * h1.y; }
-        if (i >= 2) { double l = L(i, 2); vr -= l * h2.x; vi -= l * h2.y; }
-        if (i >= 3) { double l = L(i, 3); vr -= l * h3.x; vi -= l * h3.y; }
-        double inv = 1.0 / L(i, 0);
-        cx<double> wv = mk<double>(vr * inv, vi * inv);
-        h3 = h2;
-        h2 = h1;
-        h1 = wv;
-        x[o] = mk<TI>((TI)wv.x, (TI)wv.y);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            if (i < nb) {
+                double ar = vr[u] - l1[u] * h1.x - l2[u] * h2.x - l3[u] * h3.x;
+                double ai = vi[u] - l1[u] * h1.y - l2[u] * h2.y - l3[u] * h3.y;
+                const double inv = 1.0 / l0[u];
+                h3 = h2;
+                h2 = h1;
+                h1 = mk<double>(ar * inv, ai * inv);
+                x[(size_t)i * ld + g] = mk<TI>((TI)h1.x, (TI)h1.y);
+            }
+        }
     }
     // back: L^T x = w
     h1 = mk<double>(0, 0);
     h2 = h1;
     h3 = h1;  // x_{i+1}, x_{i+2}, x_{i+3}
-    for (int i = nb - 1; i >= 0; --i) {
-        size_t o = (size_t)i * ld + g;
-        cx<TI> wv = x[o];
-        double vr = (double)wv.x, vi = (double)wv.y;
-        auto L = [&](int row, int d) -> double {
-            return per_g ? lf[((size_t)row * KORD + d) * ld + g] : lf[row * KORD + d];
-        };
-        if (i + 1 < nb) { double l = L(i + 1, 1); vr -= l * h1.x; vi -= l * h1.y; }
-        if (i + 2 < nb) { double l = L(i + 2, 2); vr -= l * h2.x; vi -= l * h2.y; }
-        if (i + 3 < nb) { double l = L(i + 3, 3); vr -= l * h3.x; vi -= l * h3.y; }
-        double inv = 1.0 / L(i, 0);
-        cx<double> xv = mk<double>(vr * inv, vi * inv);
-        h3 = h2;
-        h2 = h1;
-        h1 = xv;
-        x[o] = mk<TI>((TI)xv.x, (TI)xv.y);
+    for (int i0 = nb - 1; i0 >= 0; i0 -= U) {
+        double vr[U], vi[U], l0[U], l1[U], l2[U], l3[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 - u;
+            if (i >= 0) {
+                const cx<TI> wv = x[(size_t)i * ld + g];
+                vr[u] = (double)wv.x;
+                vi[u] = (double)wv.y;
+                l0[u] = L(i, 0);
+                l1[u] = i + 1 < nb ? L(i + 1, 1) : 0.0;
+                l2[u] = i + 2 < nb ? L(i + 2, 2) : 0.0;
+                l3[u] = i + 3 < nb ? L(i + 3, 3) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 - u;
+            if (i >= 0) {
+                double ar = vr[u] - l1[u] * h1.x - l2[u] * h2.x - l3[u] * h3.x;
+                double ai = vi[u] - l1[u] * h1.y - l2[u] * h2.y - l3[u] * h3.y;
+                const double inv = 1.0 / l0[u];
+                h3 = h2;
+                h2 = h1;
+                h1 = mk<double>(ar * inv, ai * inv);
+                x[(size_t)i * ld + g] = mk<TI>((TI)h1.x, (TI)h1.y);
+            }
+        }
     }
 }
 

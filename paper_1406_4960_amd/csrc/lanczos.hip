@@ -255,8 +255,9 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
 
     // vector workspace
     size_t nvec = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl;
-    LZ_TRY(ensure_ws(p->ws_lz, nvec * S.vbytes));
-    char* base = (char*)p->ws_lz.ptr;
+    KPoint& kw = p->kp[ik];
+    LZ_TRY(ensure_ws(kw.ws_lz, nvec * S.vbytes));
+    char* base = (char*)kw.ws_lz.ptr;
     auto take = [&](int n) {
         char* r = base;
         base += (size_t)n * S.vbytes;
@@ -281,8 +282,8 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
                    3 * NN * 16 + NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 +
                    (size_t)S.nbl * S.m * 16 + (size_t)64 * std::max(S.nbl * S.m, S.NG) * 16 +
                    (3 * (size_t)S.M + S.NG + 2 * S.nbl + 64) * 8 + S.gscratch_bytes + 64 * 256;
-    LZ_TRY(ensure_ws(p->ws_small, small));
-    char* sb = (char*)p->ws_small.ptr;
+    LZ_TRY(ensure_ws(kw.ws_small, small));
+    char* sb = (char*)kw.ws_small.ptr;
     auto stake = [&](size_t bytes) {
         char* r = sb;
         sb += (bytes + 255) / 256 * 256;
@@ -346,7 +347,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.resid = (double*)stake(S.M * sizeof(double));
     S.status = (int*)stake(64);
     S.gscratch = stake(S.gscratch_bytes);
-    if ((size_t)(sb - (char*)p->ws_small.ptr) > p->ws_small.bytes) return set_error(MB_ERR_INVALID_ARG, "small workspace layout");
+    if ((size_t)(sb - (char*)kw.ws_small.ptr) > kw.ws_small.bytes) return set_error(MB_ERR_INVALID_ARG, "small workspace layout");
     MB_HIP_TRY(hipMemsetAsync(S.status, 0, sizeof(int), s));
     S.h_theta.assign(S.M, 0.0);
     S.h_resid.assign(S.M, 0.0);

@@ -21,7 +21,13 @@ struct FftPlan {
     int rad[12];
 };
 
-// Per-k-point tables.
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Per-k-point tables and the device workspaces of calls on this k-point (calls on
+// different k-points of one problem may run concurrently on different streams).
 struct KPoint {
     int ng = 0;
     int ld = 0;
@@ -41,11 +47,11 @@ struct KPoint {
     // preconditioner factors (T + sigma S) per G, [i][d][ld] doubles, built on demand
     double* d_pfac = nullptr;
     double pfac_sigma = -1.0;
-};
-
-struct Workspace {
-    void* ptr = nullptr;
-    size_t bytes = 0;
+    Workspace ws_part;    // local-potential partial projections
+    Workspace ws_proj;    // projections <beta|c>
+    Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
+    Workspace ws_lz;      // eigensolver vectors
+    Workspace ws_small;   // eigensolver small matrices
 };
 
 struct Problem {
@@ -90,17 +96,11 @@ struct Problem {
     double* d_Z = nullptr;     float* d_Zf = nullptr;
     double* d_E = nullptr;     float* d_Ef = nullptr;
     int32_t* d_zwin = nullptr;
-    int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors (built on first use)
+    int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors
     double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
     void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)
     void* d_tw2 = nullptr; void* d_tw2f = nullptr;
 
-    Workspace ws_part;    // local-potential partial projections
-    Workspace ws_proj;    // projections <beta|c>
-    Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
-    Workspace ws_lz;      // eigensolver vectors
-    Workspace ws_small;   // eigensolver small matrices
-    Workspace ws_conv;    // precision conversion buffers
 };
 
 // stage timer: brackets one kernel launch with events when enabled
@@ -135,6 +135,7 @@ mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void
 Problem* problem_of(mb_problem* h);
 mb_status upload(Problem* p);
 mb_status ensure_ws(Workspace& w, size_t bytes);
+mb_status upload_group_windows(Problem* p);
 
 // kernel launchers (k_*.hip); prec 0 = fp64, 1 = fp32
 mb_status launch_vgrid(Problem* p, hipStream_t s);
