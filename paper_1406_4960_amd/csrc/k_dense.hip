@@ -58,6 +58,62 @@ __global__ __launch_bounds__(256) void k_gram(const zc* const* ta, const zc* con
     if (m < MA && n < NB) part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = acc;
 }
 
+// the same product with 32 x 32 output tiles, each thread holding a 2 x 2 block of
+// outputs (m = m0 + ty + 16 a, n = n0 + tx + 16 c): one LDS read per complex FMA
+constexpr int GT2 = 32;
+constexpr int GK2 = 16;
+
+__global__ __launch_bounds__(256) void k_gram32(const zc* const* ta, const zc* const* tb, int MA, int NB, int64_t K,
+                                                int64_t kchunk, int nchunk, int tiles_n, zc* part) {
+    __shared__ zc As[GT2][GK2 + 1];
+    __shared__ zc Bs[GT2][GK2 + 1];
+    const int z = blockIdx.z;
+    const int chunk = blockIdx.x;
+    const int tm = blockIdx.y / tiles_n, tn = blockIdx.y % tiles_n;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = tm * GT2, n0 = tn * GT2;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    zc acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = mk<double>(0, 0);
+    for (int64_t kb = k0; kb < k1; kb += GK2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            const int r = e / GK2, kk = e % GK2;
+            const int64_t k = kb + kk;
+            zc va = mk<double>(0, 0), vb = mk<double>(0, 0);
+            if (k < k1) {
+                if (m0 + r < MA) va = ta[(size_t)z * MA + m0 + r][k];
+                if (n0 + r < NB) vb = tb[(size_t)z * NB + n0 + r][k];
+            }
+            As[r][kk] = va;
+            Bs[r][kk] = vb;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < GK2; ++kk) {
+            const zc a0 = As[ty][kk], a1 = As[ty + 16][kk];
+            const zc b0 = Bs[tx][kk], b1 = Bs[tx + 16][kk];
+            cfmac(acc[0][0], a0, b0);
+            cfmac(acc[0][1], a0, b1);
+            cfmac(acc[1][0], a1, b0);
+            cfmac(acc[1][1], a1, b1);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int m = m0 + ty + 16 * a, n = n0 + tx + 16 * c;
+            if (m < MA && n < NB) part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = acc[a][c];
+        }
+}
+
 // one wave per output element: lanes stride over the chunks, then a shuffle tree
 __global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
     const size_t per = (size_t)MA * NB;
@@ -157,27 +213,43 @@ __global__ __launch_bounds__(256) void k_dots_reduce(const zc* part, int nchunk,
     if (lane == 0) out[v] = mk<double>(re, im);
 }
 
-// residual norms r_v = || h_v - theta_v s_v ||_2 and finiteness
-__global__ __launch_bounds__(256) void k_resid(const zc* const* th, const zc* const* ts, const double* theta,
-                                               int64_t K, double* out) {
+// residual norms r_v = || h_v - theta_v s_v ||_2: one 1024-thread block per vector,
+// four independent loads in flight per thread, wave shuffles then one LDS pass
+__global__ __launch_bounds__(1024) void k_resid(const zc* const* th, const zc* const* ts, const double* theta,
+                                                int64_t K, double* out) {
     const int v = blockIdx.x;
     const zc* h = th[v];
     const zc* s = ts[v];
     const double t = theta[v];
     double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < K; k += 256) {
-        zc a = h[k], b = s[k];
-        double re = a.x - t * b.x, im = a.y - t * b.y;
+    int64_t k = threadIdx.x;
+    for (; k + 3 * 1024 < K; k += 4 * 1024) {
+        zc a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = h[k + u * 1024];
+            b[u] = s[k + u * 1024];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double re = a[u].x - t * b[u].x, im = a[u].y - t * b[u].y;
+            acc += re * re + im * im;
+        }
+    }
+    for (; k < K; k += 1024) {
+        const zc a = h[k], b = s[k];
+        const double re = a.x - t * b.x, im = a.y - t * b.y;
         acc += re * re + im * im;
     }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double red[16];
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < 16; ++w) sum += red[w];
+        out[v] = sqrt(sum);
     }
-    if (threadIdx.x == 0) out[v] = sqrt(red[0]);
 }
 
 // Y_v[k] += sign * coef_v * X_v[k]
@@ -234,6 +306,9 @@ __device__ inline int rr_pair(int r, int k, int Np) {
     return (r + k) % (Np - 1);
 }
 
+// squared relative size below which an off-diagonal element is not rotated
+constexpr double JACOBI_TOL2 = 1e-28;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
                                                zc* gwork, int use_lds, int max_sweeps, int* status, int* sweeps_out) {
@@ -250,7 +325,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     zc* P2 = W0 + 2 * NN;
     const int tid = threadIdx.x;
     __shared__ int bad;
-    __shared__ double s_off, s_norm;
+    __shared__ int s_more;
     __shared__ unsigned char dead[256];  // directions numerically in the span of earlier ones
     if (tid == 0) bad = 0;
     // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
@@ -342,35 +417,28 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     double* gc = nullptr;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
-        // off-diagonal norm: per-thread partials, wave shuffle tree, one atomic per wave
-        if (tid == 0) { s_off = 0.0; s_norm = 0.0; }
+        // converged when no off-diagonal element is above the rotation threshold
+        // |a_pq| > 1e-14 (|a_pp| + |a_qq|): a smaller element changes the eigenvalues by
+        // at most |a_pq|^2 / gap (or |a_pq| for a cluster), far below FP64 rounding of
+        // the matrix itself, and rotating it only reshuffles rounding noise
+        if (tid == 0) s_more = 0;
         __syncthreads();
-        double off = 0.0, nrm = 0.0;
+        int more = 0;
         for (int e = tid; e < NNi; e += NT) {
-            int i = (int)(e / N), k = (int)(e % N);
-            if (dead[i] || dead[k]) continue;  // deflated directions are already decoupled
-            zc a = P1[e];
-            double m2 = a.x * a.x + a.y * a.y;
-            nrm += m2;
-            if (i != k) off += m2;
+            const int i = e / N, k = e - i * N;
+            if (k <= i || dead[i] || dead[k]) continue;  // deflated directions are already decoupled
+            const zc a = P1[e];
+            const double r2 = a.x * a.x + a.y * a.y;
+            const double scale = fabs(P1[(size_t)i * N + i].x) + fabs(P1[(size_t)k * N + k].x);
+            if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) more = 1;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            off += __shfl_down(off, o, 64);
-            nrm += __shfl_down(nrm, o, 64);
-        }
-        if ((tid & 63) == 0) {
-            atomicAdd(&s_off, off);
-            atomicAdd(&s_norm, nrm);
-        }
+        if (more) s_more = 1;
         __syncthreads();
-        if (s_off <= 1e-28 * s_norm || s_off == 0.0) break;
-        const int wave = tid / 64, lane = tid % 64, nwave = NT / 64;
+        if (!s_more) break;
         for (int r = 0; r < Np - 1; ++r) {
-            // rows: one wave per pair.  The wave reads its pair's pivots a_pp, a_qq,
-            // a_pq (rows p and q are touched by no other pair this round), derives
-            // the rotation, then its lanes rotate the two rows:
-            //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
-            for (int pi = wave; pi < npair; pi += nwave) {
+            // rotation of every pair of this round from its pivots a_pp, a_qq, a_pq
+            // (the pairs are disjoint, so no pair's pivots change within the round)
+            for (int pi = tid; pi < npair; pi += NT) {
                 int p, q;
                 if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
                 else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
@@ -381,7 +449,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
                     const double r2 = apq.x * apq.x + apq.y * apq.y;
                     const double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
                     const double scale = fabs(app) + fabs(aqq);
-                    if (r2 > 1e-300 && r2 > 1e-36 * scale * scale) {
+                    if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) {
                         // tan of the rotation angle: t = 2|a_pq| sgn(d) / (|d| + sqrt(d^2 + 4|a_pq|^2)),
                         // d = a_qq - a_pp; c = 1/sqrt(1 + t^2); phase a_pq / |a_pq|
                         const double d = aqq - app;
@@ -394,36 +462,38 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
                         si = sn * apq.y;
                     }
                 }
-                // every lane of the wave holds the pivots in registers before any lane writes
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0) { rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q; }
-                if (q < N && (sr != 0.0 || si != 0.0)) {
-                    const zc se = mk<double>(sr, si);
-                    const zc sec = mk<double>(sr, -si);
-                    for (int j = lane; j < N; j += 64) {
-                        zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
-                        P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
-                        P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
-                    }
-                }
+                rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
             }
             __syncthreads();
-            // columns of A and V, one wave per pair:
-            //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
-            for (int pi = wave; pi < npair; pi += nwave) {
+            // rows p, q of every pair:
+            //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
+            for (int e = tid; e < npair * N; e += NT) {
+                const int pi = e / N, j = e - pi * N;
                 const int p = rp[pi], q = rq[pi];
                 if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
                 const double c = rc[pi];
                 const zc se = mk<double>(rsr[pi], rsi[pi]);
                 const zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                for (int i = lane; i < N; i += 64) {
-                    zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
-                    P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
-                    P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
-                    zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
-                    P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
-                    P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
-                }
+                const zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
+                P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
+                P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
+            }
+            __syncthreads();
+            // columns p, q of A and V:
+            //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
+            for (int e = tid; e < npair * N; e += NT) {
+                const int pi = e / N, i = e - pi * N;
+                const int p = rp[pi], q = rq[pi];
+                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
+                const double c = rc[pi];
+                const zc se = mk<double>(rsr[pi], rsi[pi]);
+                const zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                const zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
+                P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
+                P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
+                const zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
+                P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
+                P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
             }
             __syncthreads();
         }
@@ -535,9 +605,12 @@ __global__ void k_copy_cols(const zc* Y, int ldy, int ncols, int nrows, zc* out)
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
                      void* scratch, size_t scratch_bytes, hipStream_t s) {
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
-    int tiles_m = (MA + GT - 1) / GT, tiles_n = (NB + GT - 1) / GT;
+    const bool big = MA > GT && NB > GT;  // 32 x 32 tiles for the wide products
+    const int tile = big ? GT2 : GT, kstep = big ? GK2 : GK;
+    int tiles_m = (MA + tile - 1) / tile, tiles_n = (NB + tile - 1) / tile;
     int ntiles = tiles_m * tiles_n * nz;
-    int64_t maxchunk = (K + 255) / 256;
+    // at least 256 (64 for the wide tiles) k per chunk, about 1024 blocks in all
+    int64_t maxchunk = big ? (K + 63) / 64 : (K + 255) / 256;
     int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 1024 / std::max(1, ntiles)));
     size_t need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
     while (need > scratch_bytes && nchunk > 1) {
@@ -546,12 +619,16 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     }
     if (need > scratch_bytes) return set_error(MB_ERR_INVALID_ARG, "gram scratch too small");
     int64_t kchunk = (K + nchunk - 1) / nchunk;
-    kchunk = (kchunk + GK - 1) / GK * GK;
+    kchunk = (kchunk + kstep - 1) / kstep * kstep;
     nchunk = (int)((K + kchunk - 1) / kchunk);
     dim3 grid(nchunk, tiles_m * tiles_n, nz);
     StageScope ts_(MB_STAGE_GRAM, s);
-    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk,
-                       nchunk, tiles_n, (zc*)scratch);
+    if (big)
+        hipLaunchKernelGGL(k_gram32, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K,
+                           kchunk, nchunk, tiles_n, (zc*)scratch);
+    else
+        hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K,
+                           kchunk, nchunk, tiles_n, (zc*)scratch);
     MB_HIP_TRY(hipGetLastError());
     size_t tot = (size_t)MA * NB * nz;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot * 64 + 255) / 256)), dim3(256), 0, s, (const zc*)scratch,
@@ -594,7 +671,7 @@ mb_status dense_resid(const void* const* th, const void* const* ts, const double
                       double* out, hipStream_t s) {
     StageScope ts_(MB_STAGE_OTHER, s);
     if (nvec <= 0) return MB_OK;
-    hipLaunchKernelGGL(k_resid, dim3(nvec), dim3(256), 0, s, (const zc* const*)th, (const zc* const*)ts, theta, K,
+    hipLaunchKernelGGL(k_resid, dim3(nvec), dim3(1024), 0, s, (const zc* const*)th, (const zc* const*)ts, theta, K,
                        out);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -636,8 +713,7 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
     const size_t dyn = use_lds ? lds : 0;
     StageScope ts_(MB_STAGE_SMALLEIG, s);
-    int nt = N <= 12 ? 64 : 1024;
-    if (const char* e = getenv("MBKS_GENEIG_NT")) nt = atoi(e);
+    const int nt = N <= 12 ? 64 : N <= 48 ? 256 : 1024;
     if (nt == 256) {
         if (dyn > 65536)
             MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
