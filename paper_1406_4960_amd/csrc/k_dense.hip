@@ -114,6 +114,111 @@ __global__ __launch_bounds__(256) void k_gram32(const zc* const* ta, const zc* c
         }
 }
 
+// narrow products (MA <= 16): block (chunk, n, z) streams its k range once, each
+// thread accumulating conj(A_m[k]) B_n[k] for every m in registers; wave shuffles
+// and one LDS pass reduce the block's MA sums into part[z][chunk][m][n]
+constexpr int SKINNY = 16;
+
+__global__ __launch_bounds__(256) void k_gram_skinny(const zc* const* ta, const zc* const* tb, int MA, int NB,
+                                                     int64_t K, int64_t kchunk, int nchunk, zc* part) {
+    const int z = blockIdx.z;
+    const int n = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    const zc* bcol = tb[(size_t)z * NB + n];
+    const zc* const* arow = ta + (size_t)z * MA;
+    zc acc[SKINNY];
+#pragma unroll
+    for (int m = 0; m < SKINNY; ++m) acc[m] = mk<double>(0, 0);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+        const zc bv = bcol[k];
+#pragma unroll
+        for (int m = 0; m < SKINNY; ++m)
+            if (m < MA) cfmac(acc[m], arow[m][k], bv);
+    }
+    __shared__ zc red[4][SKINNY];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int m = 0; m < SKINNY; ++m) {
+        if (m < MA) {
+            double re = acc[m].x, im = acc[m].y;
+            for (int off = 32; off > 0; off >>= 1) {
+                re += __shfl_down(re, off, 64);
+                im += __shfl_down(im, off, 64);
+            }
+            if (lane == 0) red[wave][m] = mk<double>(re, im);
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < MA) {
+        const int m = threadIdx.x;
+        zc v = red[0][m];
+        for (int w = 1; w < 4; ++w) v = cadd(v, red[w][m]);
+        part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = v;
+    }
+}
+
+// small square-ish products (MA, NB <= 6, e.g. the per-block projected matrices):
+// block (chunk, z) streams every A_m and B_n of its k range exactly once and keeps
+// all MA x NB sums in registers
+constexpr int TINY = 6;
+
+__global__ __launch_bounds__(256) void k_gram_tiny(const zc* const* ta, const zc* const* tb, int MA, int NB,
+                                                   int64_t K, int64_t kchunk, int nchunk, zc* part) {
+    const int z = blockIdx.z;
+    const int chunk = blockIdx.x;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    const zc* A[TINY];
+    const zc* B[TINY];
+#pragma unroll
+    for (int m = 0; m < TINY; ++m) {
+        A[m] = m < MA ? ta[(size_t)z * MA + m] : nullptr;
+        B[m] = m < NB ? tb[(size_t)z * NB + m] : nullptr;
+    }
+    zc acc[TINY][TINY];
+#pragma unroll
+    for (int m = 0; m < TINY; ++m)
+#pragma unroll
+        for (int n = 0; n < TINY; ++n) acc[m][n] = mk<double>(0, 0);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+        zc av[TINY], bv[TINY];
+#pragma unroll
+        for (int m = 0; m < TINY; ++m) {
+            av[m] = m < MA ? A[m][k] : mk<double>(0, 0);
+            bv[m] = m < NB ? B[m][k] : mk<double>(0, 0);
+        }
+#pragma unroll
+        for (int m = 0; m < TINY; ++m)
+#pragma unroll
+            for (int n = 0; n < TINY; ++n)
+                if (m < MA && n < NB) cfmac(acc[m][n], av[m], bv[n]);
+    }
+    __shared__ zc red[4][TINY * TINY];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int m = 0; m < TINY; ++m)
+#pragma unroll
+        for (int n = 0; n < TINY; ++n) {
+            if (m < MA && n < NB) {
+                double re = acc[m][n].x, im = acc[m][n].y;
+                for (int off = 32; off > 0; off >>= 1) {
+                    re += __shfl_down(re, off, 64);
+                    im += __shfl_down(im, off, 64);
+                }
+                if (lane == 0) red[wave][m * TINY + n] = mk<double>(re, im);
+            }
+        }
+    __syncthreads();
+    if ((int)threadIdx.x < MA * NB) {
+        const int m = threadIdx.x / NB, n = threadIdx.x % NB;
+        zc v = red[0][m * TINY + n];
+        for (int w = 1; w < 4; ++w) v = cadd(v, red[w][m * TINY + n]);
+        part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = v;
+    }
+}
+
 // one wave per output element: lanes stride over the chunks, then a shuffle tree
 __global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
     const size_t per = (size_t)MA * NB;
@@ -309,9 +414,12 @@ __device__ inline int rr_pair(int r, int k, int Np) {
 // squared relative size below which an off-diagonal element is not rotated
 constexpr double JACOBI_TOL2 = 1e-28;
 
-template <int NT>
+// USE_LDS: the three work matrices live in LDS; the pointers then derive from the
+// shared array alone, so every access compiles to an LDS instruction (a pointer
+// that may be either LDS or global memory would turn them into flat accesses)
+template <int NT, bool USE_LDS>
 __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
-                                               zc* gwork, int use_lds, int max_sweeps, int* status, int* sweeps_out) {
+                                               zc* gwork, int max_sweeps, int* status, int* sweeps_out) {
     extern __shared__ unsigned char sm[];
     const int z = blockIdx.x;
     const size_t NN = (size_t)N * N;
@@ -319,7 +427,11 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     const zc* H = Hs + z * NN;
     const zc* S = Ss + z * NN;
     // three N x N work matrices: in LDS when they fit, else in global scratch
-    zc* W0 = use_lds ? reinterpret_cast<zc*>(sm) : gwork + z * 3 * NN;
+    zc* W0;
+    if constexpr (USE_LDS)
+        W0 = reinterpret_cast<zc*>(sm);
+    else
+        W0 = gwork + z * 3 * NN;
     zc* Lg = W0;            // Cholesky factor L
     zc* P1 = W0 + NN;
     zc* P2 = W0 + 2 * NN;
@@ -605,13 +717,17 @@ __global__ void k_copy_cols(const zc* Y, int ldy, int ncols, int nrows, zc* out)
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
                      void* scratch, size_t scratch_bytes, hipStream_t s) {
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
-    const bool big = MA > GT && NB > GT;  // 32 x 32 tiles for the wide products
-    const int tile = big ? GT2 : GT, kstep = big ? GK2 : GK;
+    const bool tiny = MA <= TINY && NB <= TINY;  // all outputs of a chunk in one block
+    const bool skinny = !tiny && MA <= SKINNY;    // one block per output column
+    const bool big = !tiny && !skinny && MA > GT && NB > GT;  // 32 x 32 tiles for the wide products
+    const int tile = big ? GT2 : GT, kstep = (tiny || skinny) ? 256 : big ? GK2 : GK;
     int tiles_m = (MA + tile - 1) / tile, tiles_n = (NB + tile - 1) / tile;
-    int ntiles = tiles_m * tiles_n * nz;
-    // at least 256 (64 for the wide tiles) k per chunk, about 1024 blocks in all
+    int ntiles = tiny ? nz : skinny ? NB * nz : tiles_m * tiles_n * nz;
+    // at least 256 (64 for the wide tiles) k per chunk; about 1024 blocks in all
+    // (4096 for the narrow kernel, whose blocks are short)
     int64_t maxchunk = big ? (K + 63) / 64 : (K + 255) / 256;
-    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 1024 / std::max(1, ntiles)));
+    const int target = (tiny || skinny) ? 4096 : 1024;
+    int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, target / std::max(1, ntiles)));
     size_t need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
     while (need > scratch_bytes && nchunk > 1) {
         nchunk /= 2;
@@ -621,9 +737,15 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     int64_t kchunk = (K + nchunk - 1) / nchunk;
     kchunk = (kchunk + kstep - 1) / kstep * kstep;
     nchunk = (int)((K + kchunk - 1) / kchunk);
-    dim3 grid(nchunk, tiles_m * tiles_n, nz);
+    dim3 grid(nchunk, tiny ? 1 : skinny ? NB : tiles_m * tiles_n, nz);
     StageScope ts_(MB_STAGE_GRAM, s);
-    if (big)
+    if (tiny)
+        hipLaunchKernelGGL(k_gram_tiny, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB,
+                           K, kchunk, nchunk, (zc*)scratch);
+    else if (skinny)
+        hipLaunchKernelGGL(k_gram_skinny, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB,
+                           K, kchunk, nchunk, (zc*)scratch);
+    else if (big)
         hipLaunchKernelGGL(k_gram32, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K,
                            kchunk, nchunk, tiles_n, (zc*)scratch);
     else
@@ -709,27 +831,28 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
                        int* status, hipStream_t s, int* sweeps) {
     if (N <= 0 || nz <= 0) return MB_OK;
     size_t lds = 3 * (size_t)N * N * sizeof(zc);
-    int use_lds = lds <= 150000 ? 1 : 0;
+    const bool use_lds = lds <= 150000;
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
     const size_t dyn = use_lds ? lds : 0;
     StageScope ts_(MB_STAGE_SMALLEIG, s);
     const int nt = N <= 12 ? 64 : N <= 48 ? 256 : 1024;
-    if (nt == 256) {
+    auto launch = [&](auto kern, int threads) -> mb_status {
         if (dyn > 65536)
-            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_geneig<256>, dim3(nz), dim3(256), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, use_lds, 60, status, sweeps);
-    } else if (nt == 64) {
-        if (dyn > 65536)
-            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_geneig<64>, dim3(nz), dim3(64), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, use_lds, 60, status, sweeps);
-    } else {
-        if (dyn > 65536)
-            MB_HIP_TRY(hipFuncSetAttribute((const void*)k_geneig<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
-        hipLaunchKernelGGL(k_geneig<1024>, dim3(nz), dim3(1024), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, use_lds, 60, status, sweeps);
-    }
+            MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+        hipLaunchKernelGGL(kern, dim3(nz), dim3(threads), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
+                           (zc*)gwork, 60, status, sweeps);
+        return MB_OK;
+    };
+    mb_status st;
+    if (!use_lds)
+        st = launch(k_geneig<1024, false>, 1024);
+    else if (nt == 64)
+        st = launch(k_geneig<64, true>, 64);
+    else if (nt == 256)
+        st = launch(k_geneig<256, true>, 256);
+    else
+        st = launch(k_geneig<1024, true>, 1024);
+    if (st != MB_OK) return st;
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }

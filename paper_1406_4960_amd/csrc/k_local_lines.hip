@@ -44,6 +44,58 @@ struct LinePlan {
     static constexpr RadixPlan p = make_plan(N);
 };
 
+// Roots of unity exp(2 pi i m / N) as compile-time constants: the angle is reduced
+// to an octant with integer arithmetic and sin / cos of the remaining |x| <= pi/4
+// come from their Taylor series, nested from the smallest term (within 1e-16 of
+// the exact values).  After unrolling every twiddle factor is an immediate operand.
+struct SinCos {
+    double s, c;
+};
+
+constexpr SinCos taylor_sincos(double x) {
+    const double x2 = x * x;
+    double s = 1.0, c = 1.0;
+    for (int k = 13; k >= 1; --k) {
+        s = 1.0 - s * x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        c = 1.0 - c * x2 / ((2.0 * k - 1.0) * (2.0 * k));
+    }
+    return SinCos{x * s, c};
+}
+
+constexpr SinCos unit_root(int m, int n) {
+    m %= n;
+    if (m < 0) m += n;
+    const int o = (8 * m) / n;  // octant of the angle 2 pi m / n
+    const double h = 2.0 * 3.14159265358979323846 / (8.0 * n);
+    const SinCos a = taylor_sincos(h * (double)(8 * m - o * n));        // angle - o pi / 4
+    const SinCos b = taylor_sincos(h * (double)((o + 1) * n - 8 * m));  // (o + 1) pi / 4 - angle
+    switch (o) {
+        case 0: return SinCos{a.s, a.c};
+        case 1: return SinCos{b.c, b.s};
+        case 2: return SinCos{a.c, -a.s};
+        case 3: return SinCos{b.s, -b.c};
+        case 4: return SinCos{-a.s, -a.c};
+        case 5: return SinCos{-b.c, -b.s};
+        case 6: return SinCos{-a.c, a.s};
+        default: return SinCos{-b.s, b.c};
+    }
+}
+
+template <int N>
+struct RootTable {
+    double c[N], s[N];
+    constexpr RootTable() : c(), s() {
+        for (int m = 0; m < N; ++m) {
+            const SinCos v = unit_root(m, N);
+            c[m] = v.c;
+            s[m] = v.s;
+        }
+    }
+};
+
+template <int N>
+__device__ constexpr RootTable<N> kRoots{};
+
 // y_k = sum_r v_r exp(sign 2 pi i r k / R), R in {2, 3, 4, 5}
 template <typename T, int R, int SIGN>
 __device__ __forceinline__ void bfly(cx<T>* v) {
@@ -91,10 +143,10 @@ __device__ __forceinline__ void bfly(cx<T>* v) {
     }
 }
 
-// One Stockham stage in registers: in -> out, span NS so far, radix R.
-// tw[m] = exp(+2 pi i m / N) in LDS (read with constant offsets).
+// One Stockham stage in registers: in -> out, span NS so far, radix R; twiddles
+// exp(SIGN 2 pi i m / N) from the compile-time table.
 template <typename T, int N, int NS, int R, int SIGN>
-__device__ __forceinline__ void line_stage(const cx<T>* in, cx<T>* out, const cx<T>* tw) {
+__device__ __forceinline__ void line_stage(const cx<T>* in, cx<T>* out) {
     constexpr int NBF = N / R;
     constexpr int TS = N / (NS * R);
 #pragma unroll
@@ -106,8 +158,8 @@ __device__ __forceinline__ void line_stage(const cx<T>* in, cx<T>* out, const cx
         if (k != 0) {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                cx<T> w = tw[r * k * TS];
-                if (SIGN < 0) w.y = -w.y;
+                const int m = r * k * TS;
+                const cx<T> w = mk<T>((T)kRoots<N>.c[m], (T)(SIGN < 0 ? -kRoots<N>.s[m] : kRoots<N>.s[m]));
                 v[r] = cmul(v[r], w);
             }
         }
@@ -119,26 +171,30 @@ __device__ __forceinline__ void line_stage(const cx<T>* in, cx<T>* out, const cx
 }
 
 template <typename T, int N, int S, int NS, int SIGN>
-__device__ __forceinline__ void line_fft_rec(cx<T>* a, cx<T>* b, const cx<T>* tw) {
+__device__ __forceinline__ void line_fft_rec(cx<T>* a, cx<T>* b) {
     constexpr RadixPlan P = LinePlan<N>::p;
     if constexpr (S < P.nr) {
         constexpr int R = P.rad[S];
-        line_stage<T, N, NS, R, SIGN>(a, b, tw);
-        line_fft_rec<T, N, S + 1, NS * R, SIGN>(b, a, tw);
+        line_stage<T, N, NS, R, SIGN>(a, b);
+        line_fft_rec<T, N, S + 1, NS * R, SIGN>(b, a);
     }
 }
 
 // in-place transform of v[N] (result back in v)
 template <typename T, int N, int SIGN>
-__device__ __forceinline__ void line_fft(cx<T>* v, const cx<T>* tw) {
+__device__ __forceinline__ void line_fft(cx<T>* v) {
     cx<T> tmp[N];
-    line_fft_rec<T, N, 0, 1, SIGN>(v, tmp, tw);
+    line_fft_rec<T, N, 0, 1, SIGN>(v, tmp);
     constexpr RadixPlan P = LinePlan<N>::p;
     if constexpr (P.nr % 2 == 1) {
 #pragma unroll
         for (int e = 0; e < N; ++e) v[e] = tmp[e];
     }
 }
+
+// LDS bytes ahead of the planes: the list of grid rows that hold sphere points
+template <int N1>
+constexpr size_t LINE_HDR = ((sizeof(int32_t) * N1 + 255) / 256) * 256;
 
 template <typename TI, typename T>
 struct LineArgs {
@@ -149,8 +205,6 @@ struct LineArgs {
     const T* V;
     const int32_t* gmap;
     const int32_t* rows;
-    const cx<T>* tw1;
-    const cx<T>* tw2;
     int nbands, ld, ng, nint, nq, nb, nrows, qp;
     T inv_n;
 };
@@ -164,10 +218,8 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const Li
     constexpr int P2 = N2 + 1;          // padded row stride
     constexpr int PLANE = N1 * P2;
     extern __shared__ unsigned char smem_raw[];
-    cx<T>* tw1 = reinterpret_cast<cx<T>*>(smem_raw);
-    cx<T>* tw2 = tw1 + N1;
-    int32_t* rows = reinterpret_cast<int32_t*>(tw2 + N2);
-    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256);
+    int32_t* rows = reinterpret_cast<int32_t*>(smem_raw);
+    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + LINE_HDR<N1>);
 
     unsigned L = xcd_logical(blockIdx.x, gridDim.x);
     LineArgs<TI, T> a = a0;
@@ -180,8 +232,6 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const Li
     const int s = (int)(L / (unsigned)a.nbands);
     if (s >= a.nint) return;
     const int tid = threadIdx.x;
-    for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
-    for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
     for (int e = tid; e < a.nrows; e += NT) rows[e] = a.rows[e];
 
     const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
@@ -234,7 +284,7 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const Li
             cx<T> v[N2];
 #pragma unroll
             for (int e = 0; e < N2; ++e) v[e] = base[e];
-            line_fft<T, N2, +1>(v, tw2);
+            line_fft<T, N2, +1>(v);
 #pragma unroll
             for (int e = 0; e < N2; ++e) base[e] = v[e];
         }
@@ -248,13 +298,13 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const Li
             cx<T> v[N1];
 #pragma unroll
             for (int e = 0; e < N1; ++e) v[e] = base[e * P2];
-            line_fft<T, N1, +1>(v, tw1);
+            line_fft<T, N1, +1>(v);
 #pragma unroll
             for (int e = 0; e < N1; ++e) {
                 const T w = Vq[e * N2];
                 v[e] = mk<T>(v[e].x * w, v[e].y * w);
             }
-            line_fft<T, N1, -1>(v, tw1);
+            line_fft<T, N1, -1>(v);
 #pragma unroll
             for (int e = 0; e < N1; ++e) base[e * P2] = v[e];
         }
@@ -266,7 +316,7 @@ __global__ __launch_bounds__(NT) void k_local_lines(LineArgs<TI, T> a0, const Li
             cx<T> v[N2];
 #pragma unroll
             for (int e = 0; e < N2; ++e) v[e] = base[e];
-            line_fft<T, N2, -1>(v, tw2);
+            line_fft<T, N2, -1>(v);
 #pragma unroll
             for (int e = 0; e < N2; ++e) base[e] = v[e];
         }
@@ -315,8 +365,6 @@ LineArgs<TI, T> make_line_args(Problem* p, int ik, const void* c, void* part, in
     a.V = (const T*)(dbl ? (const void*)p->d_V : (const void*)p->d_Vf);
     a.gmap = kp.d_gmap;
     a.rows = kp.d_rows;
-    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
-    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
     a.nbands = nbands;
     a.ld = ld;
     a.ng = kp.ng;
@@ -332,7 +380,7 @@ LineArgs<TI, T> make_line_args(Problem* p, int ik, const void* c, void* part, in
 // planes per group: all Gauss planes of an interval when they fit in the LDS budget
 template <typename T, int N1, int N2>
 int planes_per_group(int nq, size_t budget, size_t* lds_out) {
-    const size_t hdr = ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256;
+    const size_t hdr = LINE_HDR<N1>;
     const size_t plane = sizeof(cx<T>) * (size_t)N1 * (N2 + 1);
     int qp = nq;
     while (qp > 1 && hdr + qp * plane > budget) --qp;
@@ -353,8 +401,6 @@ mb_status run_lines(Problem* p, int ik, const void* c, void* part, int nbands, i
     a.V = (const T*)(dbl ? (const void*)p->d_V : (const void*)p->d_Vf);
     a.gmap = kp.d_gmap;
     a.rows = kp.d_rows;
-    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
-    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
     a.nbands = nbands;
     a.ld = ld;
     a.ng = kp.ng;
@@ -379,7 +425,7 @@ mb_status run_lines(Problem* p, int ik, const void* c, void* part, int nbands, i
 template <typename TI, typename T, int N1, int N2>
 mb_status lines_dispatch(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s,
                          size_t budget) {
-    const size_t hdr = ((sizeof(cx<T>) * (N1 + N2) + sizeof(int32_t) * N1 + 255) / 256) * 256;
+    const size_t hdr = LINE_HDR<N1>;
     const size_t plane = sizeof(cx<T>) * (size_t)N1 * (N2 + 1);
     int qp = p->nq;
     while (qp > 1 && hdr + qp * plane > budget) --qp;
