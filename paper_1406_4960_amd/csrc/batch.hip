@@ -3,8 +3,9 @@
 // and the eigensolver run over such a list.
 //
 // The in-plane work (evaluate / FFT / V / FFT / project, Sec. II.B.1) of all items
-// with the same square grid shares one launch of the line-per-thread kernel; items
-// whose grid has no line kernel share one launch of the generic kernel; the banded
+// with the same grid shares one launch of the line-per-thread kernel (small grids) or
+// of the two-step line kernel (larger grids); the remaining items share the generic
+// kernel's launches; the banded
 // combine (kinetic part, local partial sums, projector expansion) is one launch over
 // every item.  Work units of a launch are laid out item after item; each block
 // finds its item by binary search in a table of first units.
@@ -92,6 +93,7 @@ mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUplo
     std::vector<BatchItem> generic;
     for (auto& kv : by_grid) {
         mb_status st = launch_local_lines_batch(kv.second, lp, up, s);
+        if (st == MB_ERR_INVALID_ARG) st = launch_local_split_batch(kv.second, lp, up, s);
         if (st == MB_ERR_INVALID_ARG)
             generic.insert(generic.end(), kv.second.begin(), kv.second.end());
         else if (st != MB_OK)

@@ -170,9 +170,13 @@ __global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a0, const LocalAr
     const int b = (int)(L % (unsigned)a.nbands);
     const int s = (int)(L / (unsigned)a.nbands);
     if (s >= a.nint) return;
+    // the plane is stored with row stride N2 + 1 so that column passes (stride one
+    // row) spread over the LDS banks
     cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw);
     const int npts = a.N1 * a.N2;
-    cx<T>* tw1 = grid + npts;
+    const int P2 = a.N2 + 1;
+    const int nstore = a.N1 * P2;
+    cx<T>* tw1 = grid + nstore;
     cx<T>* tw2 = tw1 + a.N1;
     int32_t* rows = reinterpret_cast<int32_t*>(tw2 + a.N2);
 
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a0, const LocalAr
 
     for (int jq = 0; jq < a.nq; ++jq) {
         const int q = s * a.nq + jq;
-        for (int e = threadIdx.x; e < npts; e += NT) grid[e] = mk<T>(0, 0);
+        for (int e = threadIdx.x; e < nstore; e += NT) grid[e] = mk<T>(0, 0);
         __syncthreads();
         T bv[KORD];
 #pragma unroll
@@ -208,23 +212,25 @@ __global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a0, const LocalAr
                         psi.y = fma(bv[t], (T)cv.y, psi.y);
                     }
                 }
-                grid[a.gmap[g]] = psi;
+                const int gm = a.gmap[g];
+                grid[(gm / a.N2) * P2 + gm % a.N2] = psi;
             }
         }
         __syncthreads();
         // inverse transform: rows (axis 2) that hold G, then all columns (axis 1)
-        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, a.N2, 1, +1);
-        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, a.N2, +1);
+        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, P2, 1, +1);
+        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, P2, +1);
         const T* Vq = a.V + (size_t)q * npts;
         for (int e = threadIdx.x; e < npts; e += NT) {
-            T v = Vq[e];
-            cx<T> u = grid[e];
-            grid[e] = mk<T>(u.x * v, u.y * v);
+            const T v = Vq[e];
+            const int o = (e / a.N2) * P2 + e % a.N2;
+            const cx<T> u = grid[o];
+            grid[o] = mk<T>(u.x * v, u.y * v);
         }
         __syncthreads();
         // forward transform: all columns, then the rows that hold G
-        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, a.N2, -1);
-        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, a.N2, 1, -1);
+        fft_axis<T, NT>(grid, tw1, a.p1, a.N2, nullptr, 1, P2, -1);
+        fft_axis<T, NT>(grid, tw2, a.p2, a.nrows, rows, P2, 1, -1);
         T wb[KORD];
 #pragma unroll
         for (int t = 0; t < KORD; ++t) wb[t] = a.wbval[q * KORD + t] * a.inv_n;
@@ -232,7 +238,8 @@ __global__ __launch_bounds__(NT) void k_local(LocalArgs<TI, T> a0, const LocalAr
         for (int k = 0; k < MAXG; ++k) {
             int g = threadIdx.x + k * NT;
             if (g < a.ng) {
-                cx<T> u = grid[a.gmap[g]];
+                const int gm = a.gmap[g];
+                const cx<T> u = grid[(gm / a.N2) * P2 + gm % a.N2];
 #pragma unroll
                 for (int t = 0; t < KORD; ++t) {
                     acc[t][k].x = fma(wb[t], u.x, acc[t][k].x);
@@ -317,7 +324,7 @@ mb_status local_batch_impl(const std::vector<BatchItem>& items, TableUploader& u
         if (it.p->order != KORD) return MB_ERR_INVALID_ARG;
         if (it.nbands == 0) continue;
         LocalArgs<TI, T> a = make_local_args<TI, T>(it.p, it.ik, it.c, it.part, it.nbands, it.ld);
-        size_t l = sizeof(cx<T>) * ((size_t)a.N1 * a.N2 + a.N1 + a.N2) + sizeof(int32_t) * a.nrows;
+        size_t l = sizeof(cx<T>) * ((size_t)a.N1 * (a.N2 + 1) + a.N1 + a.N2) + sizeof(int32_t) * a.nrows;
         if (l > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
         const int work = std::max(max_stage_work(a.p2, a.nrows), max_stage_work(a.p1, a.N2));
         const int v = local_variant(work, a.ng);
@@ -370,7 +377,7 @@ template <typename TI, typename T>
 mb_status local_impl(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
     const KPoint& kp = p->kp[ik];
     LocalArgs<TI, T> a = make_local_args<TI, T>(p, ik, c, part, nbands, ld);
-    size_t lds = sizeof(cx<T>) * ((size_t)p->N1 * p->N2 + p->N1 + p->N2) + sizeof(int32_t) * a.nrows;
+    size_t lds = sizeof(cx<T>) * ((size_t)p->N1 * (p->N2 + 1) + p->N1 + p->N2) + sizeof(int32_t) * a.nrows;
     if (lds > 163840) return set_error(MB_ERR_INVALID_ARG, "in-plane grid does not fit in LDS");
     int work = std::max(max_stage_work(p->plan2, a.nrows), max_stage_work(p->plan1, p->N2));
     // smallest block that covers the FFT stages and the G set
@@ -426,10 +433,13 @@ __global__ void k_vgrid(double* V, float* Vf, const VTerm* terms, int nterms, in
 mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
                        hipStream_t s) {
     if (p->order != KORD) return set_error(MB_ERR_INVALID_ARG, "GPU kernels support order 4 only");
-    // line-per-thread kernel for small grids unless MBKS_LOCAL_KERNEL=generic
+    // line-per-thread kernel for small grids, two-step line kernel for larger ones;
+    // MBKS_LOCAL_KERNEL=generic forces the generic kernel (used to cross-check them)
     const char* sel = getenv("MBKS_LOCAL_KERNEL");
     if (!sel || std::string(sel) != "generic") {
         mb_status st = launch_local_lines(p, ik, c, part, nbands, ld, prec, s);
+        if (st != MB_ERR_INVALID_ARG) return st;
+        st = launch_local_split(p, ik, c, part, nbands, ld, prec, s);
         if (st != MB_ERR_INVALID_ARG) return st;
     }
     if (prec == 0) return local_impl<double, double>(p, ik, c, part, nbands, ld, s);

@@ -142,6 +142,8 @@ mb_status launch_vgrid(Problem* p, hipStream_t s);
 mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
                        int prec, hipStream_t s);
 // line-per-thread variant for small grids; MB_ERR_INVALID_ARG = no variant for this grid
+mb_status launch_local_split(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
+                             hipStream_t s);
 mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
                              int prec, hipStream_t s);
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
@@ -194,6 +196,8 @@ struct TableUploader {
 
 // each returns MB_ERR_INVALID_ARG (without a message) when it cannot take the items
 mb_status launch_local_lines_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up,
+                                   hipStream_t s);
+mb_status launch_local_split_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up,
                                    hipStream_t s);
 mb_status launch_local_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s);
 mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s);
