@@ -70,8 +70,11 @@ def traffic_record(name):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1406_4960_amd", "csrc", rec.get("source", "k_local.hip")), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    files = rec.get("sources", [rec.get("source", "k_local.hip")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1406_4960_amd", "csrc", f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec
 

@@ -168,7 +168,7 @@ typedef struct {
     int32_t krylov_global;/* Krylov vectors of the global cycle (>= 0) */
     int32_t max_iter;     /* grand cycles (>= 1) */
     double tol;           /* converged when every ||H x - eps S x||_2 <= tol (x^H S x = 1) */
-    double sigma;         /* shift of the kinetic preconditioner (T + sigma S)^{-1}, Ha; <= 0: S^{-1} */
+    double sigma;         /* shift of the kinetic preconditioner (T + sigma S)^{-1}, Ha (default 0.05); <= 0: S^{-1} */
     double switch_tol;    /* MB_FP32/MB_BF16X3: residual at which the solve continues in FP64 */
     uint64_t seed;        /* seed of the random start when x0 is NULL */
 } mb_lanczos_opts;

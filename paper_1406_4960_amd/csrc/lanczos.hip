@@ -418,7 +418,7 @@ extern "C" void mb_lanczos_default_opts(mb_lanczos_opts* o) {
     o->krylov_global = 2;
     o->max_iter = 300;
     o->tol = 1e-7;
-    o->sigma = 1.0;
+    o->sigma = 0.05;
     o->switch_tol = 1e-4;
     o->seed = 14064960ull;
 }
