@@ -438,6 +438,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     const int tid = threadIdx.x;
     __shared__ int bad;
     __shared__ int s_more;
+    __shared__ int s_rot[2];
     __shared__ unsigned char dead[256];  // directions numerically in the span of earlier ones
     if (tid == 0) bad = 0;
     // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
@@ -533,7 +534,10 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         // |a_pq| > 1e-14 (|a_pp| + |a_qq|): a smaller element changes the eigenvalues by
         // at most |a_pq|^2 / gap (or |a_pq| for a cluster), far below FP64 rounding of
         // the matrix itself, and rotating it only reshuffles rounding noise
-        if (tid == 0) s_more = 0;
+        if (tid == 0) {
+            s_more = 0;
+            s_rot[0] = 0;
+        }
         __syncthreads();
         int more = 0;
         for (int e = tid; e < NNi; e += NT) {
@@ -549,7 +553,11 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         if (!s_more) break;
         for (int r = 0; r < Np - 1; ++r) {
             // rotation of every pair of this round from its pivots a_pp, a_qq, a_pq
-            // (the pairs are disjoint, so no pair's pivots change within the round)
+            // (the pairs are disjoint, so no pair's pivots change within the round).
+            // s_rot[r & 1] records whether any pair rotates; the flag of the next round
+            // is cleared here, before this round's barrier, so it is clear before any
+            // thread can set it
+            if (tid == 0) s_rot[(r + 1) & 1] = 0;
             for (int pi = tid; pi < npair; pi += NT) {
                 int p, q;
                 if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
@@ -575,8 +583,10 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
                     }
                 }
                 rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
+                if (sr != 0.0 || si != 0.0) s_rot[r & 1] = 1;
             }
             __syncthreads();
+            if (!s_rot[r & 1]) continue;  // nothing rotates this round (uniform branch)
             // rows p, q of every pair:
             //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
             for (int e = tid; e < npair * N; e += NT) {

@@ -19,7 +19,7 @@ namespace mb {
 namespace {
 
 constexpr int KORD = 4;
-constexpr int CH = 8;  // rows per thread in the combine kernel
+constexpr int CH = 4;  // rows per thread in the combine kernel
 
 template <typename TI, typename T>
 struct CombineArgs {
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
 // The recurrence is sequential in i; the loads of each chunk of U rows are issued
 // together ahead of the chunk's arithmetic so their latencies overlap.  r may
 // equal x (rows are read before they are overwritten).
-template <typename TI, int U = 8>
+template <typename TI, int U = 4>
 __device__ inline void band_solve(const cx<TI>* r, cx<TI>* x, const double* lf, int nb, int ld, int g,
                                   int per_g, double theta, const cx<TI>* sv) {
     auto L = [&](int row, int d) -> double {
