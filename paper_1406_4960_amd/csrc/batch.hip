@@ -80,8 +80,10 @@ mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUplo
             it.proj = nullptr;
             continue;
         }
-        if (lp == 0)
-            BT_TRY(launch_nl_project(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, 0, s));
+        // as in the single-item operator: matrix cores for BF16x3 and for FP32 with at
+        // least 64 projectors, the vector kernel otherwise
+        if (prec != 3 && (lp == 0 || it.p->np < 64))
+            BT_TRY(launch_nl_project(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, lp, s));
         else
             BT_TRY(launch_nl_project_mfma(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, prec == 3 ? 2 : 1, false,
                                           s));

@@ -192,6 +192,7 @@ def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
     d = workloads.CONFIGS[cfg]()
     p, dm, _ = _setup(d, 1)
     x = random_lib_block(42, 17, dm["nb"], dm["ng"], dm["ld"])
+    monkeypatch.setenv("MBKS_NL_KERNEL", "mfma")
     y_mfma = _run(p, "hpsi", 1, x, "fp32")
     monkeypatch.setenv("MBKS_NL_KERNEL", "vector")
     y_vec = _run(p, "hpsi", 1, x, "fp32")
