@@ -21,6 +21,8 @@ Printed JSON line:
   batched_48       the 48-problem uneven batch: hpsi_apply_batched throughput per
                    precision, and mixed vs FP64 time to the eigenpairs of its first
                    problems
+  supercell_2x2    the 2x2 supercell (72x72 grid, 64 bands, 4 k-points): time to its
+                   eigenpairs mixed vs FP64
   roofline         the fused local-potential kernel (dominant kernel), from its
                    launches in the FP64 hpsi leg
   cpu_baseline     the CPU FP64 oracle's matrix-free H application, bounded sample
@@ -168,6 +170,36 @@ def batched_leg(args, torch, mbks, workloads):
     return res
 
 
+def c3_leg(torch, mbks, workloads):
+    """The 2x2 supercell (72x72 grid, ~1,900 G, 96 splines, 8 atoms, 64 bands, 4
+    k-points): time to the eigenpairs of all k-points (solved together) in the mixed
+    form and in plain FP64, and the largest eigenvalue difference between the two."""
+    d = workloads.graphene_2x2()
+    p = mbks.Problem(d, device=0)
+    nk, M = len(d["kpts"]), d["nbands"]
+    b = mbks.Batch([(p, ik) for ik in range(nk)])
+    o = p.default_opts()
+    o.max_iter = 1
+    b.lanczos_lowest([M] * nk, "fp64", opts=o, raise_not_converged=False)  # workspaces, factors
+    res = {"workload": d["name"], "kpoints": nk, "bands": M}
+    eigs = {}
+    for prec in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, xs, infos, st = b.lanczos_lowest([M] * nk, prec, raise_not_converged=False)
+        torch.cuda.synchronize()
+        res[prec] = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": st,
+                     "iters": [i["iters"] for i in infos], "max_resid": max(i["max_resid"] for i in infos)}
+        eigs[prec] = e
+        del xs
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
+    res["max_eig_diff_mixed_vs_fp64"] = max(float(np.max(np.abs(a - c))) for a, c in zip(eigs["fp32"], eigs["fp64"]))
+    log("c3", res)
+    b.close()
+    p.close()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +212,7 @@ def main(argv=None):
     ap.add_argument("--hpsi-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
                     help="problems of the uneven batch whose eigenpairs are timed (all their k-points)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -336,6 +369,7 @@ def main(argv=None):
     roofline["step_stage_ms"] = {k: round(v[0], 3) for k, v in tot.items()}
 
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
+    c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -369,6 +403,7 @@ def main(argv=None):
         "fp64": fp64,
         "hpsi": {k: {kk: vv for kk, vv in v.items() if kk != "stage_raw"} for k, v in hp.items()},
         "batched_48": batched,
+        "supercell_2x2": c3,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
