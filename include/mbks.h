@@ -171,6 +171,8 @@ typedef struct {
     double sigma;         /* shift of the kinetic preconditioner (T + sigma S)^{-1}, Ha (default 0.05); <= 0: S^{-1} */
     double switch_tol;    /* MB_FP32/MB_BF16X3: residual at which the solve continues in FP64 */
     uint64_t seed;        /* seed of the random start when x0 is NULL */
+    int32_t extra;        /* buffer vectors iterated above the nev wanted ones (not required to
+                             converge); < 0: min(16, max(4, nev / 4)) */
 } mb_lanczos_opts;
 
 typedef struct {

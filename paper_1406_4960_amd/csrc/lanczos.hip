@@ -45,6 +45,7 @@ struct Solver {
     int ik;
     hipStream_t s;
     int M, b, nbl, m, mA, NG, NR;
+    int nwant;  // leading vectors whose residuals decide convergence (the rest are buffer)
     int ld;
     int64_t K;  // complex elements per vector
     size_t vbytes;
@@ -203,7 +204,7 @@ struct Solver {
     mb_status global_cycle(int prec) {
         if (mA == 0) return global_rr(M);
         int v = 0;
-        for (int j = 1; j < M; ++j)
+        for (int j = 1; j < nwant; ++j)
             if (h_resid[j] > h_resid[v]) v = j;
         // Krylov vectors in X[M .. M+mA)
         LZ_TRY(launch_prec_apply(p, ik, vec(HX, v), vec(SX, v), theta + v, nullptr, vec(X, M), 1, ld, s));
@@ -238,20 +239,29 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.p = p;
     S.ik = ik;
     S.s = s;
-    S.M = nev;
-    S.b = std::max(1, std::min(o.block, nev));
-    while (nev % S.b) --S.b;
-    S.nbl = nev / S.b;
+    // nbuf buffer vectors above the nev wanted ones: iterated like the others but not
+    // required to converge, so a cluster straddling the nev-th root does not stall
+    // the iteration
+    const int64_t basis = (int64_t)kp.ng * p->nb;
+    int nbuf = o.extra >= 0 ? o.extra : std::min(16, std::max(4, nev / 4));
+    nbuf = (int)std::max<int64_t>(0, std::min<int64_t>(nbuf, basis - nev));
+    const int M = nev + nbuf;
+    S.M = M;
+    S.nwant = nev;
+    S.b = std::max(1, std::min(o.block, M));
+    while (M % S.b) --S.b;
+    S.nbl = M / S.b;
     S.m = std::max(1, o.krylov);
     S.mA = std::max(0, o.krylov_global);
-    S.NG = nev + S.mA;
+    S.NG = M + S.mA;
     S.NR = S.b + S.m;
     S.ld = kp.ld;
     S.K = (int64_t)p->nb * kp.ld;
     S.vbytes = (size_t)S.K * 16;
     if (S.NG > 256 || S.NR > 64 || S.b > 32)
-        return set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: nev + krylov_global must be <= 256, block + krylov <= 64");
-    if ((int64_t)nev > (int64_t)kp.ng * p->nb) return set_error(MB_ERR_INVALID_ARG, "nev exceeds the basis size");
+        return set_error(MB_ERR_INVALID_ARG,
+                         "lanczos_lowest: nev + buffer + krylov_global must be <= 256, block + krylov <= 64");
+    if ((int64_t)nev > basis) return set_error(MB_ERR_INVALID_ARG, "nev exceeds the basis size");
 
     // vector workspace
     size_t nvec = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl;
@@ -355,8 +365,12 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     LZ_TRY(launch_prec_factor(p, ik, o.sigma, s));
 
     // start vectors
-    if (x0) MB_HIP_TRY(hipMemcpyAsync(S.X, x0, (size_t)S.M * S.vbytes, hipMemcpyDeviceToDevice, s));
-    else LZ_TRY(dense_random(S.X, S.M, p->nb, S.ld, kp.ng, o.seed, s));
+    if (x0) {
+        MB_HIP_TRY(hipMemcpyAsync(S.X, x0, (size_t)nev * S.vbytes, hipMemcpyDeviceToDevice, s));
+        if (nbuf > 0) LZ_TRY(dense_random(S.vec(S.X, nev), nbuf, p->nb, S.ld, kp.ng, o.seed, s));
+    } else {
+        LZ_TRY(dense_random(S.X, S.M, p->nb, S.ld, kp.ng, o.seed, s));
+    }
     int cur = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 2 : 4;
     LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, cur));
     LZ_TRY(S.global_rr(S.M));
@@ -367,7 +381,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     int stall = 0;
     for (; it < o.max_iter; ++it) {
         LZ_TRY(S.residuals());
-        double mx = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+        double mx = *std::max_element(S.h_resid.begin(), S.h_resid.begin() + nev);
         if (cur != 0) {
             if (mx < 0.9 * best) { best = mx; stall = 0; } else ++stall;
             if (mx <= o.switch_tol || stall >= 4) {
@@ -376,7 +390,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
                 LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, 0));
                 LZ_TRY(S.global_rr(S.M));
                 LZ_TRY(S.residuals());
-                mx = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+                mx = *std::max_element(S.h_resid.begin(), S.h_resid.begin() + nev);
             }
         }
         if (cur == 0 && mx <= o.tol) {
@@ -395,15 +409,15 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
         LZ_TRY(S.residuals());
         set_error(MB_ERR_NOT_CONVERGED, "lanczos_lowest: max_iter reached");
     }
-    if (xout) MB_HIP_TRY(hipMemcpyAsync(xout, S.X, (size_t)S.M * S.vbytes, hipMemcpyDeviceToDevice, s));
+    if (xout) MB_HIP_TRY(hipMemcpyAsync(xout, S.X, (size_t)nev * S.vbytes, hipMemcpyDeviceToDevice, s));
     MB_HIP_TRY(hipStreamSynchronize(s));
-    if (eig) std::memcpy(eig, S.h_theta.data(), S.M * sizeof(double));
+    if (eig) std::memcpy(eig, S.h_theta.data(), nev * sizeof(double));
     if (info) {
         info->iters = it;
         info->iters_low = it_low;
         info->h_applies = S.applies;
         info->h_applies_low = S.applies_low;
-        info->max_resid = *std::max_element(S.h_resid.begin(), S.h_resid.end());
+        info->max_resid = *std::max_element(S.h_resid.begin(), S.h_resid.begin() + nev);
         info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return result;
@@ -421,6 +435,7 @@ extern "C" void mb_lanczos_default_opts(mb_lanczos_opts* o) {
     o->sigma = 0.05;
     o->switch_tol = 1e-4;
     o->seed = 14064960ull;
+    o->extra = -1;
 }
 
 extern "C" mb_status lanczos_lowest(mb_problem* h, int ik, int nev, mb_precision prec, const mb_lanczos_opts* opts,
