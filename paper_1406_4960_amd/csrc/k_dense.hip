@@ -414,10 +414,12 @@ __device__ inline int rr_pair(int r, int k, int Np) {
 // squared relative size below which an off-diagonal element is not rotated
 constexpr double JACOBI_TOL2 = 1e-28;
 
-// USE_LDS: the three work matrices live in LDS; the pointers then derive from the
-// shared array alone, so every access compiles to an LDS instruction (a pointer
-// that may be either LDS or global memory would turn them into flat accesses)
-template <int NT, bool USE_LDS>
+// MODE 2: the three work matrices (Cholesky factor L, A, V) live in LDS; MODE 1: A,
+// which every Jacobi phase reads and writes, lives in LDS and L, V in global scratch
+// (problems too large for all three); MODE 0: all in global scratch.  Pointers that
+// derive from the shared array alone compile to LDS instructions (a pointer that may
+// be either LDS or global memory would turn them into flat accesses).
+template <int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
                                                zc* gwork, int max_sweeps, int* status, int* sweeps_out) {
     extern __shared__ unsigned char sm[];
@@ -427,14 +429,23 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     const zc* H = Hs + z * NN;
     const zc* S = Ss + z * NN;
     // three N x N work matrices: in LDS when they fit, else in global scratch
-    zc* W0;
-    if constexpr (USE_LDS)
-        W0 = reinterpret_cast<zc*>(sm);
-    else
-        W0 = gwork + z * 3 * NN;
-    zc* Lg = W0;            // Cholesky factor L
-    zc* P1 = W0 + NN;
-    zc* P2 = W0 + 2 * NN;
+    zc* const G0 = gwork + z * 3 * NN;
+    zc* Lg;  // Cholesky factor L
+    zc* P1;  // work matrix, then A
+    zc* P2;  // work matrix, then V
+    if constexpr (MODE == 2) {
+        Lg = reinterpret_cast<zc*>(sm);
+        P1 = Lg + NN;
+        P2 = Lg + 2 * NN;
+    } else if constexpr (MODE == 1) {
+        P1 = reinterpret_cast<zc*>(sm);
+        Lg = G0;
+        P2 = G0 + 2 * NN;
+    } else {
+        Lg = G0;
+        P1 = G0 + NN;
+        P2 = G0 + 2 * NN;
+    }
     const int tid = threadIdx.x;
     __shared__ int bad;
     __shared__ int s_more;
@@ -840,10 +851,10 @@ mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed,
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
                        int* status, hipStream_t s, int* sweeps) {
     if (N <= 0 || nz <= 0) return MB_OK;
-    size_t lds = 3 * (size_t)N * N * sizeof(zc);
-    const bool use_lds = lds <= 150000;
     if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
-    const size_t dyn = use_lds ? lds : 0;
+    const size_t nn16 = (size_t)N * N * sizeof(zc);
+    const int mode = 3 * nn16 <= 150000 ? 2 : nn16 <= 150000 ? 1 : 0;
+    const size_t dyn = mode == 2 ? 3 * nn16 : mode == 1 ? nn16 : 0;
     StageScope ts_(MB_STAGE_SMALLEIG, s);
     // one wave for the smallest problems; otherwise 1024 threads (measured on N = 16-34:
     // 1.0-1.5x faster than 256 threads, 1.3-2.7x faster than 64)
@@ -856,12 +867,14 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
         return MB_OK;
     };
     mb_status st;
-    if (!use_lds)
-        st = launch(k_geneig<1024, false>, 1024);
+    if (mode == 0)
+        st = launch(k_geneig<1024, 0>, 1024);
+    else if (mode == 1)
+        st = launch(k_geneig<1024, 1>, 1024);
     else if (nt == 64)
-        st = launch(k_geneig<64, true>, 64);
+        st = launch(k_geneig<64, 2>, 64);
     else
-        st = launch(k_geneig<1024, true>, 1024);
+        st = launch(k_geneig<1024, 2>, 1024);
     if (st != MB_OK) return st;
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
