@@ -17,7 +17,8 @@ Printed JSON line:
   value            H band-vectors applied per second over the timed steps
   ms_per_step      time to the 4 x 32 eigenpairs (all k-points)
   fp64             the same step in plain FP64 (time, eigenvalue errors)
-  hpsi             pure hpsi_apply throughput (32 bands x 4 k per call) in FP64 / FP32
+  hpsi             pure hpsi_apply throughput (32 bands x 4 k per call) in FP64 / FP32,
+                   eager and replayed from a captured HIP graph
   batched_48       the 48-problem uneven batch: hpsi_apply_batched throughput per
                    precision, and mixed vs FP64 time to the eigenpairs of its first
                    problems
@@ -268,8 +269,23 @@ def main(argv=None):
         ms = e0.elapsed_time(e1)
         st = mbks.timer_read()
         mbks.timer_enable(False)
+        # the same calls captured once in a HIP graph and replayed
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            for ik in range(nk):
+                p.hpsi(ik, xs[ik], ys[ik], prec)
+        gr.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.hpsi_reps):
+            gr.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1)
+        del gr
         hp[prec] = {"band_vectors_per_s": args.hpsi_reps * nk * M / (ms * 1e-3),
                     "ms_per_call": ms / (args.hpsi_reps * nk),
+                    "graph_band_vectors_per_s": args.hpsi_reps * nk * M / (ms_graph * 1e-3),
                     "stages_ms": {k: round(v[0], 4) for k, v in st.items() if v[1]},
                     "stage_raw": st}
         log("hpsi", prec, {k: v for k, v in hp[prec].items() if k != "stage_raw"})

@@ -122,3 +122,22 @@ def test_lanczos_graphene_full(ik, prec, tol):
     orth, res = _check_vectors(p, ik, x, eig, d["nbands"])
     assert orth < 1e-10 and np.max(res) < 1e-6
     p.close()
+
+
+@pytest.mark.parametrize("extra", [0, 3, 8])
+def test_lanczos_buffer_vectors(extra):
+    # buffer vectors above the wanted roots change the iteration, not the result
+    d = workloads.micro(seed=3, natoms=2, mmax=2, nint=11, grid=8, kfrac=(0.23, -0.31))
+    print(f"[case] lanczos buffer {extra}", flush=True)
+    nev = 7
+    ref = solve.solve_problem(d, 0, nev=nev)[3]
+    p = mbks.Problem(d, device=0)
+    o = p.default_opts()
+    o.extra = extra
+    eig, x, info, st = p.lanczos_lowest(0, nev, "fp64", opts=o)
+    assert st == 0, info
+    assert eig.shape == (nev,) and x.shape[0] == nev
+    assert np.max(np.abs(eig - ref)) < 1e-8
+    orth, res = _check_vectors(p, 0, x, eig, nev)
+    assert orth < 1e-10 and np.max(res) < 1e-6
+    p.close()
