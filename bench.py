@@ -244,6 +244,12 @@ def main(argv=None):
     dims = [p.dims(ik) for ik in range(nk)]
     log("workload", desc["name"], dims[0])
 
+    # ---- kernel choices measured per k-point (mb_autotune), kept for the run ----
+    tuned = {}
+    for prec in ("fp64", "fp32"):
+        tuned[prec] = [p.autotune(ik, M, prec) for ik in range(nk)]
+    log("autotune", tuned)
+
     # ---- pure H application throughput (inputs resident in HBM) ---------------
     hp = {}
     for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64)):
@@ -418,6 +424,7 @@ def main(argv=None):
         "h_applies_per_step": applies / args.steps,
         "fp64": fp64,
         "hpsi": {k: {kk: vv for kk, vv in v.items() if kk != "stage_raw"} for k, v in hp.items()},
+        "autotune_k0": {k: v[0] for k, v in tuned.items()},
         "batched_48": batched,
         "supercell_2x2": c3,
         "roofline": roofline,

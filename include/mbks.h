@@ -157,6 +157,28 @@ mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nban
 mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
+/* Autotuner of the operator's kernel choices for one k-point, block size and
+ * precision: times the local-potential kernels that support the grid (the
+ * line-per-thread kernel at LDS budgets of 22-160 KB per workgroup, i.e. 1 to all
+ * Gauss planes of an interval per workgroup; the two-step line kernel; the generic
+ * kernel) and, in FP32, the two projector paths (vector kernel, matrix cores), on
+ * nbands scratch vectors, and makes the fastest the choice of later hpsi_apply and
+ * eigensolver calls on that k-point (MB_FP32 / MB_BF16X3 also set it for the
+ * eigensolver's FP32 arithmetic on complex128 vectors).  A measurement call: it
+ * allocates and frees scratch memory and synchronises `stream`; it must not overlap
+ * other calls on the same k-point.  info may be NULL. */
+typedef struct {
+    int32_t local_kernel;     /* 0 line-per-thread, 1 two-step line, 2 generic */
+    int32_t lds_budget_kb;    /* line-per-thread kernel: LDS budget per workgroup */
+    int32_t nl_matrix_cores;  /* FP32 projectors: 1 matrix cores, 0 vector kernel, -1 not tuned */
+    int32_t candidates;       /* configurations timed */
+    double local_ms;          /* chosen local kernel, per call of nbands vectors */
+    double local_default_ms;  /* the untuned choice, per call */
+    double nl_ms;             /* chosen projector path, per call (0 if not tuned) */
+} mb_tune_info;
+mb_status mb_autotune(mb_problem* p, int ik, int64_t nbands, mb_precision prec, void* stream,
+                      mb_tune_info* info);
+
 /* x = S^{-1} r by forward and back substitution with the banded Cholesky factor
  * of S_z, shared by every G and band.  x may equal r (in place). */
 mb_status s_solve(mb_problem* p, int ik, const void* r, void* x, int64_t nbands, int64_t ld,

@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, device upload of the set-up tables and
 // composition of the operator kernels on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -214,6 +215,8 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         // MBKS_NL_KERNEL=vector / =mfma forces one FP32 path (used to cross-check them).
         const char* sel = getenv("MBKS_NL_KERNEL");
         bool vector_path = lp == 0 || p->np < 64;
+        const KPoint::Tune& tn = kp.tune[lp];
+        if (tn.set && tn.nl_mfma >= 0 && lp != 0) vector_path = tn.nl_mfma == 0;
         if (sel && std::string(sel) == "vector") vector_path = true;
         if (sel && std::string(sel) == "mfma" && lp != 0) vector_path = false;
         if (prec >= 3) vector_path = false;
@@ -386,6 +389,109 @@ mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply: c and y overlap");
     return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld,
                        prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream);
+}
+
+mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, void* stream, mb_tune_info* info) {
+    mb::Problem* p = mb::problem_of(h);
+    if (!p) return set_error(MB_ERR_INVALID_ARG, "mb_autotune: problem is NULL");
+    if (p->device < 0) return set_error(MB_ERR_NO_DEVICE, "mb_autotune: host-only problem");
+    if (ik < 0 || ik >= (int)p->kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_autotune: ik out of range");
+    if (nbands < 1 || nbands > 4096) return set_error(MB_ERR_INVALID_ARG, "mb_autotune: nbands must be 1..4096");
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "mb_autotune: unknown precision");
+    if (p->order != 4) return set_error(MB_ERR_INVALID_ARG, "mb_autotune: GPU kernels support order 4 only");
+    hipStream_t s = (hipStream_t)stream;
+    mb::KPoint& kp = p->kp[ik];
+    const int cls = prec == MB_FP64 ? 0 : 1;
+    const int nb = (int)nbands, ld = kp.ld;
+    const size_t csz = cls == 0 ? 16 : 8;
+    void *c = nullptr, *part = nullptr, *proj = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    mb_status st = MB_OK;
+    const mb::KPoint::Tune saved = kp.tune[cls];
+    auto cleanup = [&]() {
+        if (c) (void)hipFree(c);
+        if (part) (void)hipFree(part);
+        if (proj) (void)hipFree(proj);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipMalloc(&c, (size_t)nb * p->nb * ld * csz) != hipSuccess ||
+        hipMalloc(&part, (size_t)nb * p->nint * 4 * ld * csz) != hipSuccess ||
+        hipMalloc(&proj, std::max<size_t>(16, (size_t)nb * p->np * csz)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return set_error(MB_ERR_OOM, "mb_autotune: scratch allocation failed");
+    }
+    (void)hipMemsetAsync(c, 0, (size_t)nb * p->nb * ld * csz, s);
+    // average time of 3 calls after one warm-up; < 0 when the configuration is unsupported
+    auto timeit = [&](auto&& call) -> double {
+        mb_status r = call();
+        if (r == MB_ERR_INVALID_ARG) return -1.0;
+        if (r != MB_OK) { st = r; return -1.0; }
+        (void)hipEventRecord(e0, s);
+        for (int rep = 0; rep < 3; ++rep) {
+            r = call();
+            if (r != MB_OK) { st = r; return -1.0; }
+        }
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) { st = set_error(MB_ERR_HIP, "mb_autotune: event"); return -1.0; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms / 3.0;
+    };
+    // each candidate through its own launcher, which reports a grid it cannot take
+    auto local_with = [&](int kind, int budget) {
+        if (kind == 0) return mb::launch_local_lines(p, ik, c, part, nb, ld, cls, s, budget);
+        if (kind == 1) return mb::launch_local_split(p, ik, c, part, nb, ld, cls, s);
+        kp.tune[cls] = mb::KPoint::Tune{1, 2, 110, -1};
+        return mb::launch_local(p, ik, c, part, nb, ld, cls, s);
+    };
+    // the untuned choice first
+    kp.tune[cls] = mb::KPoint::Tune{};
+    const double t_default = timeit([&]() { return mb::launch_local(p, ik, c, part, nb, ld, cls, s); });
+    int best_kind = -1, best_budget = 110, ncand = 0;
+    double best = 1e300;
+    const int budgets[] = {22, 44, 66, 88, 110, 160};
+    for (int bk : budgets) {
+        const double t = timeit([&]() { return local_with(0, bk); });
+        if (st != MB_OK) break;
+        if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = 0; best_budget = bk; } }
+    }
+    for (int kind = 1; kind <= 2 && st == MB_OK; ++kind) {
+        const double t = timeit([&]() { return local_with(kind, 110); });
+        if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = kind; best_budget = 110; } }
+    }
+    int nl_mfma = -1;
+    double nl_best = 0.0;
+    if (st == MB_OK && p->np > 0 && cls == 1) {
+        const double tv = timeit([&]() { return mb::launch_nl_project(p, ik, c, proj, nb, ld, 1, s); });
+        const double tm = timeit([&]() { return mb::launch_nl_project_mfma(p, ik, c, proj, nb, ld, 1, false, s); });
+        if (st == MB_OK && tv >= 0 && tm >= 0) {
+            nl_mfma = tm < tv ? 1 : 0;
+            nl_best = std::min(tv, tm);
+            ncand += 2;
+        }
+    }
+    if (st != MB_OK || best_kind < 0) {
+        kp.tune[cls] = saved;
+        cleanup();
+        return st != MB_OK ? st : set_error(MB_ERR_INVALID_ARG, "mb_autotune: no local kernel ran");
+    }
+    kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, nl_mfma};
+    if (cls == 1) kp.tune[2] = kp.tune[1];  // complex128 vectors with FP32 arithmetic (mixed solver)
+    cleanup();
+    if (info) {
+        info->local_kernel = best_kind;
+        info->lds_budget_kb = best_budget;
+        info->nl_matrix_cores = nl_mfma;
+        info->candidates = ncand;
+        info->local_ms = best;
+        info->local_default_ms = t_default;
+        info->nl_ms = nl_best;
+    }
+    return MB_OK;
 }
 
 mb_status spsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,

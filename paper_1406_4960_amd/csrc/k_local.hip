@@ -433,10 +433,19 @@ __global__ void k_vgrid(double* V, float* Vf, const VTerm* terms, int nterms, in
 mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
                        hipStream_t s) {
     if (p->order != KORD) return set_error(MB_ERR_INVALID_ARG, "GPU kernels support order 4 only");
-    // line-per-thread kernel for small grids, two-step line kernel for larger ones;
+    // line-per-thread kernel for small grids, two-step line kernel for larger ones, unless
+    // mb_autotune measured another choice for this k-point and precision;
     // MBKS_LOCAL_KERNEL=generic forces the generic kernel (used to cross-check them)
+    const KPoint::Tune& tn = p->kp[ik].tune[prec];
     const char* sel = getenv("MBKS_LOCAL_KERNEL");
-    if (!sel || std::string(sel) != "generic") {
+    const bool generic_only = sel && std::string(sel) == "generic";
+    if (!generic_only && tn.set && tn.kind == 0) {
+        mb_status st = launch_local_lines(p, ik, c, part, nbands, ld, prec, s, tn.budget_kb);
+        if (st != MB_ERR_INVALID_ARG) return st;
+    } else if (!generic_only && tn.set && tn.kind == 1) {
+        mb_status st = launch_local_split(p, ik, c, part, nbands, ld, prec, s);
+        if (st != MB_ERR_INVALID_ARG) return st;
+    } else if (!generic_only && !(tn.set && tn.kind == 2)) {
         mb_status st = launch_local_lines(p, ik, c, part, nbands, ld, prec, s);
         if (st != MB_ERR_INVALID_ARG) return st;
         st = launch_local_split(p, ik, c, part, nbands, ld, prec, s);

@@ -271,9 +271,10 @@ mb_status lines_dispatch(Problem* p, int ik, const void* c, void* part, int nban
 }
 
 template <typename TI, typename T>
-mb_status lines_by_size(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s) {
+mb_status lines_by_size(Problem* p, int ik, const void* c, void* part, int nbands, int ld, hipStream_t s,
+                        int budget_kb) {
     if (p->N1 != p->N2) return MB_ERR_INVALID_ARG;
-    const size_t budget = 110 * 1024;
+    const size_t budget = (size_t)budget_kb * 1024;
     switch (p->N1) {
         case 16: return lines_dispatch<TI, T, 16, 16>(p, ik, c, part, nbands, ld, s, budget);
         case 24: return lines_dispatch<TI, T, 24, 24>(p, ik, c, part, nbands, ld, s, budget);
@@ -370,11 +371,11 @@ mb_status lines_batch_by_size(const std::vector<BatchItem>& items, TableUploader
 // Returns MB_OK if a line kernel handled the grid, MB_ERR_INVALID_ARG if the grid
 // has no line kernel (the caller then uses the generic one).
 mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
-                             hipStream_t s) {
+                             hipStream_t s, int budget_kb) {
     if (p->order != KORD) return MB_ERR_INVALID_ARG;
-    if (prec == 0) return lines_by_size<double, double>(p, ik, c, part, nbands, ld, s);
-    if (prec == 1) return lines_by_size<float, float>(p, ik, c, part, nbands, ld, s);
-    return lines_by_size<double, float>(p, ik, c, part, nbands, ld, s);
+    if (prec == 0) return lines_by_size<double, double>(p, ik, c, part, nbands, ld, s, budget_kb);
+    if (prec == 1) return lines_by_size<float, float>(p, ik, c, part, nbands, ld, s, budget_kb);
+    return lines_by_size<double, float>(p, ik, c, part, nbands, ld, s, budget_kb);
 }
 
 }  // namespace mb

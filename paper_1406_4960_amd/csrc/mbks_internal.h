@@ -52,6 +52,14 @@ struct KPoint {
     Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
     Workspace ws_lz;      // eigensolver vectors
     Workspace ws_small;   // eigensolver small matrices
+    // kernel choices measured by mb_autotune, per arithmetic class of the local part
+    // (0: FP64, 1: FP32 with complex64 vectors, 2: FP32 with complex128 vectors)
+    struct Tune {
+        int set = 0;
+        int kind = -1;        // local kernel: 0 line-per-thread, 1 two-step, 2 generic
+        int budget_kb = 110;  // LDS budget of the line-per-thread kernel (planes per group)
+        int nl_mfma = -1;     // FP32 projector path: 1 matrix cores, 0 vector kernel, -1 default
+    } tune[3];
 };
 
 struct Problem {
@@ -145,7 +153,7 @@ mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands
 mb_status launch_local_split(Problem* p, int ik, const void* c, void* part, int nbands, int ld, int prec,
                              hipStream_t s);
 mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
-                             int prec, hipStream_t s);
+                             int prec, hipStream_t s, int budget_kb = 110);
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
                             int prec, hipStream_t s);
 // matrix-core projections: mode 1 FP32 MFMA, mode 2 BF16x3 MFMA; vin64 = complex128 vectors

@@ -26,7 +26,7 @@ MB_MAX_GAUSS = 4
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
            "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
-           "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched",
+           "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
@@ -58,6 +58,11 @@ class LanczosOpts(ctypes.Structure):
     _fields_ = [("block", c_int32), ("krylov", c_int32), ("krylov_global", c_int32), ("max_iter", c_int32),
                 ("tol", c_double), ("sigma", c_double), ("switch_tol", c_double), ("seed", c_uint64),
                 ("extra", c_int32)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("local_kernel", c_int32), ("lds_budget_kb", c_int32), ("nl_matrix_cores", c_int32),
+                ("candidates", c_int32), ("local_ms", c_double), ("local_default_ms", c_double), ("nl_ms", c_double)]
 
 
 class LanczosInfo(ctypes.Structure):
@@ -100,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.mb_lanczos_default_opts.restype = None
     lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
                                    POINTER(LanczosInfo), vp]
+    lib.mb_autotune.argtypes = [vp, c_int, c_int64, c_int, vp, POINTER(TuneInfo)]
     lib.mb_batch_create.argtypes = [vp, vp, c_int, POINTER(vp)]
     lib.mb_batch_destroy.argtypes = [vp]
     lib.hpsi_apply_batched.argtypes = [vp, vp, vp, vp, vp, c_int, vp]
@@ -303,6 +309,12 @@ class Problem:
     def s_solve(self, ik, r, x, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, r, x, prec)
         _check(load().s_solve(self.h, ik, _ptr(r), _ptr(x), nbands, ld, _prec(prec), _stream(stream)))
+
+    def autotune(self, ik, nbands, prec="fp64", stream=None):
+        """Measure the kernel choices for (ik, nbands, prec) and keep the fastest."""
+        info = TuneInfo()
+        _check(load().mb_autotune(self.h, ik, int(nbands), _prec(prec), _stream(stream), ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in TuneInfo._fields_}
 
     @staticmethod
     def default_opts() -> LanczosOpts:

@@ -1,0 +1,45 @@
+"""mb_autotune: the kernel choices it stores leave the operator unchanged (up to the
+summation-order differences of the kernels, the bars of the kernel cross-checks) and
+the choice it reports is one of the kernels that support the grid."""
+import pytest
+import torch
+
+from paper_1406_4960_amd import mbks, workloads
+from tests.helpers import random_lib_block, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("cfg,prec,kinds", [("graphene", "fp64", {0, 2}), ("graphene", "fp32", {0, 2}),
+                                            ("graphene_2x2", "fp32", {1, 2}), ("graphene_2x2", "fp64", {1, 2})])
+def test_autotune_keeps_operator(cfg, prec, kinds):
+    print(f"[case] autotune {cfg} {prec}", flush=True)
+    d = workloads.CONFIGS[cfg]()
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.from_numpy(random_lib_block(90, 6, dm["nb"], dm["ng"], dm["ld"])).to(DEV).to(ct)
+    y0 = torch.empty_like(x)
+    p.hpsi(0, x, y0, prec)
+    info = p.autotune(0, 16, prec)
+    print(info, flush=True)
+    assert info["local_kernel"] in kinds
+    assert info["candidates"] >= 2 and info["local_ms"] > 0 and info["local_default_ms"] > 0
+    if prec == "fp32":
+        assert info["nl_matrix_cores"] in (0, 1)
+    y1 = torch.empty_like(x)
+    p.hpsi(0, x, y1, prec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_err(y1.to(torch.complex128).cpu().numpy(), y0.to(torch.complex128).cpu().numpy()) < tol
+    p.close()
+
+
+def test_autotune_bad_args():
+    p = mbks.Problem(workloads.tiny(), device=0)
+    with pytest.raises(mbks.MbError):
+        p.autotune(3, 8)
+    with pytest.raises(mbks.MbError):
+        p.autotune(0, 0)
+    p.close()
