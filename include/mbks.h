@@ -225,6 +225,7 @@ void mb_lanczos_default_opts(mb_lanczos_opts* opts);
  * x0: device complex128 [nev][N_b][ld] start vectors, or NULL for a seeded random
  * start.  eig: host, nev doubles (ascending).  x: device complex128
  * [nev][N_b][ld] output, S-orthonormal.  info and opts may be NULL (defaults).
+ * Limits: nev + buffer + krylov_global <= 512, block + krylov <= 64.
  * Returns MB_ERR_NOT_CONVERGED (outputs filled) after opts->max_iter cycles. */
 mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
                          const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
@@ -270,7 +271,7 @@ mb_status lanczos_lowest_batched(mb_batch* b, const int* nev, mb_precision prec,
 
 /* The projected-eigenproblem step of lanczos_lowest on its own (Rayleigh-Ritz with
  * the Jacobi method, Sec. II.C): nz independent generalized Hermitian problems
- * H y = theta S y of size N (1..256), H and S row-major N x N complex128 each
+ * H y = theta S y of size N (1..512), H and S row-major N x N complex128 each
  * (2*N*N doubles, interleaved re/im), S positive definite.  S = L L^H is reduced
  * by a Cholesky factor, A = L^{-1} H L^{-H} is diagonalised by cyclic Jacobi
  * sweeps with the round-robin parallel ordering, Y = L^{-H} V.  Outputs: evals

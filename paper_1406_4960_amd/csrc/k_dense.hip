@@ -411,6 +411,9 @@ __device__ inline int rr_pair(int r, int k, int Np) {
     return (r + k) % (Np - 1);
 }
 
+// largest projected problem (per-pair and per-root tables in LDS are sized by it)
+constexpr int GENEIG_MAX = 512;
+
 // squared relative size below which an off-diagonal element is not rotated
 constexpr double JACOBI_TOL2 = 1e-28;
 
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     __shared__ int bad;
     __shared__ int s_more;
     __shared__ int s_rot[2];
-    __shared__ unsigned char dead[256];  // directions numerically in the span of earlier ones
+    __shared__ unsigned char dead[GENEIG_MAX];  // directions numerically in the span of earlier ones
     if (tid == 0) bad = 0;
     // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
     //    dependent direction: it is taken out of the reduction (unit pivot, zero column)
@@ -536,8 +539,8 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     // 5. cyclic Jacobi
     const int Np = N + (N & 1);
     const int npair = Np / 2;
-    __shared__ double rc[128], rsr[128], rsi[128];  // c, s e^{i phi} per pair (npair <= 128 in LDS mode)
-    __shared__ int rp[128], rq[128];
+    __shared__ double rc[GENEIG_MAX / 2], rsr[GENEIG_MAX / 2], rsi[GENEIG_MAX / 2];  // c, s e^{i phi} per pair
+    __shared__ int rp[GENEIG_MAX / 2], rq[GENEIG_MAX / 2];
     double* gc = nullptr;
     int sweep = 0;
     for (; sweep < max_sweeps; ++sweep) {
@@ -634,8 +637,8 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     (void)gc;
     // 6. order and back-transform in LDS: Yl = L^{-H} V (into P1 once the eigenvalues
     //    are saved), then column j of Yl goes to column rank(j) of Y
-    __shared__ double evs[256];
-    __shared__ int rk[256];
+    __shared__ double evs[GENEIG_MAX];
+    __shared__ int rk[GENEIG_MAX];
     for (int j = tid; j < N; j += NT) evs[j] = P1[(size_t)j * N + j].x;
     __syncthreads();
     for (int j = tid; j < N; j += NT) {
@@ -851,7 +854,7 @@ mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed,
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
                        int* status, hipStream_t s, int* sweeps) {
     if (N <= 0 || nz <= 0) return MB_OK;
-    if (N > 256) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 256");
+    if (N > GENEIG_MAX) return set_error(MB_ERR_INVALID_ARG, "projected problem larger than 512");
     const size_t nn16 = (size_t)N * N * sizeof(zc);
     const int mode = 3 * nn16 <= 150000 ? 2 : nn16 <= 150000 ? 1 : 0;
     const size_t dyn = mode == 2 ? 3 * nn16 : mode == 1 ? nn16 : 0;
@@ -904,7 +907,7 @@ mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* ou
 extern "C" mb_status mb_small_geneig(const double* H, const double* S, int N, int nz, double* evals, double* Y,
                                      int* sweeps, void* stream) {
     using namespace mb;
-    if (!H || !S || !evals || !Y || N < 1 || N > 256 || nz < 1 || nz > 4096)
+    if (!H || !S || !evals || !Y || N < 1 || N > GENEIG_MAX || nz < 1 || nz > 4096)
         return set_error(MB_ERR_INVALID_ARG, "mb_small_geneig: bad arguments");
     hipStream_t s = (hipStream_t)stream;
     const size_t nn = (size_t)N * N * nz;

@@ -258,9 +258,9 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.ld = kp.ld;
     S.K = (int64_t)p->nb * kp.ld;
     S.vbytes = (size_t)S.K * 16;
-    if (S.NG > 256 || S.NR > 64 || S.b > 32)
+    if (S.NG > 512 || S.NR > 64 || S.b > 32)
         return set_error(MB_ERR_INVALID_ARG,
-                         "lanczos_lowest: nev + buffer + krylov_global must be <= 256, block + krylov <= 64");
+                         "lanczos_lowest: nev + buffer + krylov_global must be <= 512, block + krylov <= 64");
     if ((int64_t)nev > basis) return set_error(MB_ERR_INVALID_ARG, "nev exceeds the basis size");
 
     // vector workspace

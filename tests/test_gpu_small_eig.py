@@ -24,7 +24,7 @@ def _problems(nz, N, seed, near_diag=False):
 
 
 @pytest.mark.parametrize("nz,N,near", [(1, 1, False), (32, 5, False), (1, 34, False), (1, 34, True),
-                                       (3, 66, False), (1, 82, True), (2, 97, True)])
+                                       (3, 66, False), (1, 82, True), (2, 97, True), (1, 340, True)])
 def test_small_geneig_vs_lapack(nz, N, near):
     H, S = _problems(nz, N, 10 + N, near)
     ev, Y, sw = mbks.small_geneig(H, S)
