@@ -20,7 +20,10 @@ mb_status dense_axpy(void* const* ty, const void* const* tx, const void* coef, d
                      hipStream_t s);
 mb_status dense_normalize(void* const* t1, void* const* t2, const void* d, int nvec, int64_t K, hipStream_t s);
 mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed, hipStream_t s);
-// nz problems of size N: H, S, Y row-major N x N each, evals N each; gwork 3 N^2 complex per problem
+// nz problems of size N: H, S, Y row-major N x N each, evals N each; gwork of
+// geneig_work_bytes(N, nz) bytes.  Problems whose work matrices do not fit in LDS
+// synchronize the stream once per Jacobi sweep (the host reads a convergence flag).
+size_t geneig_work_bytes(int N, int nz);
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
                        int* status, hipStream_t s, int* sweeps = nullptr);
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,

@@ -414,6 +414,24 @@ __device__ inline int rr_pair(int r, int k, int Np) {
 // largest projected problem (per-pair and per-root tables in LDS are sized by it)
 constexpr int GENEIG_MAX = 512;
 
+// Flags of the multi-workgroup Jacobi, after the nz problems' four N x N matrices:
+// [0..2] any problem still rotating, one slot per sweep modulo 3; per problem z,
+// [4 + 4z + 0..2] this problem still rotating (same slots) and [4 + 4z + 3] the copy
+// of A (0 or 1) that holds its final matrix.
+__device__ inline int* jacobi_flags(zc* gwork, int nz, size_t NN) {
+    return reinterpret_cast<int*>(gwork + (size_t)nz * 4 * NN);
+}
+
+// the two rows of round r's pair pi (q = Np - 1 is the padding index when N is odd)
+__device__ inline void rr_rows(int r, int pi, int Np, int& p, int& q) {
+    if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
+    else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
+    if (p > q) { int t = p; p = q; q = t; }
+}
+
+// sweep limit of the projected eigen-solve
+constexpr int GENEIG_SWEEPS = 60;
+
 // squared relative size below which an off-diagonal element is not rotated
 constexpr double JACOBI_TOL2 = 1e-28;
 
@@ -422,7 +440,12 @@ constexpr double JACOBI_TOL2 = 1e-28;
 // (problems too large for all three); MODE 0: all in global scratch.  Pointers that
 // derive from the shared array alone compile to LDS instructions (a pointer that may
 // be either LDS or global memory would turn them into flat accesses).
-template <int NT, int MODE>
+// MODE 3 is the large-problem form: the matrices are in global scratch with room for
+// a second copy of A, and the kernel runs in two parts around a Jacobi that spreads
+// each round over many workgroups: PART 1 reduces to A (and V = I) and stops, PART 2
+// orders and back-transforms from the copy of A the last sweep left (PART 0 is the
+// whole solve in one workgroup).
+template <int NT, int MODE, int PART = 0>
 __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N, double* evals, zc* Ys,
                                                zc* gwork, int max_sweeps, int* status, int* sweeps_out) {
     extern __shared__ unsigned char sm[];
@@ -432,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     const zc* H = Hs + z * NN;
     const zc* S = Ss + z * NN;
     // three N x N work matrices: in LDS when they fit, else in global scratch
-    zc* const G0 = gwork + z * 3 * NN;
+    zc* const G0 = gwork + z * (MODE == 3 ? 4 : 3) * NN;
     zc* Lg;  // Cholesky factor L
     zc* P1;  // work matrix, then A
     zc* P2;  // work matrix, then V
@@ -455,186 +478,201 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
     __shared__ int s_rot[2];
     __shared__ unsigned char dead[GENEIG_MAX];  // directions numerically in the span of earlier ones
     if (tid == 0) bad = 0;
-    // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
-    //    dependent direction: it is taken out of the reduction (unit pivot, zero column)
-    //    and later pinned at the top of the spectrum so it is never selected
-    for (int e = tid; e < NNi; e += NT) P1[e] = S[e];
-    __syncthreads();
-    for (int j = 0; j < N; ++j) {
-        if (tid == 0) {
-            double d = P1[(size_t)j * N + j].x;
-            double d0 = S[(size_t)j * N + j].x;
-            dead[j] = 0;
-            if (!isfinite(d) || !isfinite(d0)) {
-                bad = 2;
-                d = 1.0;
-            } else if (!(d > 1e-8 * d0) || !(d0 > 0.0)) {
-                dead[j] = 1;
-                d = 1.0;
-            }
-            P1[(size_t)j * N + j] = mk<double>(sqrt(d), 0.0);
-        }
+    if constexpr (PART != 2) {
+        // 1. Cholesky of S in P1; a pivot that lost all but 1e-8 of its diagonal marks a
+        //    dependent direction: it is taken out of the reduction (unit pivot, zero column)
+        //    and later pinned at the top of the spectrum so it is never selected
+        for (int e = tid; e < NNi; e += NT) P1[e] = S[e];
         __syncthreads();
-        double inv = 1.0 / P1[(size_t)j * N + j].x;
-        for (int i = j + 1 + tid; i < N; i += NT)
-            P1[(size_t)i * N + j] = dead[j] ? mk<double>(0, 0) : cscale(P1[(size_t)i * N + j], inv);
-        __syncthreads();
-        // trailing update of the lower triangle: A_ik -= L_ij conj(L_kj), i >= k > j
-        int w = N - j - 1;
-        for (int e = tid; e < w * w; e += NT) {
-            int i = j + 1 + e / w, k = j + 1 + e % w;
-            if (k > i) continue;
-            zc lij = P1[(size_t)i * N + j], lkj = P1[(size_t)k * N + j];
-            zc t = mk<double>(lij.x * lkj.x + lij.y * lkj.y, lij.y * lkj.x - lij.x * lkj.y);  // lij conj(lkj)
-            P1[(size_t)i * N + k] = csub(P1[(size_t)i * N + k], t);
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < NNi; e += NT) {
-        int i = (int)(e / N), k = (int)(e % N);
-        Lg[e] = (k <= i) ? P1[e] : mk<double>(0, 0);
-    }
-    // 2. B = L^{-1} H in P2 (column-wise forward substitution)
-    for (int e = tid; e < NNi; e += NT) P2[e] = H[e];
-    __syncthreads();
-    for (int col = tid; col < N; col += NT) {
-        for (int i = 0; i < N; ++i) {
-            zc v = P2[(size_t)i * N + col];
-#pragma unroll 8
-            for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P2[(size_t)k * N + col]));
-            P2[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
-        }
-    }
-    __syncthreads();
-    // 3. A = L^{-1} B^H into P1: column j solves L a = conj(row j of B)
-    for (int col = tid; col < N; col += NT) {
-        for (int i = 0; i < N; ++i) {
-            zc b = P2[(size_t)col * N + i];
-            zc v = mk<double>(b.x, -b.y);
-#pragma unroll 8
-            for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P1[(size_t)k * N + col]));
-            P1[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
-        }
-    }
-    __syncthreads();
-    // 4. Hermitian part of A; V = I
-    for (int e = tid; e < NNi; e += NT) {
-        int i = (int)(e / N), k = (int)(e % N);
-        if (k < i) {
-            zc a = P1[(size_t)i * N + k], b = P1[(size_t)k * N + i];
-            zc h = mk<double>(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-            P1[(size_t)i * N + k] = h;
-            P1[(size_t)k * N + i] = mk<double>(h.x, -h.y);
-        } else if (k == i) {
-            P1[e] = mk<double>(P1[e].x, 0.0);
-        }
-        P2[e] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    for (int e = tid; e < NNi; e += NT) {
-        int i = (int)(e / N), k = (int)(e % N);
-        if (dead[i] || dead[k]) P1[e] = mk<double>(i == k ? 1e30 : 0.0, 0.0);
-    }
-    __syncthreads();
-    // 5. cyclic Jacobi
-    const int Np = N + (N & 1);
-    const int npair = Np / 2;
-    __shared__ double rc[GENEIG_MAX / 2], rsr[GENEIG_MAX / 2], rsi[GENEIG_MAX / 2];  // c, s e^{i phi} per pair
-    __shared__ int rp[GENEIG_MAX / 2], rq[GENEIG_MAX / 2];
-    double* gc = nullptr;
-    int sweep = 0;
-    for (; sweep < max_sweeps; ++sweep) {
-        // converged when no off-diagonal element is above the rotation threshold
-        // |a_pq| > 1e-14 (|a_pp| + |a_qq|): a smaller element changes the eigenvalues by
-        // at most |a_pq|^2 / gap (or |a_pq| for a cluster), far below FP64 rounding of
-        // the matrix itself, and rotating it only reshuffles rounding noise
-        if (tid == 0) {
-            s_more = 0;
-            s_rot[0] = 0;
-        }
-        __syncthreads();
-        int more = 0;
-        for (int e = tid; e < NNi; e += NT) {
-            const int i = e / N, k = e - i * N;
-            if (k <= i || dead[i] || dead[k]) continue;  // deflated directions are already decoupled
-            const zc a = P1[e];
-            const double r2 = a.x * a.x + a.y * a.y;
-            const double scale = fabs(P1[(size_t)i * N + i].x) + fabs(P1[(size_t)k * N + k].x);
-            if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) more = 1;
-        }
-        if (more) s_more = 1;
-        __syncthreads();
-        if (!s_more) break;
-        for (int r = 0; r < Np - 1; ++r) {
-            // rotation of every pair of this round from its pivots a_pp, a_qq, a_pq
-            // (the pairs are disjoint, so no pair's pivots change within the round).
-            // s_rot[r & 1] records whether any pair rotates; the flag of the next round
-            // is cleared here, before this round's barrier, so it is clear before any
-            // thread can set it
-            if (tid == 0) s_rot[(r + 1) & 1] = 0;
-            for (int pi = tid; pi < npair; pi += NT) {
-                int p, q;
-                if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
-                else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
-                if (p > q) { int t = p; p = q; q = t; }
-                double c = 1.0, sr = 0.0, si = 0.0;
-                if (q < N) {
-                    const zc apq = P1[(size_t)p * N + q];
-                    const double r2 = apq.x * apq.x + apq.y * apq.y;
-                    const double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
-                    const double scale = fabs(app) + fabs(aqq);
-                    if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) {
-                        // tan of the rotation angle: t = 2|a_pq| sgn(d) / (|d| + sqrt(d^2 + 4|a_pq|^2)),
-                        // d = a_qq - a_pp; c = 1/sqrt(1 + t^2); phase a_pq / |a_pq|
-                        const double d = aqq - app;
-                        const double inv_r = rsqrt(r2);
-                        const double rabs = r2 * inv_r;
-                        const double t = (d >= 0 ? 2.0 : -2.0) * rabs / (fabs(d) + sqrt(d * d + 4.0 * r2));
-                        c = rsqrt(1.0 + t * t);
-                        const double sn = t * c * inv_r;
-                        sr = sn * apq.x;  // s e^{i phi}
-                        si = sn * apq.y;
-                    }
+        for (int j = 0; j < N; ++j) {
+            if (tid == 0) {
+                double d = P1[(size_t)j * N + j].x;
+                double d0 = S[(size_t)j * N + j].x;
+                dead[j] = 0;
+                if (!isfinite(d) || !isfinite(d0)) {
+                    bad = 2;
+                    d = 1.0;
+                } else if (!(d > 1e-8 * d0) || !(d0 > 0.0)) {
+                    dead[j] = 1;
+                    d = 1.0;
                 }
-                rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
-                if (sr != 0.0 || si != 0.0) s_rot[r & 1] = 1;
+                P1[(size_t)j * N + j] = mk<double>(sqrt(d), 0.0);
             }
             __syncthreads();
-            if (!s_rot[r & 1]) continue;  // nothing rotates this round (uniform branch)
-            // rows p, q of every pair:
-            //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
-            for (int e = tid; e < npair * N; e += NT) {
-                const int pi = e / N, j = e - pi * N;
-                const int p = rp[pi], q = rq[pi];
-                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                const double c = rc[pi];
-                const zc se = mk<double>(rsr[pi], rsi[pi]);
-                const zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                const zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
-                P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
-                P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
-            }
+            double inv = 1.0 / P1[(size_t)j * N + j].x;
+            for (int i = j + 1 + tid; i < N; i += NT)
+                P1[(size_t)i * N + j] = dead[j] ? mk<double>(0, 0) : cscale(P1[(size_t)i * N + j], inv);
             __syncthreads();
-            // columns p, q of A and V:
-            //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
-            for (int e = tid; e < npair * N; e += NT) {
-                const int pi = e / N, i = e - pi * N;
-                const int p = rp[pi], q = rq[pi];
-                if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                const double c = rc[pi];
-                const zc se = mk<double>(rsr[pi], rsi[pi]);
-                const zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                const zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
-                P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
-                P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
-                const zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
-                P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
-                P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+            // trailing update of the lower triangle: A_ik -= L_ij conj(L_kj), i >= k > j
+            int w = N - j - 1;
+            for (int e = tid; e < w * w; e += NT) {
+                int i = j + 1 + e / w, k = j + 1 + e % w;
+                if (k > i) continue;
+                zc lij = P1[(size_t)i * N + j], lkj = P1[(size_t)k * N + j];
+                zc t = mk<double>(lij.x * lkj.x + lij.y * lkj.y, lij.y * lkj.x - lij.x * lkj.y);  // lij conj(lkj)
+                P1[(size_t)i * N + k] = csub(P1[(size_t)i * N + k], t);
             }
             __syncthreads();
         }
+        for (int e = tid; e < NNi; e += NT) {
+            int i = (int)(e / N), k = (int)(e % N);
+            Lg[e] = (k <= i) ? P1[e] : mk<double>(0, 0);
+        }
+        // 2. B = L^{-1} H in P2 (column-wise forward substitution)
+        for (int e = tid; e < NNi; e += NT) P2[e] = H[e];
+        __syncthreads();
+        for (int col = tid; col < N; col += NT) {
+            for (int i = 0; i < N; ++i) {
+                zc v = P2[(size_t)i * N + col];
+    #pragma unroll 8
+                for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P2[(size_t)k * N + col]));
+                P2[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+            }
+        }
+        __syncthreads();
+        // 3. A = L^{-1} B^H into P1: column j solves L a = conj(row j of B)
+        for (int col = tid; col < N; col += NT) {
+            for (int i = 0; i < N; ++i) {
+                zc b = P2[(size_t)col * N + i];
+                zc v = mk<double>(b.x, -b.y);
+    #pragma unroll 8
+                for (int k = 0; k < i; ++k) v = csub(v, cmul(Lg[(size_t)i * N + k], P1[(size_t)k * N + col]));
+                P1[(size_t)i * N + col] = cscale(v, 1.0 / Lg[(size_t)i * N + i].x);
+            }
+        }
+        __syncthreads();
+        // 4. Hermitian part of A; V = I
+        for (int e = tid; e < NNi; e += NT) {
+            int i = (int)(e / N), k = (int)(e % N);
+            if (k < i) {
+                zc a = P1[(size_t)i * N + k], b = P1[(size_t)k * N + i];
+                zc h = mk<double>(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+                P1[(size_t)i * N + k] = h;
+                P1[(size_t)k * N + i] = mk<double>(h.x, -h.y);
+            } else if (k == i) {
+                P1[e] = mk<double>(P1[e].x, 0.0);
+            }
+            P2[e] = mk<double>(i == k ? 1.0 : 0.0, 0.0);
+        }
+        __syncthreads();
+        for (int e = tid; e < NNi; e += NT) {
+            int i = (int)(e / N), k = (int)(e % N);
+            if (dead[i] || dead[k]) P1[e] = mk<double>(i == k ? 1e30 : 0.0, 0.0);
+        }
+        __syncthreads();
     }
-    (void)gc;
+    int* const jfl = jacobi_flags(gwork, gridDim.x, NN);
+    if constexpr (PART == 1) {
+        // the multi-workgroup sweeps start from A in the first copy; clear this
+        // problem's per-sweep flags (and, once, the any-problem flags)
+        if (tid == 0) {
+            for (int k = 0; k < 4; ++k) jfl[4 + 4 * z + k] = 0;
+            if (z == 0)
+                for (int k = 0; k < 3; ++k) jfl[k] = 0;
+            if (bad) atomicMax(status, bad);
+        }
+        return;
+    }
+    int sweep = 0;
+    if constexpr (PART == 0) {
+        // 5. cyclic Jacobi
+        const int Np = N + (N & 1);
+        const int npair = Np / 2;
+        __shared__ double rc[GENEIG_MAX / 2], rsr[GENEIG_MAX / 2], rsi[GENEIG_MAX / 2];  // c, s e^{i phi} per pair
+        __shared__ int rp[GENEIG_MAX / 2], rq[GENEIG_MAX / 2];
+        for (; sweep < max_sweeps; ++sweep) {
+            // converged when no off-diagonal element is above the rotation threshold
+            // |a_pq| > 1e-14 (|a_pp| + |a_qq|): a smaller element changes the eigenvalues by
+            // at most |a_pq|^2 / gap (or |a_pq| for a cluster), far below FP64 rounding of
+            // the matrix itself, and rotating it only reshuffles rounding noise
+            if (tid == 0) {
+                s_more = 0;
+                s_rot[0] = 0;
+            }
+            __syncthreads();
+            int more = 0;
+            for (int e = tid; e < NNi; e += NT) {
+                const int i = e / N, k = e - i * N;
+                if (k <= i || dead[i] || dead[k]) continue;  // deflated directions are already decoupled
+                const zc a = P1[e];
+                const double r2 = a.x * a.x + a.y * a.y;
+                const double scale = fabs(P1[(size_t)i * N + i].x) + fabs(P1[(size_t)k * N + k].x);
+                if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) more = 1;
+            }
+            if (more) s_more = 1;
+            __syncthreads();
+            if (!s_more) break;
+            for (int r = 0; r < Np - 1; ++r) {
+                // rotation of every pair of this round from its pivots a_pp, a_qq, a_pq
+                // (the pairs are disjoint, so no pair's pivots change within the round).
+                // s_rot[r & 1] records whether any pair rotates; the flag of the next round
+                // is cleared here, before this round's barrier, so it is clear before any
+                // thread can set it
+                if (tid == 0) s_rot[(r + 1) & 1] = 0;
+                for (int pi = tid; pi < npair; pi += NT) {
+                    int p, q;
+                    if (pi == 0) { p = r % (Np - 1); q = Np - 1; }
+                    else { p = rr_pair(r, pi, Np); q = (r - pi + (Np - 1)) % (Np - 1); }
+                    if (p > q) { int t = p; p = q; q = t; }
+                    double c = 1.0, sr = 0.0, si = 0.0;
+                    if (q < N) {
+                        const zc apq = P1[(size_t)p * N + q];
+                        const double r2 = apq.x * apq.x + apq.y * apq.y;
+                        const double app = P1[(size_t)p * N + p].x, aqq = P1[(size_t)q * N + q].x;
+                        const double scale = fabs(app) + fabs(aqq);
+                        if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) {
+                            // tan of the rotation angle: t = 2|a_pq| sgn(d) / (|d| + sqrt(d^2 + 4|a_pq|^2)),
+                            // d = a_qq - a_pp; c = 1/sqrt(1 + t^2); phase a_pq / |a_pq|
+                            const double d = aqq - app;
+                            const double inv_r = rsqrt(r2);
+                            const double rabs = r2 * inv_r;
+                            const double t = (d >= 0 ? 2.0 : -2.0) * rabs / (fabs(d) + sqrt(d * d + 4.0 * r2));
+                            c = rsqrt(1.0 + t * t);
+                            const double sn = t * c * inv_r;
+                            sr = sn * apq.x;  // s e^{i phi}
+                            si = sn * apq.y;
+                        }
+                    }
+                    rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
+                    if (sr != 0.0 || si != 0.0) s_rot[r & 1] = 1;
+                }
+                __syncthreads();
+                if (!s_rot[r & 1]) continue;  // nothing rotates this round (uniform branch)
+                // rows p, q of every pair:
+                //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
+                for (int e = tid; e < npair * N; e += NT) {
+                    const int pi = e / N, j = e - pi * N;
+                    const int p = rp[pi], q = rq[pi];
+                    if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
+                    const double c = rc[pi];
+                    const zc se = mk<double>(rsr[pi], rsi[pi]);
+                    const zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                    const zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
+                    P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
+                    P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
+                }
+                __syncthreads();
+                // columns p, q of A and V:
+                //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
+                for (int e = tid; e < npair * N; e += NT) {
+                    const int pi = e / N, i = e - pi * N;
+                    const int p = rp[pi], q = rq[pi];
+                    if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
+                    const double c = rc[pi];
+                    const zc se = mk<double>(rsr[pi], rsi[pi]);
+                    const zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                    const zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
+                    P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
+                    P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
+                    const zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
+                    P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
+                    P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if constexpr (PART == 2) P1 = G0 + NN + (size_t)jfl[4 + 4 * z + 3] * 2 * NN;  // copy of A the sweeps ended in
     // 6. order and back-transform in LDS: Yl = L^{-H} V (into P1 once the eigenvalues
     //    are saved), then column j of Yl goes to column rank(j) of Y
     __shared__ double evs[GENEIG_MAX];
@@ -671,7 +709,127 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
         Y[(size_t)i * N + rk[j]] = P1[e];
     }
     if (tid == 0 && bad) atomicMax(status, bad);
-    if (tid == 0 && sweeps_out) sweeps_out[z] = sweep;
+    if constexpr (PART == 0)
+        if (tid == 0 && sweeps_out) sweeps_out[z] = sweep;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-workgroup cyclic Jacobi on A (the large-problem form, between the two parts
+// of k_geneig<.., 3, ..>).  The same rotations as the one-workgroup sweep, in the same
+// round-robin order, but one launch per round: block pi of a round owns rows p, q of
+// its pair.  Every block derives all the round's rotations from the pivots of the
+// round's input copy of A, applies its own rotation to rows p, q and every pair's
+// rotation to the columns, and writes rows p, q of the other copy; V = V J is applied
+// to rows p, q of V in place.  Copies alternate every round, so sweep s starts from
+// copy s & 1 (a sweep has an odd number of rounds).
+// ---------------------------------------------------------------------------
+// sweep s's check: is any off-diagonal element above the rotation threshold?
+__global__ __launch_bounds__(256) void k_jacobi_check(zc* gwork, int N, int s, int* sweeps_out) {
+    const int z = blockIdx.y, nz = gridDim.y;
+    const size_t NN = (size_t)N * N;
+    int* const fl = jacobi_flags(gwork, nz, NN);
+    int* const mine = fl + 4 + 4 * z;
+    const int cur = s % 3, prev = (s + 2) % 3, next = (s + 1) % 3;
+    if (s > 0 && mine[prev] == 0) return;  // converged at an earlier check
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        mine[next] = 0;
+        mine[3] = s & 1;
+        if (sweeps_out) sweeps_out[z] = s;
+        if (z == 0) fl[next] = 0;
+    }
+    const zc* A = gwork + (size_t)z * 4 * NN + NN + (size_t)(s & 1) * 2 * NN;
+    const int NNi = N * N;
+    int more = 0;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < NNi; e += gridDim.x * 256) {
+        const int i = e / N, k = e - i * N;
+        if (k <= i) continue;
+        const zc a = A[e];
+        const double r2 = a.x * a.x + a.y * a.y;
+        const double scale = fabs(A[(size_t)i * N + i].x) + fabs(A[(size_t)k * N + k].x);
+        if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) more = 1;
+    }
+    if (__syncthreads_or(more) && threadIdx.x == 0) {
+        atomicOr(&mine[cur], 1);
+        atomicOr(&fl[cur], 1);
+    }
+}
+
+// round r of sweep s; grid (N_p / 2 pairs, problems), 256 threads
+__global__ __launch_bounds__(256) void k_jacobi_round(zc* gwork, int N, int s, int r) {
+    const int z = blockIdx.y, nz = gridDim.y;
+    const size_t NN = (size_t)N * N;
+    if (jacobi_flags(gwork, nz, NN)[4 + 4 * z + s % 3] == 0) return;  // converged
+    const int Np = N + (N & 1), npair = Np / 2;
+    const int in = (int)(((long long)s * (Np - 1) + r) & 1);
+    zc* const G0 = gwork + (size_t)z * 4 * NN;
+    const zc* const A = G0 + NN + (size_t)in * 2 * NN;
+    zc* const Ao = G0 + NN + (size_t)(in ^ 1) * 2 * NN;
+    zc* const V = G0 + 2 * NN;
+    __shared__ double rc[GENEIG_MAX / 2], rsr[GENEIG_MAX / 2], rsi[GENEIG_MAX / 2];
+    __shared__ int rp[GENEIG_MAX / 2], rq[GENEIG_MAX / 2];
+    const int tid = threadIdx.x;
+    for (int pi = tid; pi < npair; pi += 256) {
+        int p, q;
+        rr_rows(r, pi, Np, p, q);
+        double c = 1.0, sr = 0.0, si = 0.0;
+        if (q < N) {
+            const zc apq = A[(size_t)p * N + q];
+            const double r2 = apq.x * apq.x + apq.y * apq.y;
+            const double app = A[(size_t)p * N + p].x, aqq = A[(size_t)q * N + q].x;
+            const double scale = fabs(app) + fabs(aqq);
+            if (r2 > 1e-300 && r2 > JACOBI_TOL2 * scale * scale) {
+                // same rotation as the one-workgroup sweep: tan t from d = a_qq - a_pp
+                const double d = aqq - app;
+                const double inv_r = rsqrt(r2);
+                const double rabs = r2 * inv_r;
+                const double tn = (d >= 0 ? 2.0 : -2.0) * rabs / (fabs(d) + sqrt(d * d + 4.0 * r2));
+                c = rsqrt(1.0 + tn * tn);
+                const double sn = tn * c * inv_r;
+                sr = sn * apq.x;
+                si = sn * apq.y;
+            }
+        }
+        rc[pi] = c; rsr[pi] = sr; rsi[pi] = si; rp[pi] = p; rq[pi] = q;
+    }
+    __syncthreads();
+    const int me = blockIdx.x;
+    const int p0 = rp[me], q0 = rq[me];
+    const bool hq0 = q0 < N;
+    const double c0 = rc[me];
+    const zc se0 = mk<double>(rsr[me], rsi[me]), sec0 = mk<double>(rsr[me], -rsi[me]);
+    const zc zero = mk<double>(0.0, 0.0);
+    for (int cp = tid; cp < npair; cp += 256) {
+        const int p1 = rp[cp], q1 = rq[cp];
+        const bool hq1 = q1 < N;
+        const double c1 = rc[cp];
+        const zc se1 = mk<double>(rsr[cp], rsi[cp]), sec1 = mk<double>(rsr[cp], -rsi[cp]);
+        // the 2 x 2 block of A at rows (p0, q0), columns (p1, q1): rows first
+        // (x_p' = c x_p - s e^{i phi} x_q, x_q' = s e^{-i phi} x_p + c x_q), then columns
+        // (y_p' = c y_p - s e^{-i phi} y_q, y_q' = s e^{i phi} y_p + c y_q)
+        const zc a00 = A[(size_t)p0 * N + p1];
+        const zc a01 = hq1 ? A[(size_t)p0 * N + q1] : zero;
+        const zc a10 = hq0 ? A[(size_t)q0 * N + p1] : zero;
+        const zc a11 = hq0 && hq1 ? A[(size_t)q0 * N + q1] : zero;
+        const zc b00 = csub(cscale(a00, c0), cmul(se0, a10)), b10 = cadd(cmul(sec0, a00), cscale(a10, c0));
+        const zc b01 = csub(cscale(a01, c0), cmul(se0, a11)), b11 = cadd(cmul(sec0, a01), cscale(a11, c0));
+        Ao[(size_t)p0 * N + p1] = csub(cscale(b00, c1), cmul(sec1, b01));
+        if (hq1) Ao[(size_t)p0 * N + q1] = cadd(cmul(se1, b00), cscale(b01, c1));
+        if (hq0) {
+            Ao[(size_t)q0 * N + p1] = csub(cscale(b10, c1), cmul(sec1, b11));
+            if (hq1) Ao[(size_t)q0 * N + q1] = cadd(cmul(se1, b10), cscale(b11, c1));
+        }
+        // rows p0, q0 of V at columns (p1, q1), column rotation only (skipped when
+        // the pair does not rotate, as in the one-workgroup sweep)
+        if (hq1 && (rsr[cp] != 0.0 || rsi[cp] != 0.0)) {
+            const int rows[2] = {p0, q0};
+            for (int k = 0; k < (hq0 ? 2 : 1); ++k) {
+                const size_t o = (size_t)rows[k] * N;
+                const zc vp = V[o + p1], vq = V[o + q1];
+                V[o + p1] = csub(cscale(vp, c1), cmul(sec1, vq));
+                V[o + q1] = cadd(cmul(se1, vp), cscale(vq, c1));
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -866,13 +1024,32 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
         if (dyn > 65536)
             MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
         hipLaunchKernelGGL(kern, dim3(nz), dim3(threads), dyn, s, (const zc*)H, (const zc*)S, N, evals, (zc*)Y,
-                           (zc*)gwork, 60, status, sweeps);
+                           (zc*)gwork, GENEIG_SWEEPS, status, sweeps);
         return MB_OK;
     };
     mb_status st;
-    if (mode == 0)
-        st = launch(k_geneig<1024, 0>, 1024);
-    else if (mode == 1)
+    if (mode == 0) {
+        // large problems: reduction and back-transform in one workgroup per problem,
+        // the Jacobi sweeps spread over N/2 workgroups per problem, one launch per
+        // round; the host reads the any-problem flag after each sweep's check
+        st = launch(k_geneig<1024, 3, 1>, 1024);
+        if (st != MB_OK) return st;
+        const int Np = N + (N & 1);
+        const int nchk = (int)std::min<size_t>(64, ((size_t)N * N + 2047) / 2048);
+        const int* any = reinterpret_cast<const int*>((const zc*)gwork + (size_t)nz * 4 * N * N);
+        for (int sw = 0;; ++sw) {
+            hipLaunchKernelGGL(k_jacobi_check, dim3(nchk, nz), dim3(256), 0, s, (zc*)gwork, N, sw, sweeps);
+            MB_HIP_TRY(hipGetLastError());
+            int more = 0;
+            MB_HIP_TRY(hipMemcpyAsync(&more, any + sw % 3, sizeof(int), hipMemcpyDeviceToHost, s));
+            MB_HIP_TRY(hipStreamSynchronize(s));
+            if (!more || sw == GENEIG_SWEEPS) break;
+            for (int r = 0; r < Np - 1; ++r)
+                hipLaunchKernelGGL(k_jacobi_round, dim3(Np / 2, nz), dim3(256), 0, s, (zc*)gwork, N, sw, r);
+            MB_HIP_TRY(hipGetLastError());
+        }
+        st = launch(k_geneig<1024, 3, 2>, 1024);
+    } else if (mode == 1)
         st = launch(k_geneig<1024, 1>, 1024);
     else if (nt == 64)
         st = launch(k_geneig<64, 2>, 64);
@@ -881,6 +1058,10 @@ mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* eval
     if (st != MB_OK) return st;
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
+}
+
+size_t geneig_work_bytes(int N, int nz) {
+    return (size_t)4 * N * N * nz * sizeof(zc) + 16 * (size_t)nz + 64;
 }
 
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
@@ -930,7 +1111,7 @@ extern "C" mb_status mb_small_geneig(const double* H, const double* S, int N, in
         (void)hipGetLastError();
     }
     void** bufs[] = {&dH, &dS, &dY, &dW, (void**)&dE, (void**)&dst, (void**)&dsw};
-    const size_t sizes[] = {nn * 16, nn * 16, nn * 16, 3 * nn * 16, (size_t)N * nz * 8, 64, (size_t)nz * 4 + 64};
+    const size_t sizes[] = {nn * 16, nn * 16, nn * 16, geneig_work_bytes(N, nz), (size_t)N * nz * 8, 64, (size_t)nz * 4 + 64};
     for (int k = 0; k < 7; ++k) {
         hipError_t e = hipMalloc(bufs[k], sizes[k]);
         if (e != hipSuccess) {

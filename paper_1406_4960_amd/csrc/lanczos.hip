@@ -289,7 +289,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
                         (size_t)S.nbl * (3 * (size_t)S.m * S.m / 2 + S.m + 1);
     S.gscratch_bytes = (size_t)32 << 20;
     size_t small = ntab * sizeof(void*) + 3 * NN * 16 + (size_t)S.NG * S.M * 16 + (size_t)S.nbl * S.NR * S.b * 16 +
-                   3 * NN * 16 + NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 +
+                   4 * NN * 16 + 16 * (size_t)std::max(S.nbl, 1) + 64 + NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 +
                    (size_t)S.nbl * S.m * 16 + (size_t)64 * std::max(S.nbl * S.m, S.NG) * 16 +
                    (3 * (size_t)S.M + S.NG + 2 * S.nbl + 64) * 8 + S.gscratch_bytes + 64 * 256;
     LZ_TRY(ensure_ws(kw.ws_small, small));
@@ -346,7 +346,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     S.Sp = stake(NN * 16);
     S.Y = stake(NN * 16);
     S.W = stake(std::max((size_t)S.NG * S.M, (size_t)S.nbl * S.NR * S.b) * 16);
-    S.gwork = stake(3 * NN * 16);
+    S.gwork = stake(4 * NN * 16 + 16 * (size_t)std::max(S.nbl, 1) + 64);
     S.evals = (double*)stake(NN * sizeof(double));
     S.coef = stake((size_t)S.M * std::max(S.nbl, S.NG) * 16);
     S.dots = stake((size_t)std::max(S.nbl * S.m, 1) * 16);

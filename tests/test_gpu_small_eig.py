@@ -24,7 +24,8 @@ def _problems(nz, N, seed, near_diag=False):
 
 
 @pytest.mark.parametrize("nz,N,near", [(1, 1, False), (32, 5, False), (1, 34, False), (1, 34, True),
-                                       (3, 66, False), (1, 82, True), (2, 97, True), (1, 340, True)])
+                                       (3, 66, False), (1, 82, True), (2, 97, True), (2, 151, False),
+                                       (1, 340, True), (1, 512, False)])
 def test_small_geneig_vs_lapack(nz, N, near):
     H, S = _problems(nz, N, 10 + N, near)
     ev, Y, sw = mbks.small_geneig(H, S)
@@ -36,6 +37,28 @@ def test_small_geneig_vs_lapack(nz, N, near):
         R = H[z] @ Y[z] - S[z] @ Y[z] * ev[z][None, :]
         assert np.max(np.abs(R)) < 1e-10 * scale
         assert sw[z] < 60
+
+
+def test_small_geneig_large_batch_converging_at_different_sweeps():
+    # problems solved by the multi-workgroup sweeps: a near-diagonal problem stops
+    # sweeping before a dense one of the same launch, and both stay exact
+    N = 131
+    rng = np.random.default_rng(7)
+    E = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Hn = (np.diag(np.sort(rng.uniform(-1, 50, N))) + 1e-7 * (E + E.conj().T))[None]
+    Sn = np.eye(N, dtype=complex)[None]
+    Hd, Sd = _problems(1, N, 8, near_diag=False)
+    H = np.concatenate([Hn, Hd, Hn])
+    S = np.concatenate([Sn, Sd, Sn])
+    ev, Y, sw = mbks.small_geneig(H, S)
+    assert sw[0] < sw[1] and sw[0] == sw[2]
+    for z in range(3):
+        w = scipy.linalg.eigh(H[z], S[z], eigvals_only=True)
+        scale = max(1.0, np.max(np.abs(w)))
+        assert np.max(np.abs(ev[z] - w)) < 1e-12 * scale
+        R = H[z] @ Y[z] - S[z] @ Y[z] * ev[z][None, :]
+        assert np.max(np.abs(R)) < 1e-10 * scale
+    np.testing.assert_array_equal(ev[0], ev[2])
 
 
 def test_small_geneig_deflates_dependent_direction():
