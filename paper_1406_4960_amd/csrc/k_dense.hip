@@ -114,6 +114,85 @@ __global__ __launch_bounds__(256) void k_gram32(const zc* const* ta, const zc* c
         }
 }
 
+// the widest products (MA, NB >= 256): 64 x 64 output tiles, each thread a 4 x 4
+// block (m = m0 + ty + 16 a, n = n0 + tx + 16 c), so 8 LDS reads feed 16 complex
+// FMAs; the next k step's tile is loaded into registers while the current one is
+// used.  Blocks run tile-fastest through (tile, chunk, z), mapped so that each XCD
+// takes a contiguous run: the tiles of one k chunk share that XCD's L2.
+constexpr int G64 = 64;
+constexpr int GK64 = 16;
+
+__global__ __launch_bounds__(256) void k_gram64(const zc* const* ta, const zc* const* tb, int MA, int NB, int64_t K,
+                                                int64_t kchunk, int nchunk, int tiles_m, int tiles_n, zc* part) {
+    __shared__ zc As[G64][GK64 + 1];
+    __shared__ zc Bs[G64][GK64 + 1];
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int ntile = tiles_m * tiles_n;
+    const int tile = (int)(L % ntile);
+    const int chunk = (int)((L / ntile) % nchunk);
+    const int z = (int)(L / ntile / nchunk);
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = tm * G64, n0 = tn * G64;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    // loader mapping: element e = tid + 256 u of the 64 x 16 tile, row e / 16, k e % 16
+    const int lk = threadIdx.x % GK64, lr = threadIdx.x / GK64;  // rows lr + 16 u
+    const zc* arow[4];
+    const zc* brow[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = lr + 16 * u;
+        arow[u] = m0 + r < MA ? ta[(size_t)z * MA + m0 + r] : nullptr;
+        brow[u] = n0 + r < NB ? tb[(size_t)z * NB + n0 + r] : nullptr;
+    }
+    zc pa[4], pb[4];
+    auto fetch = [&](int64_t kb) {
+        const int64_t k = kb + lk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pa[u] = (k < k1 && arow[u]) ? arow[u][k] : mk<double>(0, 0);
+            pb[u] = (k < k1 && brow[u]) ? brow[u][k] : mk<double>(0, 0);
+        }
+    };
+    zc acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = mk<double>(0, 0);
+    if (k0 < k1) fetch(k0);
+    for (int64_t kb = k0; kb < k1; kb += GK64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[lr + 16 * u][lk] = pa[u];
+            Bs[lr + 16 * u][lk] = pb[u];
+        }
+        __syncthreads();
+        if (kb + GK64 < k1) fetch(kb + GK64);
+#pragma unroll 2
+        for (int kk = 0; kk < GK64; ++kk) {
+            zc a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = As[ty + 16 * i][kk];
+                b[i] = Bs[tx + 16 * i][kk];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cfmac(acc[i][c], a[i], b[c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int m = m0 + ty + 16 * a, n = n0 + tx + 16 * c;
+            if (m < MA && n < NB) part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = acc[a][c];
+        }
+}
+
 // narrow products (MA <= 16): block (chunk, n, z) streams its k range once, each
 // thread accumulating conj(A_m[k]) B_n[k] for every m in registers; wave shuffles
 // and one LDS pass reduce the block's MA sums into part[z][chunk][m][n]
@@ -242,40 +321,60 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, in
 // ---------------------------------------------------------------------------
 // Combination: Y_{z,n}[k] = alpha * sum_m W_z[m][n] X_{z,m}[k] + beta * Y_{z,n}[k]
 // ---------------------------------------------------------------------------
-constexpr int CN = 8;  // outputs per thread
+// One thread per k and CW outputs.  The coefficients are read straight from global
+// memory at wave-uniform addresses (they compile to scalar loads into SGPRs, which
+// the FMAs take as operands), so there is no LDS staging and no limit on MI; each
+// input element is read once per CW outputs.  Inputs are
+// loaded through global-address-space pointers: flat loads would share the scalar
+// loads' wait counter, and every coefficient wait would then drain them.
+typedef double gd2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) gd2* gd2p;
 
-__global__ __launch_bounds__(256) void k_combo(const zc* const* tx, zc* const* ty, const zc* W, int MI, int NO,
-                                               int64_t K, double alpha, double beta) {
-    extern __shared__ unsigned char sm[];
-    zc* Ws = reinterpret_cast<zc*>(sm);  // MI x CN
+template <int CW, bool FULL>
+__global__ __launch_bounds__(256) void k_combo_w(const zc* const* __restrict__ tx, zc* const* __restrict__ ty,
+                                                 const zc* __restrict__ W, int MI, int NO, int64_t K, double alpha,
+                                                 double beta, int nbeg) {
     const int z = blockIdx.z;
-    const int n0 = blockIdx.y * CN;
-    const int nn = min(CN, NO - n0);
-    const zc* Wz = W + (size_t)z * MI * NO;
-    for (int e = threadIdx.x; e < MI * CN; e += blockDim.x) {
-        int m = e / CN, j = e % CN;
-        Ws[e] = (j < nn) ? Wz[(size_t)m * NO + n0 + j] : mk<double>(0, 0);
-    }
-    __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n0 = nbeg + blockIdx.y * CW;
+    const int nn = FULL ? CW : NO - n0;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= K) return;
-    zc acc[CN];
+    const zc* __restrict__ Wz = W + (size_t)z * MI * NO + n0;
+    const zc* const* xt = tx + (size_t)z * MI;
+    zc acc[CW];
 #pragma unroll
-    for (int j = 0; j < CN; ++j) acc[j] = mk<double>(0, 0);
+    for (int j = 0; j < CW; ++j) acc[j] = mk<double>(0, 0);
+#pragma unroll 2
     for (int m = 0; m < MI; ++m) {
-        zc x = tx[(size_t)z * MI + m][k];
+        const gd2 xv = ((gd2p)xt[m])[k];
+        const zc x = mk<double>(xv.x, xv.y);
+        const zc* __restrict__ wr = Wz + (size_t)m * NO;
 #pragma unroll
-        for (int j = 0; j < CN; ++j) cfma(acc[j], Ws[m * CN + j], x);
+        for (int j = 0; j < CW; ++j)
+            if (FULL || j < nn) cfma(acc[j], wr[j], x);
     }
 #pragma unroll
-    for (int j = 0; j < CN; ++j) {
-        if (j < nn) {
+    for (int j = 0; j < CW; ++j) {
+        if (FULL || j < nn) {
             zc* yp = ty[(size_t)z * NO + n0 + j] + k;
             zc o = cscale(acc[j], alpha);
             if (beta != 0.0) o = cadd(o, cscale(*yp, beta));
             *yp = o;
         }
     }
+}
+
+template <int CW>
+void launch_combo_w(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
+                    double alpha, double beta, hipStream_t s) {
+    const unsigned kb = (unsigned)((K + 255) / 256);
+    const int nfull = NO / CW;
+    if (nfull > 0)
+        hipLaunchKernelGGL((k_combo_w<CW, true>), dim3(kb, nfull, nz), dim3(256), 0, s, (const zc* const*)tx,
+                           (zc* const*)ty, (const zc*)W, MI, NO, K, alpha, beta, 0);
+    if (NO % CW)
+        hipLaunchKernelGGL((k_combo_w<CW, false>), dim3(kb, 1, nz), dim3(256), 0, s, (const zc* const*)tx,
+                           (zc* const*)ty, (const zc*)W, MI, NO, K, alpha, beta, nfull * CW);
 }
 
 // ---------------------------------------------------------------------------
@@ -896,13 +995,24 @@ __global__ void k_copy_cols(const zc* Y, int ldy, int ncols, int nrows, zc* out)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static bool gram64_enabled() {
+    static const bool on = [] {
+        const char* e = getenv("MBKS_GRAM64");
+        return !(e && e[0] == '0');
+    }();
+    return on;
+}
+
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
                      void* scratch, size_t scratch_bytes, hipStream_t s) {
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
     const bool tiny = MA <= TINY && NB <= TINY;  // all outputs of a chunk in one block
     const bool skinny = !tiny && MA <= SKINNY;    // one block per output column
     const bool big = !tiny && !skinny && MA > GT && NB > GT;  // 32 x 32 tiles for the wide products
-    const int tile = big ? GT2 : GT, kstep = (tiny || skinny) ? 256 : big ? GK2 : GK;
+    // 64 x 64 tiles from 256 up (measured: 1.3x faster than 32 x 32 tiles at
+    // MA, NB ~ 340-1000, slower at ~ 100-250, where the grid has too few blocks)
+    const bool wide = big && MA >= 256 && NB >= 256 && gram64_enabled();
+    const int tile = wide ? G64 : big ? GT2 : GT, kstep = (tiny || skinny) ? 256 : wide ? GK64 : big ? GK2 : GK;
     int tiles_m = (MA + tile - 1) / tile, tiles_n = (NB + tile - 1) / tile;
     int ntiles = tiny ? nz : skinny ? NB * nz : tiles_m * tiles_n * nz;
     // at least 256 (64 for the wide tiles) k per chunk; about 1024 blocks in all
@@ -927,6 +1037,10 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     else if (skinny)
         hipLaunchKernelGGL(k_gram_skinny, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB,
                            K, kchunk, nchunk, (zc*)scratch);
+    else if (wide)
+        hipLaunchKernelGGL(k_gram64, dim3((unsigned)(tiles_m * tiles_n * nchunk * nz)), dim3(256), 0, s,
+                           (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk, tiles_m, tiles_n,
+                           (zc*)scratch);
     else if (big)
         hipLaunchKernelGGL(k_gram32, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K,
                            kchunk, nchunk, tiles_n, (zc*)scratch);
@@ -944,12 +1058,17 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
 mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
                       double alpha, double beta, hipStream_t s) {
     if (MI <= 0 || NO <= 0 || nz <= 0) return MB_OK;
-    size_t lds = (size_t)MI * CN * sizeof(zc);
-    if (lds > 65536) return set_error(MB_ERR_INVALID_ARG, "combination with too many inputs");
-    dim3 grid((unsigned)((K + 255) / 256), (NO + CN - 1) / CN, nz);
     StageScope ts_(MB_STAGE_COMBO, s);
-    hipLaunchKernelGGL(k_combo, grid, dim3(256), lds, s, (const zc* const*)tx, (zc* const*)ty, (const zc*)W, MI, NO,
-                       K, alpha, beta);
+    static const int cw_env = [] {
+        const char* e = getenv("MBKS_COMBO_CW");
+        return e ? atoi(e) : -1;
+    }();
+    // 16 outputs per thread for the wide combinations (measured 1.8x faster than 8 on
+    // MI, NO ~ 300-1000), 8 for the narrow ones, whose grids would otherwise be small
+    const int cw = (cw_env == 8 || cw_env == 16 || cw_env == 32) ? cw_env : (MI >= 64 && NO >= 64) ? 16 : 8;
+    if (cw == 8) launch_combo_w<8>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);
+    else if (cw == 16) launch_combo_w<16>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);
+    else launch_combo_w<32>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }

@@ -287,7 +287,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     const size_t NN = std::max((size_t)S.NG * S.NG, (size_t)S.nbl * S.NR * S.NR);
     const size_t ntab = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl + 3 * (size_t)S.nbl * S.NR +
                         (size_t)S.nbl * (3 * (size_t)S.m * S.m / 2 + S.m + 1);
-    S.gscratch_bytes = (size_t)32 << 20;
+    S.gscratch_bytes = std::max((size_t)32 << 20, 4 * NN * 16);  // Gram partial sums over k chunks
     size_t small = ntab * sizeof(void*) + 3 * NN * 16 + (size_t)S.NG * S.M * 16 + (size_t)S.nbl * S.NR * S.b * 16 +
                    4 * NN * 16 + 16 * (size_t)std::max(S.nbl, 1) + 64 + NN * sizeof(double) + (size_t)S.M * std::max(S.nbl, S.NG) * 16 +
                    (size_t)S.nbl * S.m * 16 + (size_t)64 * std::max(S.nbl * S.m, S.NG) * 16 +
