@@ -24,6 +24,9 @@ Printed JSON line:
                    problems
   supercell_2x2    the 2x2 supercell (72x72 grid, 64 bands, 4 k-points): time to its
                    eigenpairs mixed vs FP64
+  surface          the large surface slab (128x64 grid, 256 projectors, 320 bands),
+                   k-point 0: hpsi_apply throughput per precision and time to its
+                   320 eigenpairs mixed vs FP64
   roofline         the fused local-potential kernel (dominant kernel), from its
                    launches in the FP64 hpsi leg
   cpu_baseline     the CPU FP64 oracle's matrix-free H application, bounded sample
@@ -201,6 +204,73 @@ def c3_leg(torch, mbks, workloads):
     return res
 
 
+def surface_leg(torch, mbks, workloads):
+    """The large surface slab (128x64 grid, ~3,990 G, 192 splines with 6 Gauss
+    points, 64 atoms / 256 projectors, 320 bands) at k-point 0 of its 8: pure
+    hpsi_apply throughput per precision on 320 band-vectors, and the time to its
+    320 lowest eigenpairs in the mixed form and in plain FP64."""
+    d = workloads.surface()
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    M = d["nbands"]
+    res = {"workload": d["name"], "kpoint": 0, "bands": M, "n_per_k": dm["ng"] * dm["nb"],
+           "projectors": dm["np"], "gauss_planes": dm["nzq"]}
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(14064964)
+    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64), ("bf16x3", torch.complex64)):
+        x = torch.randn((M, dm["nb"], dm["ld"]), dtype=ct, device="cuda:0", generator=gen)
+        x[:, :, dm["ng"]:] = 0
+        y = torch.empty_like(x)
+        p.hpsi(0, x, y, prec)
+        torch.cuda.synchronize()
+        reps = 3
+        mbks.timer_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            p.hpsi(0, x, y, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        st = mbks.timer_read()
+        mbks.timer_enable(False)
+        ms = e0.elapsed_time(e1) / reps
+        res[f"hpsi_{prec}"] = {"band_vectors_per_s": round(M / (ms * 1e-3), 1), "ms_per_call": round(ms, 3),
+                               "stages_ms_per_call": {k: round(v[0] / reps, 3) for k, v in st.items() if v[1]}}
+        # the fused local kernel against the vector ALU peak of its arithmetic type
+        lname = "local" if prec == "fp64" else "local32"
+        if st.get(lname, (0, 0, 0))[1]:
+            lms, _, lunits = st[lname]
+            flops_b = local_model(p, 0, 16, 16)[0]
+            ach = flops_b * lunits / (lms * 1e-3) / 1e12
+            peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
+            res[f"hpsi_{prec}"]["local_kernel_alu"] = {"achieved_tflops": round(ach, 3), "peak": peak,
+                                                       "frac": round(ach / peak, 4)}
+        log("surface hpsi", prec, res[f"hpsi_{prec}"])
+        del x, y
+        torch.cuda.empty_cache()
+    o = p.default_opts()
+    o.max_iter = 1
+    xs = p.lanczos_lowest(0, M, "fp64", opts=o, raise_not_converged=False)[1]  # workspaces, factors
+    del xs
+    eigs = {}
+    for prec in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, xs, info, st = p.lanczos_lowest(0, M, prec, raise_not_converged=False)
+        torch.cuda.synchronize()
+        res[prec] = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": st, "iters": info["iters"],
+                     "iters_reduced_precision": info["iters_low"], "h_applies": info["h_applies"],
+                     "max_resid": info["max_resid"]}
+        eigs[prec] = e
+        del xs
+        torch.cuda.empty_cache()
+        log("surface solve", prec, res[prec])
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
+    res["max_eig_diff_mixed_vs_fp64"] = float(np.max(np.abs(eigs["fp32"] - eigs["fp64"])))
+    p.close()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +284,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
+    ap.add_argument("--no-surface", action="store_true",
+                    help="skip the surface-slab leg (320 bands: hpsi per precision, eigenpairs of one k-point)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
                     help="problems of the uneven batch whose eigenpairs are timed (all their k-points)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -392,6 +464,7 @@ def main(argv=None):
 
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
     c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
+    surf = None if args.no_surface else surface_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -427,6 +500,7 @@ def main(argv=None):
         "autotune_k0": {k: v[0] for k, v in tuned.items()},
         "batched_48": batched,
         "supercell_2x2": c3,
+        "surface": surf,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -8,6 +8,7 @@
 // Kleinman-Bylander expansion leave in one pass.  s_solve and the
 // preconditioner are forward / back substitutions with banded Cholesky factors.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -37,9 +38,11 @@ struct CombineArgs {
     int nbands, ld, ng, nb, nint, np;
 };
 
-// One block per (band, chunk of CH rows, 256 columns); items == nullptr: one
-// problem described by a0, else a batch (item t owns blocks [unit_begin[t], unit_begin[t+1])).
-template <typename TI, typename T>
+// One block per (group of BB bands, chunk of CH rows, 256 columns); items == nullptr:
+// one problem described by a0, else a batch (item t owns blocks [unit_begin[t],
+// unit_begin[t+1])).  With BB > 1 every F_p(G) and Z_p(i) loaded for the projector
+// expansion serves BB bands (many projectors: the expansion dominates the pass).
+template <typename TI, typename T, int BB>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const CombineArgs<TI, T>* items,
                                                  const int32_t* unit_begin, int nitems) {
     unsigned L = blockIdx.x;
@@ -53,96 +56,118 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
     const int g = (int)(L % ncol) * 256 + threadIdx.x;
     const int row = (int)(L / ncol);
     const int nchunk = (a.nb + CH - 1) / CH;
-    const int b = row / nchunk;
-    const int i0 = (row - b * nchunk) * CH;
-    if (g >= a.ld || b >= a.nbands) return;
-    const size_t vb = (size_t)b * a.nb * a.ld;
+    const int bgrp = row / nchunk;
+    const int i0 = (row - bgrp * nchunk) * CH;
+    const int b0 = bgrp * BB;
+    if (g >= a.ld || b0 >= a.nbands) return;
+    const int nbg = min(BB, a.nbands - b0);
     const int i1 = min(i0 + CH, a.nb);
     if (g >= a.ng) {
-        for (int i = i0; i < i1; ++i) {
-            if (a.y) a.y[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
-            if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
+        for (int bb = 0; bb < nbg; ++bb) {
+            const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
+            for (int i = i0; i < i1; ++i) {
+                if (a.y) a.y[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
+                if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>(0, 0);
+            }
         }
         return;
     }
-    const cx<TI>* cb = a.c + vb + g;
     // projector expansion of the chunk's rows, sum_p F_p(G) Z_p(i) P'_p(b): each
-    // F_p(G) is loaded once for all CH rows
-    cx<T> nl[CH];
+    // F_p(G) is loaded once for all CH rows and BB bands
+    cx<T> nl[BB][CH];
 #pragma unroll
-    for (int r = 0; r < CH; ++r) nl[r] = mk<T>(0, 0);
+    for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+        for (int r = 0; r < CH; ++r) nl[bb][r] = mk<T>(0, 0);
     if (a.y && a.proj) {
         for (int p = 0; p < a.np; ++p) {
             const int lo = max(a.zwin[2 * p], i0), hi = min(a.zwin[2 * p + 1], i1 - 1);
             if (lo > hi) continue;
-            const cx<T> fp = cmul(a.F[(size_t)p * a.ld + g], a.proj[(size_t)b * a.np + p]);
+            const cx<T> f = a.F[(size_t)p * a.ld + g];
             const T* zp = a.Z + (size_t)p * a.nb;
+            T z[CH];
 #pragma unroll
             for (int r = 0; r < CH; ++r) {
                 const int i = i0 + r;
-                if (i >= lo && i <= hi) {
-                    const T z = zp[i];
-                    nl[r].x = fma(z, fp.x, nl[r].x);
-                    nl[r].y = fma(z, fp.y, nl[r].y);
+                z[r] = (i >= lo && i <= hi) ? zp[i] : (T)0;
+            }
+#pragma unroll
+            for (int bb = 0; bb < BB; ++bb) {
+                if (bb < nbg) {
+                    const cx<T> fp = cmul(f, a.proj[(size_t)(b0 + bb) * a.np + p]);
+#pragma unroll
+                    for (int r = 0; r < CH; ++r) {
+                        const int i = i0 + r;
+                        if (i >= lo && i <= hi) {
+                            nl[bb][r].x = fma(z[r], fp.x, nl[bb][r].x);
+                            nl[bb][r].y = fma(z[r], fp.y, nl[bb][r].y);
+                        }
+                    }
                 }
             }
         }
-    }
-    // sliding window of c rows i-3 .. i+3 in TI precision
-    cx<TI> w[2 * KORD - 1];
-#pragma unroll
-    for (int d = 0; d < 2 * KORD - 1; ++d) {
-        int j = i0 - (KORD - 1) + d;
-        w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
     }
     const double kk = a.y ? 0.5 * a.kg2[g] : 0.0;
 #pragma unroll
-    for (int r = 0; r < CH; ++r) {
-        const int i = i0 + r;
-        if (i >= i1) break;
-        // banded products with symmetric S_z, D_z
-        double sr = 0, si = 0, tr = 0, ti = 0;
+    for (int bb = 0; bb < BB; ++bb) {
+        if (bb >= nbg) break;
+        const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
+        const cx<TI>* cb = a.c + vb + g;
+        // sliding window of c rows i-3 .. i+3 in TI precision
+        cx<TI> w[2 * KORD - 1];
 #pragma unroll
-        for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
-            int j = i + d;
-            if (j < 0 || j >= a.nb) continue;
-            int lo = d >= 0 ? i : j;
-            int dd = d >= 0 ? d : -d;
-            double sv = a.sband[lo * KORD + dd];
-            cx<TI> cv = w[d + KORD - 1];
-            sr += sv * (double)cv.x;
-            si += sv * (double)cv.y;
-            if (a.y) {
-                double tv = 0.5 * a.dband[lo * KORD + dd];
-                tr += tv * (double)cv.x;
-                ti += tv * (double)cv.y;
-            }
+        for (int d = 0; d < 2 * KORD - 1; ++d) {
+            int j = i0 - (KORD - 1) + d;
+            w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
         }
-        if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
-        if (a.y) {
-            double yr = tr + kk * sr, yi = ti + kk * si;
-            if (a.part) {
-                T pr = 0, pi = 0;
 #pragma unroll
-                for (int t = 0; t < KORD; ++t) {
-                    int s = i + 1 - t;
-                    if (s < 0 || s >= a.nint) continue;
-                    cx<T> v = a.part[(((size_t)b * a.nint + s) * KORD + t) * a.ld + g];
-                    pr += v.x;
-                    pi += v.y;
+        for (int r = 0; r < CH; ++r) {
+            const int i = i0 + r;
+            if (i >= i1) break;
+            // banded products with symmetric S_z, D_z
+            double sr = 0, si = 0, tr = 0, ti = 0;
+#pragma unroll
+            for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
+                int j = i + d;
+                if (j < 0 || j >= a.nb) continue;
+                int lo = d >= 0 ? i : j;
+                int dd = d >= 0 ? d : -d;
+                double sv = a.sband[lo * KORD + dd];
+                cx<TI> cv = w[d + KORD - 1];
+                sr += sv * (double)cv.x;
+                si += sv * (double)cv.y;
+                if (a.y) {
+                    double tv = 0.5 * a.dband[lo * KORD + dd];
+                    tr += tv * (double)cv.x;
+                    ti += tv * (double)cv.y;
                 }
-                yr += (double)pr;
-                yi += (double)pi;
             }
-            yr += (double)nl[r].x;
-            yi += (double)nl[r].y;
-            a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
-        }
-        // slide the window
+            if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
+            if (a.y) {
+                double yr = tr + kk * sr, yi = ti + kk * si;
+                if (a.part) {
+                    T pr = 0, pi = 0;
 #pragma unroll
-        for (int d = 0; d < 2 * KORD - 2; ++d) w[d] = w[d + 1];
-        int jn = i + KORD;
-        w[2 * KORD - 2] = (jn < a.nb) ? cb[(size_t)jn * a.ld] : mk<TI>(0, 0);
+                    for (int t = 0; t < KORD; ++t) {
+                        int s = i + 1 - t;
+                        if (s < 0 || s >= a.nint) continue;
+                        cx<T> v = a.part[(((size_t)(b0 + bb) * a.nint + s) * KORD + t) * a.ld + g];
+                        pr += v.x;
+                        pi += v.y;
+                    }
+                    yr += (double)pr;
+                    yi += (double)pi;
+                }
+                yr += (double)nl[bb][r].x;
+                yi += (double)nl[bb][r].y;
+                a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
+            }
+            // slide the window
+#pragma unroll
+            for (int d = 0; d < 2 * KORD - 2; ++d) w[d] = w[d + 1];
+            int jn = i + KORD;
+            w[2 * KORD - 2] = (jn < a.nb) ? cb[(size_t)jn * a.ld] : mk<TI>(0, 0);
+        }
     }
 }
 
@@ -312,19 +337,31 @@ CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const vo
     return a;
 }
 
-inline int64_t combine_blocks(int nb, int ld, int nbands) {
-    return (int64_t)((ld + 255) / 256) * nbands * ((nb + CH - 1) / CH);
+inline int64_t combine_blocks(int nb, int ld, int nbands, int bb = 1) {
+    return (int64_t)((ld + 255) / 256) * ((nbands + bb - 1) / bb) * ((nb + CH - 1) / CH);
 }
+
+// bands per thread of the combine kernel: 4 when the projector expansion dominates
+// the pass (many projectors), else 1 (more workgroups for small band counts)
+constexpr int COMBINE_BB_NP = 64;
 
 template <typename TI, typename T>
 mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
                        void* sy, int nbands, int ld, hipStream_t s) {
     CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld);
-    const int64_t nblk = combine_blocks(p->nb, ld, nbands);
+    bool wide = y && a.proj && p->np >= COMBINE_BB_NP;
+    if (wide) {
+        const char* e = getenv("MBKS_COMBINE_BB");  // "1": one band per thread (cross-checks)
+        if (e && e[0] == '1' && e[1] == 0) wide = false;
+    }
+    const int64_t nblk = combine_blocks(p->nb, ld, nbands, wide ? 4 : 1);
     if (nblk == 0) return MB_OK;
     if (nblk > (int64_t)1 << 24) return set_error(MB_ERR_INVALID_ARG, "block too large for the combine kernel");
     StageScope ts_(y ? MB_STAGE_COMBINE : MB_STAGE_SPSI, s, nbands);
-    hipLaunchKernelGGL((k_combine<TI, T>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    if (wide)
+        hipLaunchKernelGGL((k_combine<TI, T, 4>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    else
+        hipLaunchKernelGGL((k_combine<TI, T, 1>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -351,7 +388,7 @@ mb_status combine_batch_impl(const std::vector<BatchItem>& items, TableUploader&
     MB_HIP_TRY(hipMemcpyAsync(da, ha, args.size() * sizeof(args[0]), hipMemcpyHostToDevice, s));
     MB_HIP_TRY(hipMemcpyAsync(db, hb, begin.size() * 4, hipMemcpyHostToDevice, s));
     StageScope ts_(MB_STAGE_COMBINE, s, tot_bands);
-    hipLaunchKernelGGL((k_combine<TI, T>), dim3((unsigned)units), dim3(256), 0, s, args[0],
+    hipLaunchKernelGGL((k_combine<TI, T, 1>), dim3((unsigned)units), dim3(256), 0, s, args[0],
                        (const CombineArgs<TI, T>*)da, (const int32_t*)db, (int)args.size());
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;

@@ -121,6 +121,51 @@ def test_hpsi_full_size_sampled_rows(cfg, ik, prec):
     p.close()
 
 
+_SURFACE_ROWS = {}
+
+
+def _surface_oracle_rows(ik, nbands):
+    """Oracle rows of H x and S x for the 128x64 surface slab (computed once per
+    module: sampling the 64-atom potential on the touched planes dominates)."""
+    key = (ik, nbands)
+    if key not in _SURFACE_ROWS:
+        d = workloads.surface()
+        p = mbks.Problem(d, device=0)
+        dm = p.dims(ik)
+        m, _ = p.gvectors(ik)
+        p.close()
+        perm = gperm(m, lattice.gset(d, ik)[0])
+        x = random_lib_block(17, nbands, dm["nb"], dm["ng"], dm["ld"])
+        xo = np.zeros((nbands, dm["nb"], dm["ng"]), dtype=np.complex128)
+        xo[:, :, perm] = x[:, :, :dm["ng"]]
+        # first, middle and last spline rows (edge and interior knot intervals)
+        picks = [(0, 0), (dm["nb"] // 2, dm["ng"] // 3), (dm["nb"] - 1, dm["ng"] - 1)]
+        Hr, Sr = rows.RowOracle(d, ik).apply_rows(xo, [(i, perm[g]) for i, g in picks])
+        _SURFACE_ROWS[key] = (x, picks, Hr, Sr)
+    return _SURFACE_ROWS[key]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_hpsi_surface_sampled_rows(prec):
+    # the largest slab (128x64 grid, 192 splines with 6 Gauss points, 256
+    # projectors on the matrix cores in FP32 / BF16x3) at its full size, k-point 5
+    ik, nbands = 5, 4
+    print(f"[case] hpsi sampled surface k{ik} {prec}", flush=True)
+    x, picks, Hr, Sr = _surface_oracle_rows(ik, nbands)
+    p = mbks.Problem(workloads.surface(), device=0)
+    ng = p.dims(ik)["ng"]
+    y = _run(p, "hpsi", ik, x, prec)
+    sy = _run(p, "spsi", ik, x, "fp64" if prec == "fp64" else "fp32")
+    p.close()
+    got_h = np.array([y[:, i, g] for i, g in picks]).T
+    got_s = np.array([sy[:, i, g] for i, g in picks]).T
+    tol = {"fp64": 1e-11, "fp32": 2e-5, "bf16x3": 1e-4}[prec]
+    assert np.max(np.abs(got_h - Hr)) < tol * np.max(np.abs(y))
+    assert np.max(np.abs(got_s - Sr)) < tol * np.max(np.abs(sy))
+    # padding columns of the output are written as zero
+    assert np.all(y[:, :, ng:] == 0)
+
+
 def test_hermiticity_on_gpu():
     # <x, H y> = conj <y, H x> for the matrix-free operator (no dense matrix)
     d = workloads.graphene()
@@ -165,6 +210,28 @@ def test_line_kernel_matches_generic_kernel(cfg, prec, monkeypatch):
     monkeypatch.delenv("MBKS_LOCAL_KERNEL")
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert rel_err(y_lines, y_gen) < tol
+    p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_combine_band_blocks_many_projectors(prec, monkeypatch):
+    # 16 atoms = 64 projectors: the combine pass expands the projectors for four
+    # bands per thread; 5 bands leave a ragged last group of one band.  Checked
+    # against the dense oracle and against the one-band-per-thread form
+    d = workloads.micro(seed=11, natoms=16, mmax=2, nint=11, grid=8)
+    p, dm, perm = _setup(d)
+    assert dm["np"] == 64
+    H = operators.Problem(d, 0).hamiltonian()
+    x = random_lib_block(43, 5, dm["nb"], dm["ng"], dm["ld"])
+    ref = oracle_to_lib((H @ lib_to_oracle(x, dm["ng"], perm).T).T, dm["nb"], dm["ng"], dm["ld"], perm)
+    y4 = _run(p, "hpsi", 0, x, prec)
+    monkeypatch.setenv("MBKS_COMBINE_BB", "1")
+    y1 = _run(p, "hpsi", 0, x, prec)
+    monkeypatch.delenv("MBKS_COMBINE_BB")
+    tol = {"fp64": 1e-11, "fp32": 2e-5, "bf16x3": 1e-4}[prec]
+    assert rel_err(y4, ref) < tol
+    # same operations in the same order per output element
+    assert np.max(np.abs(y4 - y1)) <= 1e-15 * np.max(np.abs(y1))
     p.close()
 
 
