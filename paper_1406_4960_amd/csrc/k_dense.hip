@@ -737,35 +737,75 @@ __global__ __launch_bounds__(NT) void k_geneig(const zc* Hs, const zc* Ss, int N
                 }
                 __syncthreads();
                 if (!s_rot[r & 1]) continue;  // nothing rotates this round (uniform branch)
-                // rows p, q of every pair:
+                // One pass over A and V.  A: every 2x2 block (rows of pair ia, columns of
+                // pair ib) is owned by one thread, which applies the row rotation of pair ia
                 //   a_pj' = c a_pj - s e^{i phi} a_qj ; a_qj' = s e^{-i phi} a_pj + c a_qj
-                for (int e = tid; e < npair * N; e += NT) {
-                    const int pi = e / N, j = e - pi * N;
-                    const int p = rp[pi], q = rq[pi];
-                    if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                    const double c = rc[pi];
-                    const zc se = mk<double>(rsr[pi], rsi[pi]);
-                    const zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                    const zc ap = P1[(size_t)p * N + j], aq = P1[(size_t)q * N + j];
-                    P1[(size_t)p * N + j] = csub(cscale(ap, c), cmul(se, aq));
-                    P1[(size_t)q * N + j] = cadd(cmul(sec, ap), cscale(aq, c));
-                }
-                __syncthreads();
-                // columns p, q of A and V:
+                // and then the column rotation of pair ib
                 //   a_ip' = c a_ip - s e^{-i phi} a_iq ; a_iq' = s e^{i phi} a_ip + c a_iq
-                for (int e = tid; e < npair * N; e += NT) {
-                    const int pi = e / N, i = e - pi * N;
-                    const int p = rp[pi], q = rq[pi];
-                    if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
-                    const double c = rc[pi];
-                    const zc se = mk<double>(rsr[pi], rsi[pi]);
-                    const zc sec = mk<double>(rsr[pi], -rsi[pi]);
-                    const zc ap = P1[(size_t)i * N + p], aq = P1[(size_t)i * N + q];
-                    P1[(size_t)i * N + p] = csub(cscale(ap, c), cmul(sec, aq));
-                    P1[(size_t)i * N + q] = cadd(cmul(se, ap), cscale(aq, c));
-                    const zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
-                    P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
-                    P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+                // (the pairs are disjoint, so this equals a full row pass followed by a full
+                // column pass, operation for operation).  V: columns p, q of every pair.
+                {
+                    const int nblk = npair * npair;
+                    for (int e = tid; e < nblk + npair * N; e += NT) {
+                        if (e < nblk) {
+                            const int ia = e / npair, ib = e - ia * npair;
+                            const int pa = rp[ia], qa = rq[ia], pb = rp[ib], qb = rq[ib];
+                            const bool va = qa < N, vb = qb < N;  // second row / column exists
+                            const bool ra = va && (rsr[ia] != 0.0 || rsi[ia] != 0.0);
+                            const bool rb = vb && (rsr[ib] != 0.0 || rsi[ib] != 0.0);
+                            if (!ra && !rb) continue;
+                            const zc zero = mk<double>(0, 0);
+                            zc x00 = P1[(size_t)pa * N + pb];
+                            zc x01 = vb ? P1[(size_t)pa * N + qb] : zero;
+                            zc x10 = va ? P1[(size_t)qa * N + pb] : zero;
+                            zc x11 = (va && vb) ? P1[(size_t)qa * N + qb] : zero;
+                            if (ra) {
+                                const double c = rc[ia];
+                                const zc se = mk<double>(rsr[ia], rsi[ia]);
+                                const zc sec = mk<double>(rsr[ia], -rsi[ia]);
+                                const zc n00 = csub(cscale(x00, c), cmul(se, x10));
+                                const zc n10 = cadd(cmul(sec, x00), cscale(x10, c));
+                                x00 = n00;
+                                x10 = n10;
+                                if (vb) {
+                                    const zc n01 = csub(cscale(x01, c), cmul(se, x11));
+                                    const zc n11 = cadd(cmul(sec, x01), cscale(x11, c));
+                                    x01 = n01;
+                                    x11 = n11;
+                                }
+                            }
+                            if (rb) {
+                                const double c = rc[ib];
+                                const zc se = mk<double>(rsr[ib], rsi[ib]);
+                                const zc sec = mk<double>(rsr[ib], -rsi[ib]);
+                                const zc n00 = csub(cscale(x00, c), cmul(sec, x01));
+                                const zc n01 = cadd(cmul(se, x00), cscale(x01, c));
+                                x00 = n00;
+                                x01 = n01;
+                                if (va) {
+                                    const zc n10 = csub(cscale(x10, c), cmul(sec, x11));
+                                    const zc n11 = cadd(cmul(se, x10), cscale(x11, c));
+                                    x10 = n10;
+                                    x11 = n11;
+                                }
+                            }
+                            P1[(size_t)pa * N + pb] = x00;
+                            if (vb) P1[(size_t)pa * N + qb] = x01;
+                            if (va) P1[(size_t)qa * N + pb] = x10;
+                            if (va && vb) P1[(size_t)qa * N + qb] = x11;
+                        } else {
+                            const int f = e - nblk;
+                            const int pi = f / N, i = f - pi * N;
+                            const int p = rp[pi], q = rq[pi];
+                            if (q >= N || (rsr[pi] == 0.0 && rsi[pi] == 0.0)) continue;
+                            const double c = rc[pi];
+                            const zc se = mk<double>(rsr[pi], rsi[pi]);
+                            const zc sec = mk<double>(rsr[pi], -rsi[pi]);
+                            const zc vp = P2[(size_t)i * N + p], vq = P2[(size_t)i * N + q];
+                            P2[(size_t)i * N + p] = csub(cscale(vp, c), cmul(sec, vq));
+                            P2[(size_t)i * N + q] = cadd(cmul(se, vp), cscale(vq, c));
+                        }
+                    }
                 }
                 __syncthreads();
             }

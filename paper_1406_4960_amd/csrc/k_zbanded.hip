@@ -21,6 +21,9 @@ namespace {
 
 constexpr int KORD = 4;
 constexpr int CH = 4;  // rows per thread in the combine kernel
+// banded solves launched with at most this many 64-thread blocks (about 4 waves per CU)
+// keep 8 rows of loads in flight per thread, larger launches 4
+constexpr int64_t SOLVE_SMALL_WAVES = 1024;
 
 template <typename TI, typename T>
 struct CombineArgs {
@@ -254,7 +257,9 @@ __device__ inline void band_solve(const cx<TI>* r, cx<TI>* x, const double* lf, 
     }
 }
 
-template <typename TI>
+// U rows of loads in flight per thread: 8 for small launches (a few waves per CU, the
+// solve is one chain of dependent rows per thread), 4 for large ones (occupancy)
+template <typename TI, int U>
 __global__ __launch_bounds__(64) void k_ssolve(const cx<TI>* r, cx<TI>* x, const double* lband, int nbands,
                                                 int ng, int nb, int ld) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(64) void k_ssolve(const cx<TI>* r, cx<TI>* x, const
         for (int i = 0; i < nb; ++i) x[vb + (size_t)i * ld + g] = mk<TI>(0, 0);
         return;
     }
-    band_solve<TI>(r + vb, x + vb, lband, nb, ld, g, 0, 0.0, nullptr);
+    band_solve<TI, U>(r + vb, x + vb, lband, nb, ld, g, 0, 0.0, nullptr);
 }
 
 // banded Cholesky of kin (1/2 D_z + 1/2 |k+G|^2 S_z) + shift S_z for every G
@@ -295,6 +300,7 @@ __global__ void k_prec_factor(double* pf, const double* sband, const double* dba
     }
 }
 
+template <int U>
 __global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx<double>* sv,
                                                     const double* theta, const int32_t* sel, cx<double>* x,
                                                     const double* pf, int nvec, int ng, int nb, int ld) {
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx
         for (int i = 0; i < nb; ++i) x[vo + (size_t)i * ld + g] = mk<double>(0, 0);
         return;
     }
-    band_solve<double>(h + vi, x + vo, pf, nb, ld, g, 1, theta ? theta[j] : 0.0, sv ? sv + vi : nullptr);
+    band_solve<double, U>(h + vi, x + vo, pf, nb, ld, g, 1, theta ? theta[j] : 0.0, sv ? sv + vi : nullptr);
 }
 
 template <typename TI, typename T>
@@ -420,12 +426,16 @@ mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, 
     const KPoint& kp = p->kp[ik];
     dim3 grid((ld + 63) / 64, nbands);
     StageScope ts_(MB_STAGE_SSOLVE, s, nbands);
-    if (prec == 1)
-        hipLaunchKernelGGL(k_ssolve<float>, grid, dim3(64), 0, s, (const cx<float>*)r, (cx<float>*)x,
-                           p->d_lband, nbands, kp.ng, p->nb, ld);
-    else
-        hipLaunchKernelGGL(k_ssolve<double>, grid, dim3(64), 0, s, (const cx<double>*)r, (cx<double>*)x,
-                           p->d_lband, nbands, kp.ng, p->nb, ld);
+    const bool small = (int64_t)grid.x * grid.y <= SOLVE_SMALL_WAVES;
+    if (prec == 1) {
+        auto kern = small ? k_ssolve<float, 8> : k_ssolve<float, 4>;
+        hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, (const cx<float>*)r, (cx<float>*)x, p->d_lband, nbands,
+                           kp.ng, p->nb, ld);
+    } else {
+        auto kern = small ? k_ssolve<double, 8> : k_ssolve<double, 4>;
+        hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, (const cx<double>*)r, (cx<double>*)x, p->d_lband, nbands,
+                           kp.ng, p->nb, ld);
+    }
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -457,7 +467,8 @@ mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, c
     if (!kp.d_pfac || ld != kp.ld) return set_error(MB_ERR_INVALID_ARG, "preconditioner not built for this ld");
     dim3 grid((ld + 63) / 64, nvec);
     StageScope ts_(MB_STAGE_PRECOND, s, nvec);
-    hipLaunchKernelGGL(k_prec_apply, grid, dim3(64), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
+    auto kern = (int64_t)grid.x * grid.y <= SOLVE_SMALL_WAVES ? k_prec_apply<8> : k_prec_apply<4>;
+    hipLaunchKernelGGL(kern, grid, dim3(64), 0, s, (const cx<double>*)h, (const cx<double>*)sv, theta,
                        sel, (cx<double>*)x, kp.d_pfac, nvec, kp.ng, p->nb, ld);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
