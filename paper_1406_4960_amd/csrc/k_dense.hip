@@ -193,6 +193,98 @@ __global__ __launch_bounds__(256) void k_gram64(const zc* const* ta, const zc* c
         }
 }
 
+// The same 64 x 64 tiles on the FP64 matrix cores (v_mfma_f64_16x16x4_f64): each wave
+// owns a 32 x 32 quarter of the tile as 2 x 2 MFMA tiles.  With a = A_m[k], b = B_n[k],
+//   Re sum conj(a) b = sum a.x b.x + sum a.y b.y,  Im = sum a.x b.y + sum (-a.y) b.x,
+// four real 16x16x4 products per tile and k step.  Lane layout of the instruction
+// (checked on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4r + l/16][l%16], r < 4 (unlike the FP32 16x16x4 form, whose D rows are 4(l/16) + r).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gram_mfma(const zc* const* ta, const zc* const* tb, int MA, int NB,
+                                                   int64_t K, int64_t kchunk, int nchunk, int tiles_m, int tiles_n,
+                                                   zc* part) {
+    __shared__ zc As[G64][GK64 + 1];
+    __shared__ zc Bs[G64][GK64 + 1];
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int ntile = tiles_m * tiles_n;
+    const int tile = (int)(L % ntile);
+    const int chunk = (int)((L / ntile) % nchunk);
+    const int z = (int)(L / ntile / nchunk);
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int m0 = tm * G64, n0 = tn * G64;
+    const int64_t k0 = (int64_t)chunk * kchunk;
+    const int64_t k1 = min(K, k0 + kchunk);
+    const int lk = threadIdx.x % GK64, lr = threadIdx.x / GK64;  // loader: rows lr + 16 u, column lk
+    const zc* arow[4];
+    const zc* brow[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int r = lr + 16 * u;
+        arow[u] = m0 + r < MA ? ta[(size_t)z * MA + m0 + r] : nullptr;
+        brow[u] = n0 + r < NB ? tb[(size_t)z * NB + n0 + r] : nullptr;
+    }
+    zc pa[4], pb[4];
+    auto fetch = [&](int64_t kb) {
+        const int64_t k = kb + lk;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pa[u] = (k < k1 && arow[u]) ? arow[u][k] : mk<double>(0, 0);
+            pb[u] = (k < k1 && brow[u]) ? brow[u][k] : mk<double>(0, 0);
+        }
+    };
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = (wave / 2) * 32, wc = (wave % 2) * 32;  // this wave's quarter of the tile
+    const int li = lane % 16, lg = lane / 16;
+    mfma_d4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cr[a][c] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+            ci[a][c] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+        }
+    if (k0 < k1) fetch(k0);
+    for (int64_t kb = k0; kb < k1; kb += GK64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[lr + 16 * u][lk] = pa[u];
+            Bs[lr + 16 * u][lk] = pb[u];
+        }
+        __syncthreads();
+        if (kb + GK64 < k1) fetch(kb + GK64);
+#pragma unroll
+        for (int st = 0; st < GK64 / 4; ++st) {
+            const int kk = 4 * st + lg;
+            zc av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[wr + 16 * a + li][kk];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bv[c] = Bs[wc + 16 * c + li][kk];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    cr[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[c].x, cr[a][c], 0, 0, 0);
+                    cr[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[c].y, cr[a][c], 0, 0, 0);
+                    ci[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[c].y, ci[a][c], 0, 0, 0);
+                    ci[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[a].y, bv[c].x, ci[a][c], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wr + 16 * a + 4 * r + lg, n = n0 + wc + 16 * c + li;
+                if (m < MA && n < NB)
+                    part[(((size_t)z * nchunk + chunk) * MA + m) * NB + n] = mk<double>(cr[a][c][r], ci[a][c][r]);
+            }
+}
+
 // narrow products (MA <= 16): block (chunk, n, z) streams its k range once, each
 // thread accumulating conj(A_m[k]) B_n[k] for every m in registers; wave shuffles
 // and one LDS pass reduce the block's MA sums into part[z][chunk][m][n]
@@ -1043,6 +1135,13 @@ static bool gram64_enabled() {
     return on;
 }
 
+// the wide Gram products run on the FP64 matrix cores unless MBKS_GRAM_MFMA=0 (read per
+// call, for cross-checks against the vector kernel)
+static bool gram_mfma_enabled() {
+    const char* e = getenv("MBKS_GRAM_MFMA");
+    return !(e && e[0] == '0');
+}
+
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
                      void* scratch, size_t scratch_bytes, hipStream_t s) {
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
@@ -1077,6 +1176,10 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     else if (skinny)
         hipLaunchKernelGGL(k_gram_skinny, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB,
                            K, kchunk, nchunk, (zc*)scratch);
+    else if (wide && gram_mfma_enabled())
+        hipLaunchKernelGGL(k_gram_mfma, dim3((unsigned)(tiles_m * tiles_n * nchunk * nz)), dim3(256), 0, s,
+                           (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk, tiles_m, tiles_n,
+                           (zc*)scratch);
     else if (wide)
         hipLaunchKernelGGL(k_gram64, dim3((unsigned)(tiles_m * tiles_n * nchunk * nz)), dim3(256), 0, s,
                            (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk, tiles_m, tiles_n,

@@ -141,3 +141,24 @@ def test_lanczos_buffer_vectors(extra):
     orth, res = _check_vectors(p, 0, x, eig, nev)
     assert orth < 1e-10 and np.max(res) < 1e-6
     p.close()
+
+
+@pytest.mark.parametrize("mfma", ["1", "0"])
+def test_lanczos_many_roots_wide_gram(mfma, monkeypatch):
+    # 280 roots of the tiny cell (296 iterated vectors with the buffer, 298 with the
+    # global Krylov vectors): the Gram products of the global Rayleigh-Ritz step take
+    # the 64 x 64-tile path, on the FP64 matrix cores (mfma = 1) or the vector kernel
+    d = workloads.tiny()
+    nev = 280
+    print(f"[case] lanczos tiny nev={nev} gram_mfma={mfma}", flush=True)
+    monkeypatch.setenv("MBKS_GRAM_MFMA", mfma)
+    ref = solve.solve_problem(d, 0, nev=nev)[3]
+    p = mbks.Problem(d, device=0)
+    eig, x, info, st = p.lanczos_lowest(0, nev, "fp64")
+    print(info, flush=True)
+    assert st == 0
+    assert np.max(np.abs(eig - ref)) < 1e-8
+    orth, res = _check_vectors(p, 0, x, eig, nev)
+    assert orth < 1e-10
+    assert np.max(res) < 1e-6
+    p.close()
