@@ -146,11 +146,12 @@ def test_lanczos_buffer_vectors(extra):
 @pytest.mark.parametrize("mfma", ["1", "0"])
 def test_lanczos_many_roots_wide_gram(mfma, monkeypatch):
     # 280 roots of the tiny cell (296 iterated vectors with the buffer, 298 with the
-    # global Krylov vectors): the Gram products of the global Rayleigh-Ritz step take
-    # the 64 x 64-tile path, on the FP64 matrix cores (mfma = 1) or the vector kernel
+    # global Krylov vectors): the Gram products of the global Rayleigh-Ritz and
+    # orthogonalisation steps take the 64 x 64-tile path, on the FP64 matrix cores
+    # (mfma = 1) or the vector kernel (mfma = 0)
     d = workloads.tiny()
     nev = 280
-    print(f"[case] lanczos tiny nev={nev} gram_mfma={mfma}", flush=True)
+    print(f"[case] lanczos tiny nev={nev} mfma={mfma}", flush=True)
     monkeypatch.setenv("MBKS_GRAM_MFMA", mfma)
     ref = solve.solve_problem(d, 0, nev=nev)[3]
     p = mbks.Problem(d, device=0)
