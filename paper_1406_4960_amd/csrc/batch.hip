@@ -80,13 +80,13 @@ mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUplo
             it.proj = nullptr;
             continue;
         }
-        // as in the single-item operator: matrix cores for BF16x3 and for FP32 with at
-        // least 64 projectors, the vector kernel otherwise
-        if (prec != 3 && (lp == 0 || it.p->np < 64))
+        // as in the single-item operator: matrix cores for BF16x3 and for FP32 / FP64
+        // with at least 64 projectors, the vector kernel otherwise
+        if (prec != 3 && it.p->np < 64)
             BT_TRY(launch_nl_project(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, lp, s));
         else
-            BT_TRY(launch_nl_project_mfma(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, prec == 3 ? 2 : 1, false,
-                                          s));
+            BT_TRY(launch_nl_project_mfma(it.p, it.ik, it.c, it.proj, it.nbands, it.ld,
+                                          prec == 3 ? 2 : lp == 0 ? 0 : 1, false, s));
     }
     // local potential, grouped by grid
     std::map<std::pair<int, int>, std::vector<BatchItem>> by_grid;

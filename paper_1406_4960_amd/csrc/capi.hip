@@ -209,21 +209,22 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
     if (p->np > 0) {
         MB_TRY(ensure_ws(kp.ws_proj, (size_t)nbands * p->np * csz));
         proj = kp.ws_proj.ptr;
-        // FP32 projections go to the matrix cores once there are enough projectors to
-        // fill their 16-wide tiles (measured: with 8 or 32 projectors the vector kernel
-        // is faster, with 256 the matrix cores are 2.7x faster); BF16x3 always uses them.
-        // MBKS_NL_KERNEL=vector / =mfma forces one FP32 path (used to cross-check them).
+        // FP32 and FP64 projections go to the matrix cores once there are enough
+        // projectors to fill their 16-wide tiles (measured: with 8 or 32 projectors the
+        // vector kernel is faster, with 256 the matrix cores are 2.7x faster in FP32);
+        // BF16x3 always uses them.  MBKS_NL_KERNEL=vector / =mfma forces one path (used
+        // to cross-check them).
         const char* sel = getenv("MBKS_NL_KERNEL");
-        bool vector_path = lp == 0 || p->np < 64;
+        bool vector_path = p->np < 64;
         const KPoint::Tune& tn = kp.tune[lp];
         if (tn.set && tn.nl_mfma >= 0 && lp != 0) vector_path = tn.nl_mfma == 0;
         if (sel && std::string(sel) == "vector") vector_path = true;
-        if (sel && std::string(sel) == "mfma" && lp != 0) vector_path = false;
+        if (sel && std::string(sel) == "mfma") vector_path = false;
         if (prec >= 3) vector_path = false;
         if (vector_path)
             MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, lp, s));
         else
-            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : 1, lp == 2, s));
+            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s));
     }
     MB_TRY(launch_local(p, ik, c, kp.ws_part.ptr, nbands, ld, lp, s));
     MB_TRY(launch_combine(p, ik, c, kp.ws_part.ptr, proj, y, sy, nbands, ld, lp, s));

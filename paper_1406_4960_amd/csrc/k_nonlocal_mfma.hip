@@ -77,6 +77,51 @@ __global__ __launch_bounds__(64) void k_nlproj_f32(const cx<TI>* c, const cx<flo
     }
 }
 
+// the same partials in FP64 on v_mfma_f64_16x16x4_f64, whose output layout differs:
+// lane l holds D[4r + l/16][l%16] (checked on gfx950)
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(64) void k_nlproj_f64(const cx<double>* c, const cx<double>* F, const double* Z,
+                                                   const int32_t* gwin, cx<double>* partial, int nbands, int np,
+                                                   int ng, int nb, int ld, int npad, int nbpad) {
+    const int i = blockIdx.x;
+    const int b0 = blockIdx.y * 16;
+    const int grp = blockIdx.z;
+    if (i < gwin[2 * grp] || i > gwin[2 * grp + 1]) return;
+    const int lane = threadIdx.x;
+    const int m = lane % 16, g = lane / 16;
+    const int p = grp * 16 + m;
+    const int b = b0 + m;
+    const cx<double>* Fp = F + (size_t)min(p, np - 1) * ld;
+    const cx<double>* cb = c + ((size_t)min(b, nbands - 1) * nb + i) * ld;
+    const bool pv = p < np, bv = b < nbands;
+    v4d accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < ng; k0 += 16) {
+        cx<double> fa[4], cv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * g + s;
+            const bool in = k < ng;
+            fa[s] = (pv && in) ? Fp[k] : mk<double>(0, 0);
+            cv[s] = (bv && in) ? cb[k] : mk<double>(0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            accr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].x, cv[s].x, accr, 0, 0, 0);
+            accr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].y, cv[s].y, accr, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].x, cv[s].y, acci, 0, 0, 0);
+            acci = __builtin_amdgcn_mfma_f64_16x16x4f64(-fa[s].y, cv[s].x, acci, 0, 0, 0);
+        }
+    }
+    // D[4r + g][m]: projector row 4r + g of the group, band column m
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int pr = grp * 16 + 4 * r + g;
+        const double z = pr < np ? Z[(size_t)pr * nb + i] : 0.0;
+        partial[((size_t)i * npad + pr) * nbpad + b0 + m] = mk<double>(z * accr[r], z * acci[r]);
+    }
+}
+
 __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
     hi = (__bf16)x;
     lo = (__bf16)(x - (float)hi);
@@ -153,9 +198,27 @@ __global__ void k_nlproj_reduce(const cx<float>* partial, const int32_t* gwin, c
     proj[(size_t)b * np + p] = mk<float>(E[p] * re, E[p] * im);
 }
 
+// FP64 form of the reduction (energies E_p in FP64)
+__global__ void k_nlproj_reduce64(const cx<double>* partial, const int32_t* gwin, const double* E, cx<double>* proj,
+                                  int nbands, int np, int npad, int nbpad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nbands * np) return;
+    const int b = idx / np, p = idx % np;
+    const int grp = p / 16;
+    const int lo = gwin[2 * grp], hi = gwin[2 * grp + 1];
+    double re = 0.0, im = 0.0;
+    for (int i = lo; i <= hi; ++i) {
+        cx<double> v = partial[((size_t)i * npad + p) * nbpad + b];
+        re += v.x;
+        im += v.y;
+    }
+    proj[(size_t)b * np + p] = mk<double>(E[p] * re, E[p] * im);
+}
+
 }  // namespace
 
-// mode 1: FP32 MFMA, mode 2: BF16x3 MFMA; vin64: vectors are complex128
+// mode 0: FP64 MFMA (complex128 vectors), mode 1: FP32 MFMA, mode 2: BF16x3 MFMA;
+// vin64: vectors are complex128
 // union z-window of every group of 16 projectors (set-up, once per problem)
 mb_status upload_group_windows(Problem* p) {
     const int ngrp = (p->np + 15) / 16;
@@ -184,12 +247,23 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
     const int npad = ngrp * 16;
     const int nbpad = (nbands + 15) / 16 * 16;
     if (!p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
-    size_t pbytes = (size_t)p->nb * npad * nbpad * sizeof(cx<float>);
+    size_t pbytes = (size_t)p->nb * npad * nbpad * (mode == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
     KPoint& kw = p->kp[ik];
     mb_status st = ensure_ws(kw.ws_nlpart, pbytes);
     if (st != MB_OK) return st;
     StageScope ts_(MB_STAGE_NL_PROJECT, s, nbands);
     dim3 grid(p->nb, nbpad / 16, ngrp);
+    if (mode == 0) {
+        cx<double>* part64 = (cx<double>*)kw.ws_nlpart.ptr;
+        hipLaunchKernelGGL(k_nlproj_f64, grid, dim3(64), 0, s, (const cx<double>*)c, (const cx<double>*)kp.d_F64,
+                           p->d_Z, p->d_gwin, part64, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
+        MB_HIP_TRY(hipGetLastError());
+        const int tot = nbands * p->np;
+        hipLaunchKernelGGL(k_nlproj_reduce64, dim3((tot + 255) / 256), dim3(256), 0, s, part64, p->d_gwin, p->d_E,
+                           (cx<double>*)proj, nbands, p->np, npad, nbpad);
+        MB_HIP_TRY(hipGetLastError());
+        return MB_OK;
+    }
     cx<float>* part = (cx<float>*)kw.ws_nlpart.ptr;
     const cx<float>* F = (const cx<float>*)kp.d_F32;
     if (mode == 1) {

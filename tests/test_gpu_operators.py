@@ -267,6 +267,13 @@ def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
     assert rel_err(y_mfma, y_vec) < 2e-5
     y_bf = _run(p, "hpsi", 1, x, "bf16x3")
     assert rel_err(y_bf, y_vec) < 1e-4
+    # FP64: the matrix-core and vector contractions differ only in summation order
+    monkeypatch.setenv("MBKS_NL_KERNEL", "mfma")
+    y64_mfma = _run(p, "hpsi", 1, x, "fp64")
+    monkeypatch.setenv("MBKS_NL_KERNEL", "vector")
+    y64_vec = _run(p, "hpsi", 1, x, "fp64")
+    monkeypatch.delenv("MBKS_NL_KERNEL")
+    assert rel_err(y64_mfma, y64_vec) < 1e-13
     p.close()
 
 
