@@ -165,20 +165,21 @@ def test_lanczos_many_roots_wide_gram(mfma, monkeypatch):
     p.close()
 
 
-def test_lanczos_surface_eigenpairs_residual_rows_vs_oracle():
-    # the 4 lowest eigenpairs of the 128x64 surface slab (k-point 0, mixed form)
-    # checked through the oracle's own operator: rows of H x - eps S x evaluated by
-    # the oracle's row evaluator (independent of the library's H) stay below the
-    # residual bar, while the rows carry weight and a 1e-4 Ha shift of eps shows up
+@pytest.mark.parametrize("cfg,ik,nev,prec", [("surface", 0, 4, "fp32"), ("graphene_2x2", 1, 8, "bf16x3")])
+def test_lanczos_eigenpairs_residual_rows_vs_oracle(cfg, ik, nev, prec):
+    # the lowest eigenpairs of the 128x64 surface slab and of the 2x2 supercell
+    # (mixed forms) checked through the oracle's own operator: rows of
+    # H x - eps S x evaluated by the oracle's row evaluator (independent of the
+    # library's H) stay below the residual bar, while the rows carry weight and a
+    # 1e-4 Ha shift of eps shows up
     from oracle import rows
-    d = workloads.surface()
-    ik, nev = 0, 4
-    print(f"[case] lanczos surface k{ik} nev={nev} mixed, oracle residual rows", flush=True)
+    d = workloads.CONFIGS[cfg]()
+    print(f"[case] lanczos {cfg} k{ik} nev={nev} {prec}, oracle residual rows", flush=True)
     p = mbks.Problem(d, device=0)
     dm = p.dims(ik)
     m, _ = p.gvectors(ik)
     perm = gperm(m, lattice.gset(d, ik)[0])
-    eig, x, info, st = p.lanczos_lowest(ik, nev, "fp32")
+    eig, x, info, st = p.lanczos_lowest(ik, nev, prec)
     print(info, eig, flush=True)
     assert st == 0 and info["max_resid"] < 1e-6
     xl = x.cpu().numpy()
