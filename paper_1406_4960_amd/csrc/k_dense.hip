@@ -1155,9 +1155,10 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     int tiles_m = (MA + tile - 1) / tile, tiles_n = (NB + tile - 1) / tile;
     int ntiles = tiny ? nz : skinny ? NB * nz : tiles_m * tiles_n * nz;
     // at least 256 (64 for the wide tiles) k per chunk; about 1024 blocks in all
-    // (4096 for the narrow kernel, whose blocks are short)
+    // (4096 for the narrow kernel, whose blocks are short; the tiny kernel's blocks end
+    // in a reduction of up to 64 sums, so they take longer k ranges)
     int64_t maxchunk = big ? (K + 63) / 64 : (K + 255) / 256;
-    const int target = (tiny || skinny) ? 4096 : 1024;
+    const int target = skinny ? 4096 : tiny ? 512 : 1024;
     int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, target / std::max(1, ntiles)));
     size_t need = (size_t)nz * nchunk * MA * NB * sizeof(zc);
     while (need > scratch_bytes && nchunk > 1) {
