@@ -89,3 +89,15 @@ def test_gpu_calls_on_host_only_handle_fail():
     assert st == -7
     assert b"host-only" in lib.mb_last_error()
     p.close()
+
+
+def test_bench_runs_on_one_gpu_only():
+    # the benchmark measures one GPU; asking for more exits with a message, before
+    # any GPU work
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
