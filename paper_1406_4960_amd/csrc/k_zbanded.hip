@@ -115,23 +115,41 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
     for (int bb = 0; bb < BB; ++bb) {
         if (bb >= nbg) break;
         const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
-        if constexpr (BB == 1) {
-            const cx<TI>* cb = a.c + vb + g;
-            // every load of the band's chunk is issued before its first store (the
-            // outputs may alias nothing the chunk reads, but the compiler cannot know):
-            // c rows i0-3 .. i0+CH+2 and the summed local partials of each row
-            cx<TI> w[CH + 2 * KORD - 2];
+        const cx<TI>* cb = a.c + vb + g;
+        // sliding window of c rows i-3 .. i+3 in TI precision
+        cx<TI> w[2 * KORD - 1];
 #pragma unroll
-            for (int d = 0; d < CH + 2 * KORD - 2; ++d) {
-                int j = i0 - (KORD - 1) + d;
-                w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
+        for (int d = 0; d < 2 * KORD - 1; ++d) {
+            int j = i0 - (KORD - 1) + d;
+            w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < CH; ++r) {
+            const int i = i0 + r;
+            if (i >= i1) break;
+            // banded products with symmetric S_z, D_z
+            double sr = 0, si = 0, tr = 0, ti = 0;
+#pragma unroll
+            for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
+                int j = i + d;
+                if (j < 0 || j >= a.nb) continue;
+                int lo = d >= 0 ? i : j;
+                int dd = d >= 0 ? d : -d;
+                double sv = a.sband[lo * KORD + dd];
+                cx<TI> cv = w[d + KORD - 1];
+                sr += sv * (double)cv.x;
+                si += sv * (double)cv.y;
+                if (a.y) {
+                    double tv = 0.5 * a.dband[lo * KORD + dd];
+                    tr += tv * (double)cv.x;
+                    ti += tv * (double)cv.y;
+                }
             }
-            cx<T> ps[CH];
-#pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                const int i = i0 + r;
-                T pr = 0, pi = 0;
-                if (a.y && a.part && i < i1) {
+            if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
+            if (a.y) {
+                double yr = tr + kk * sr, yi = ti + kk * si;
+                if (a.part) {
+                    T pr = 0, pi = 0;
 #pragma unroll
                     for (int t = 0; t < KORD; ++t) {
                         int s = i + 1 - t;
@@ -140,102 +158,18 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
                         pr += v.x;
                         pi += v.y;
                     }
+                    yr += (double)pr;
+                    yi += (double)pi;
                 }
-                ps[r] = mk<T>(pr, pi);
+                yr += (double)nl[bb][r].x;
+                yi += (double)nl[bb][r].y;
+                a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
             }
+            // slide the window
 #pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                const int i = i0 + r;
-                if (i >= i1) break;
-                // banded products with symmetric S_z, D_z
-                double sr = 0, si = 0, tr = 0, ti = 0;
-#pragma unroll
-                for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
-                    int j = i + d;
-                    if (j < 0 || j >= a.nb) continue;
-                    int lo = d >= 0 ? i : j;
-                    int dd = d >= 0 ? d : -d;
-                    double sv = a.sband[lo * KORD + dd];
-                    cx<TI> cv = w[r + d + KORD - 1];
-                    sr += sv * (double)cv.x;
-                    si += sv * (double)cv.y;
-                    if (a.y) {
-                        double tv = 0.5 * a.dband[lo * KORD + dd];
-                        tr += tv * (double)cv.x;
-                        ti += tv * (double)cv.y;
-                    }
-                }
-                if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
-                if (a.y) {
-                    double yr = tr + kk * sr, yi = ti + kk * si;
-                    if (a.part) {
-                        yr += (double)ps[r].x;
-                        yi += (double)ps[r].y;
-                    }
-                    yr += (double)nl[bb][r].x;
-                    yi += (double)nl[bb][r].y;
-                    a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
-                }
-            }
-        } else {
-            // several bands per thread: keep the register footprint small (sliding
-            // window of c rows, partials loaded row by row)
-            const cx<TI>* cb = a.c + vb + g;
-            // sliding window of c rows i-3 .. i+3 in TI precision
-            cx<TI> w[2 * KORD - 1];
-#pragma unroll
-            for (int d = 0; d < 2 * KORD - 1; ++d) {
-                int j = i0 - (KORD - 1) + d;
-                w[d] = (j >= 0 && j < a.nb) ? cb[(size_t)j * a.ld] : mk<TI>(0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < CH; ++r) {
-                const int i = i0 + r;
-                if (i >= i1) break;
-                // banded products with symmetric S_z, D_z
-                double sr = 0, si = 0, tr = 0, ti = 0;
-#pragma unroll
-                for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
-                    int j = i + d;
-                    if (j < 0 || j >= a.nb) continue;
-                    int lo = d >= 0 ? i : j;
-                    int dd = d >= 0 ? d : -d;
-                    double sv = a.sband[lo * KORD + dd];
-                    cx<TI> cv = w[d + KORD - 1];
-                    sr += sv * (double)cv.x;
-                    si += sv * (double)cv.y;
-                    if (a.y) {
-                        double tv = 0.5 * a.dband[lo * KORD + dd];
-                        tr += tv * (double)cv.x;
-                        ti += tv * (double)cv.y;
-                    }
-                }
-                if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
-                if (a.y) {
-                    double yr = tr + kk * sr, yi = ti + kk * si;
-                    if (a.part) {
-                        T pr = 0, pi = 0;
-#pragma unroll
-                        for (int t = 0; t < KORD; ++t) {
-                            int s = i + 1 - t;
-                            if (s < 0 || s >= a.nint) continue;
-                            cx<T> v = a.part[(((size_t)(b0 + bb) * a.nint + s) * KORD + t) * a.ld + g];
-                            pr += v.x;
-                            pi += v.y;
-                        }
-                        yr += (double)pr;
-                        yi += (double)pi;
-                    }
-                    yr += (double)nl[bb][r].x;
-                    yi += (double)nl[bb][r].y;
-                    a.y[vb + (size_t)i * a.ld + g] = mk<TI>((TI)yr, (TI)yi);
-                }
-                // slide the window
-#pragma unroll
-                for (int d = 0; d < 2 * KORD - 2; ++d) w[d] = w[d + 1];
-                int jn = i + KORD;
-                w[2 * KORD - 2] = (jn < a.nb) ? cb[(size_t)jn * a.ld] : mk<TI>(0, 0);
-            }
+            for (int d = 0; d < 2 * KORD - 2; ++d) w[d] = w[d + 1];
+            int jn = i + KORD;
+            w[2 * KORD - 2] = (jn < a.nb) ? cb[(size_t)jn * a.ld] : mk<TI>(0, 0);
         }
     }
 }
