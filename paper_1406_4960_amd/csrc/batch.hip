@@ -281,7 +281,22 @@ mb_status lanczos_lowest_batched(mb_batch* b, const int* nev, mb_precision prec,
     hipEvent_t ready;
     MB_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     MB_HIP_TRY(hipEventRecord(ready, caller));
-    const int nthreads = mb::timer_enabled() ? 1 : std::max(1, std::min<int>(16, (int)jobs.size()));
+    int nthreads = mb::timer_enabled() ? 1 : std::max(1, std::min<int>(16, (int)jobs.size()));
+    {
+        // as many concurrent solves as the free device memory holds (each solve of a
+        // large slab takes tens of GB of vectors, released when it ends)
+        size_t need = 0;
+        for (const auto& jb : jobs)
+            for (int t : jb.items)
+                need = std::max(need, mb::lanczos_device_bytes(b->items[t].p, b->items[t].ik, nev[t], o));
+        size_t freeb = 0, totb = 0;
+        if (need > 0 && hipMemGetInfo(&freeb, &totb) == hipSuccess) {
+            const size_t fit = (size_t)(0.85 * (double)freeb) / (need + need / 8);
+            nthreads = std::max(1, std::min<int>(nthreads, (int)std::min<size_t>(fit, 16)));
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     std::vector<mb_status> status(n, MB_OK);
     std::vector<std::string> message(n);
     std::atomic<int> next_job{0};

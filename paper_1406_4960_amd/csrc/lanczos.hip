@@ -231,6 +231,50 @@ struct Solver {
 
 }  // namespace
 
+// Shape of one solve: M iterated vectors (nev wanted + buffer), nbl blocks of b, Krylov
+// depth m, global Krylov depth mA.
+struct LzShape {
+    int M, b, nbl, m, mA;
+};
+
+static LzShape lz_shape(const Problem* p, int ik, int nev, const mb_lanczos_opts& o) {
+    const int64_t basis = (int64_t)p->kp[ik].ng * p->nb;
+    int nbuf = o.extra >= 0 ? o.extra : std::min(16, std::max(4, nev / 4));
+    nbuf = (int)std::max<int64_t>(0, std::min<int64_t>(nbuf, basis - nev));
+    LzShape z{};
+    z.M = nev + nbuf;
+    z.b = std::max(1, std::min(o.block, z.M));
+    while (z.M % z.b) --z.b;
+    z.nbl = z.M / z.b;
+    z.m = std::max(1, o.krylov);
+    z.mA = std::max(0, o.krylov_global);
+    return z;
+}
+
+// Vector workspace of one solve: trial vectors X, HX, SX (M + mA), their rotation
+// targets (M), and the block Krylov vectors K, HK, SK (m per block), all complex128.
+size_t lanczos_vector_bytes(const Problem* p, int ik, int nev, const mb_lanczos_opts& o) {
+    const LzShape z = lz_shape(p, ik, nev, o);
+    const size_t nvec = 3 * (size_t)(z.M + z.mA) + 3 * (size_t)z.M + 3 * (size_t)z.m * z.nbl;
+    return nvec * (size_t)p->nb * p->kp[ik].ld * 16;
+}
+
+// Device memory a solve holds at its peak: the vectors above and the partial rows and
+// projector partials of FP64 H applications to M vectors at once (the widest ones).
+size_t lanczos_device_bytes(const Problem* p, int ik, int nev, const mb_lanczos_opts& o) {
+    const KPoint& kp = p->kp[ik];
+    const LzShape z = lz_shape(p, ik, nev, o);
+    const size_t h = (size_t)std::max(z.M, z.nbl);
+    const size_t part = h * (size_t)p->nint * 4 * kp.ld * 16;
+    const size_t nl = (size_t)p->nb * ((p->np + 15) / 16 * 16) * ((h + 15) / 16 * 16) * 16;
+    return lanczos_vector_bytes(p, ik, nev, o) + part + nl;
+}
+
+// a k-point keeps its eigensolver vectors between solves only up to this size; larger
+// ones (hundreds of bands on large slabs) are released so that the solves of several
+// k-points of one problem can follow each other on one GPU
+constexpr size_t LZ_KEEP_BYTES = (size_t)8 << 30;
+
 mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_lanczos_opts& o, const void* x0,
                        double* eig, void* xout, mb_lanczos_info* info, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
@@ -266,6 +310,8 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     // vector workspace
     size_t nvec = 3 * (size_t)S.NG + 3 * (size_t)S.M + 3 * (size_t)S.m * S.nbl;
     KPoint& kw = p->kp[ik];
+    if (nvec * S.vbytes != lanczos_vector_bytes(p, ik, nev, o))
+        return set_error(MB_ERR_INVALID_ARG, "lanczos_lowest: workspace size mismatch");
     LZ_TRY(ensure_ws(kw.ws_lz, nvec * S.vbytes));
     char* base = (char*)kw.ws_lz.ptr;
     auto take = [&](int n) {
@@ -411,6 +457,14 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     }
     if (xout) MB_HIP_TRY(hipMemcpyAsync(xout, S.X, (size_t)nev * S.vbytes, hipMemcpyDeviceToDevice, s));
     MB_HIP_TRY(hipStreamSynchronize(s));
+    if (kw.ws_lz.bytes > LZ_KEEP_BYTES) {
+        // with it go the H-application work buffers sized for this solve
+        for (Workspace* w : {&kw.ws_lz, &kw.ws_part, &kw.ws_nlpart}) {
+            if (w->ptr) MB_HIP_TRY(hipFree(w->ptr));
+            w->ptr = nullptr;
+            w->bytes = 0;
+        }
+    }
     if (eig) std::memcpy(eig, S.h_theta.data(), nev * sizeof(double));
     if (info) {
         info->iters = it;

@@ -211,6 +211,8 @@ mb_status launch_local_batch(const std::vector<BatchItem>& items, int prec, Tabl
 mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s);
 
 // eigensolver (lanczos.hip): arguments already validated
+size_t lanczos_vector_bytes(const Problem* p, int ik, int nev, const mb_lanczos_opts& o);
+size_t lanczos_device_bytes(const Problem* p, int ik, int nev, const mb_lanczos_opts& o);
 mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_lanczos_opts& o, const void* x0,
                        double* eig, void* x, mb_lanczos_info* info, hipStream_t s);
 bool timer_enabled();
