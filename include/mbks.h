@@ -226,6 +226,9 @@ void mb_lanczos_default_opts(mb_lanczos_opts* opts);
  * start.  eig: host, nev doubles (ascending).  x: device complex128
  * [nev][N_b][ld] output, S-orthonormal.  info and opts may be NULL (defaults).
  * Limits: nev + buffer + krylov_global <= 512, block + krylov <= 64.
+ * Device memory: the k-point keeps its solver workspace between calls, except that a
+ * solve whose vectors exceed 8 GiB (hundreds of bands on large slabs) frees them and
+ * the k-point's H work buffers when it returns.  MB_ERR_OOM if they do not fit.
  * Returns MB_ERR_NOT_CONVERGED (outputs filled) after opts->max_iter cycles. */
 mb_status lanczos_lowest(mb_problem* p, int ik, int nev, mb_precision prec,
                          const mb_lanczos_opts* opts, const void* x0, double* eig, void* x,
@@ -261,8 +264,9 @@ mb_status hpsi_apply_batched(mb_batch* b, const void* const* c, void* const* y, 
 /* lanczos_lowest for every item t (nev[t] eigenpairs, eig[t] host nev[t] doubles,
  * x[t] device complex128 [nev[t]][N_b][ld_t] with the item's recommended ld_t,
  * info[t] filled; info may be NULL).  Items are solved concurrently on streams of
- * their own (up to 16 at a time); items naming the same (problem, k-point) one
- * after another;
+ * their own (up to 16 at a time, and no more than the free device memory holds at
+ * the call's start, estimated from the largest item's workspace); items naming the
+ * same (problem, k-point) one after another;
  * `stream` waits for all of them.  opts as for lanczos_lowest (NULL: defaults),
  * x0 = NULL start for every item.  Returns the first error, or
  * MB_ERR_NOT_CONVERGED when some item did not converge (all outputs filled). */
