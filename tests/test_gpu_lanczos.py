@@ -197,3 +197,24 @@ def test_lanczos_eigenpairs_residual_rows_vs_oracle(cfg, ik, nev, prec):
     assert np.max(np.abs(Sr)) > 1e-4
     assert np.max(np.abs(r)) < 1e-6
     assert np.max(np.abs(Hr - (eig[:, None] + 1e-4) * Sr)) > 1e-8
+
+
+def test_large_solve_releases_its_workspace():
+    # a 320-band solve of the surface slab holds ~85 GiB while it runs; afterwards the
+    # k-point keeps less than 2 GiB, so the other k-points' solves fit one after another
+    d = workloads.surface()
+    print("[case] surface 320-band solve, one cycle, workspace release", flush=True)
+    p = mbks.Problem(d, device=0)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(0)[0]
+    o = p.default_opts()
+    o.max_iter = 1
+    eig, x, info, st = p.lanczos_lowest(0, d["nbands"], "fp32", opts=o, raise_not_converged=False)
+    assert st in (0, -3) and info["iters"] == 1
+    del x
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free1 = torch.cuda.mem_get_info(0)[0]
+    print("held after the solve (GiB):", (free0 - free1) / 2**30, flush=True)
+    assert free0 - free1 < 2 * 2**30
+    p.close()
