@@ -18,8 +18,14 @@ solve     : lowest eigenpairs of H c = eps S c by LAPACK (generalized form of
             Sec. II.B.2), residuals.
 rows      : selected rows of H x and S x without a dense matrix (same
             definitions, evaluated one output at a time) for large cells.
+matfree   : matrix-free H x and S x (local part by a dense per-plane sum or
+            through the grid with library FFTs) and the lowest eigenpairs by a
+            library block eigensolver, for cells too large for dense assembly.
 
-Parity status: every function is pinned by the CPU tests against closed forms,
-brute-force quadrature, library routines or mathematical invariants; none is
-"parity unpinned".
+Parity status: every function is pinned by the CPU tests: bspline, lattice and
+operators against closed forms, brute-force quadrature, library routines and
+mathematical invariants (tests/test_oracle_bspline.py, test_oracle_operators.py,
+test_oracle_physics.py); rows and matfree against the dense matrices of
+operators, and matfree's eigensolver against LAPACK (test_oracle_operators.py,
+test_oracle_matfree.py).  None is "parity unpinned".
 """

@@ -97,6 +97,37 @@ def potential_on_grid(desc, zq: np.ndarray, vfunc=None) -> np.ndarray:
     return np.broadcast_to(vfunc(x, y, z), (len(zq),) + rho.shape[:2]).astype(np.float64)
 
 
+def gaussian_potential_on_grid_separable(desc, zq: np.ndarray) -> np.ndarray:
+    """The same V(rho_j, z_q) as ``potential_on_grid`` for the Gaussian wells,
+    from the factorisation exp(-|r - R - L|^2 / w^2) =
+    exp(-|rho - R_par - L|^2 / w^2) exp(-(z - R_z)^2 / w^2): in-plane maps of every
+    (atom, term) once, combined plane by plane with their z factors (a matrix
+    product).  Shape (Nq, N1, N2)."""
+    a1 = np.asarray(desc["a1"], float)
+    a2 = np.asarray(desc["a2"], float)
+    rho = grid_points(desc)
+    x, y = rho[..., 0], rho[..., 1]
+    zq = np.asarray(zq, float)
+    maps, zfac = [], []
+    for at in desc["atoms"]:
+        sp = desc["species"][at["species"]]
+        X, Y, Z = at["pos"]
+        for A, w in sp["gauss"]:
+            nimg = image_range(desc, w)
+            plane = np.zeros(x.shape)
+            for n1 in range(-nimg, nimg + 1):
+                for n2 in range(-nimg, nimg + 1):
+                    Lx = n1 * a1[0] + n2 * a2[0]
+                    Ly = n1 * a1[1] + n2 * a2[1]
+                    plane += np.exp(-((x - X - Lx) ** 2 + (y - Y - Ly) ** 2) / (w * w))
+            maps.append(A * plane.ravel())
+            zfac.append(np.exp(-((zq - Z) ** 2) / (w * w)))
+    if not maps:
+        return np.zeros((len(zq),) + x.shape)
+    out = np.array(zfac).T @ np.array(maps)
+    return out.reshape((len(zq),) + x.shape)
+
+
 def dft_matrix(N: int) -> np.ndarray:
     j = np.arange(N)
     return np.exp(-2j * math.pi * np.outer(j, j) / N)
