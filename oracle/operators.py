@@ -138,7 +138,7 @@ def vtilde_grid(desc, vgrid: np.ndarray) -> np.ndarray:
     N1, N2 = desc["grid"]
     F1 = dft_matrix(N1)
     F2 = dft_matrix(N2)
-    return np.einsum("ab,qbc,dc->qad", F1, vgrid.astype(np.complex128), F2) / (N1 * N2)
+    return np.einsum("ab,qbc,dc->qad", F1, vgrid.astype(np.complex128), F2, optimize=True) / (N1 * N2)
 
 
 def vloc_pairs_grid(desc, ik: int, zq, vfunc=None) -> np.ndarray:

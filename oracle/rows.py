@@ -9,7 +9,9 @@ operator of ``operators.Problem`` (Sec. II.B.1), evaluated directly:
   (N x)(G,i) = sum_p E_p F_p(G) Z_p(i) sum_{G',j} conj(F_p(G') Z_p(j)) x(G',j)
 
 with Vt the grid-consistent transform of the sampled potential.  The potential
-is sampled only on the z-planes that the requested rows touch.
+is sampled only on the z-planes that the requested rows touch (Gaussian wells
+through the in-plane x z factorisation of operators.py, pinned against the
+direct sum).
 """
 from __future__ import annotations
 
@@ -17,7 +19,8 @@ import numpy as np
 
 from .bspline import ZBasis
 from .lattice import gset
-from .operators import potential_on_grid, projector_factors, vtilde_grid
+from .operators import (gaussian_potential_on_grid_separable, potential_on_grid, projector_factors,
+                        vtilde_grid)
 
 
 class RowOracle:
@@ -40,7 +43,10 @@ class RowOracle:
         if need:
             has_v = self.vfunc is not None or bool(self.desc["atoms"])
             if has_v:
-                vg = potential_on_grid(self.desc, self.zb.zq[need], self.vfunc)
+                if self.vfunc is None:
+                    vg = gaussian_potential_on_grid_separable(self.desc, self.zb.zq[need])
+                else:
+                    vg = potential_on_grid(self.desc, self.zb.zq[need], self.vfunc)
                 vt = vtilde_grid(self.desc, vg)
             else:
                 N1, N2 = self.desc["grid"]
@@ -64,6 +70,7 @@ class RowOracle:
         # projections <beta_p | x_b> for all p, b
         if len(self.E):
             proj = np.einsum("pg,pi,big->pb", self.F.conj(), self.Z.conj(), x)
+        psis = {}  # psi(G', z_q) of every band, per touched plane
         for r, (i, g) in enumerate(rows):
             Sx[:, r] = x[:, :, g] @ self.Sz[i, :]
             Hx[:, r] = 0.5 * (x[:, :, g] @ (self.Dz[i, :] + self.kg2[g] * self.Sz[i, :]))
@@ -72,8 +79,9 @@ class RowOracle:
             d1 = (self.m[g, 0] - self.m[:, 0]) % N1
             d2 = (self.m[g, 1] - self.m[:, 1]) % N2
             for q, vt in zip(qs, vts):
-                psi = np.einsum("j,bjG->bG", B[q, :], x)  # psi(G', z_q)
-                Hx[:, r] += wq[q] * B[q, i] * (psi @ vt[d1, d2])
+                if q not in psis:
+                    psis[q] = np.einsum("j,bjG->bG", B[q, :], x)  # psi(G', z_q)
+                Hx[:, r] += wq[q] * B[q, i] * (psis[q] @ vt[d1, d2])
             if len(self.E):
                 coef = self.E * self.F[:, g] * self.Z[:, i]
                 Hx[:, r] += coef @ proj

@@ -124,6 +124,33 @@ def test_hpsi_full_size_sampled_rows(cfg, ik, prec):
 _SURFACE_ROWS = {}
 
 
+def _surface_picks(d, ik, dm, perm):
+    """Rows (i, g_lib) of the surface slab that reach every edge of the operator:
+    the first, middle and last spline rows; the first and last row of every
+    projector z-window (the oracle keeps projectors dense, the library drops rows
+    outside the windows); G vectors on the sphere boundary (largest |k+G|^2) and
+    G = 0.  At least 32 rows."""
+    from oracle.bspline import ZBasis
+    _, Z, _ = operators.projector_factors(d, ik, ZBasis(d["breakpoints"], d["order"], d["nq"]))
+    zmax = np.max(np.abs(Z))
+    edges = set()
+    for zrow in Z:
+        live = np.nonzero(np.abs(zrow) >= 1e-14 * zmax)[0]
+        edges.update((int(live[0]), int(live[-1])))
+    edges = sorted(edges)
+    m, kg = lattice.gset(d, ik)
+    kg2 = np.sum(kg * kg, axis=1)
+    inv = np.argsort(perm)                      # oracle G index -> library G index
+    outer = [int(inv[g]) for g in np.argsort(-kg2)[:12]]
+    g0 = int(inv[int(np.argmin(kg2))])
+    picks = [(0, 0), (dm["nb"] // 2, dm["ng"] // 3), (dm["nb"] - 1, dm["ng"] - 1), (dm["nb"] // 2, g0)]
+    for n, i in enumerate(edges):
+        picks.append((i, outer[n % len(outer)] if n % 2 == 0 else (37 * n + 11) % dm["ng"]))
+    while len(picks) < 32:
+        picks.append(((5 * len(picks)) % dm["nb"], outer[len(picks) % len(outer)]))
+    return picks
+
+
 def _surface_oracle_rows(ik, nbands):
     """Oracle rows of H x and S x for the 128x64 surface slab (computed once per
     module: sampling the 64-atom potential on the touched planes dominates)."""
@@ -138,8 +165,7 @@ def _surface_oracle_rows(ik, nbands):
         x = random_lib_block(17, nbands, dm["nb"], dm["ng"], dm["ld"])
         xo = np.zeros((nbands, dm["nb"], dm["ng"]), dtype=np.complex128)
         xo[:, :, perm] = x[:, :, :dm["ng"]]
-        # first, middle and last spline rows (edge and interior knot intervals)
-        picks = [(0, 0), (dm["nb"] // 2, dm["ng"] // 3), (dm["nb"] - 1, dm["ng"] - 1)]
+        picks = _surface_picks(d, ik, dm, perm)
         Hr, Sr = rows.RowOracle(d, ik).apply_rows(xo, [(i, perm[g]) for i, g in picks])
         _SURFACE_ROWS[key] = (x, picks, Hr, Sr)
     return _SURFACE_ROWS[key]
