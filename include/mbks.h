@@ -157,6 +157,21 @@ mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nban
 mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
+/* Reserve the H work buffers of k-point ik (local partial rows, projections, matrix-core
+ * partial projections) for calls of up to max_bands vectors with row stride ld (0: the
+ * recommended ld), in any precision.  With lock != 0 they are also locked: later
+ * hpsi_apply / lanczos_lowest calls on this k-point that would need larger buffers
+ * return MB_ERR_INVALID_ARG instead of reallocating them, and solves do not release
+ * them, so their device addresses stay fixed until mb_problem_reserve is called again
+ * (lock = 0 unlocks) or the problem is destroyed.  A HIP graph that captured
+ * hpsi_apply / spsi_apply / s_solve on this k-point holds these addresses: reserve and
+ * lock before capturing, and keep the lock while the graph may be replayed.  Without a
+ * lock a later call on the k-point with more bands, or a solve of hundreds of bands,
+ * may free and reallocate the buffers, and a replay would write to freed memory.
+ * Synchronises the device when it grows a buffer; no call on this k-point may be in
+ * flight.  max_bands = 0 only sets the lock. */
+mb_status mb_problem_reserve(mb_problem* p, int ik, int64_t max_bands, int64_t ld, int lock);
+
 /* Autotuner of the operator's kernel choices for one k-point, block size and
  * precision: times the local-potential kernels that support the grid (the
  * line-per-thread kernel at LDS budgets of 22-160 KB per workgroup, i.e. 1 to all

@@ -153,6 +153,30 @@ mb_status ensure_ws(Workspace& w, size_t bytes) {
     return MB_OK;
 }
 
+mb_status ensure_hws(KPoint& kp, Workspace& w, size_t bytes) {
+    if (kp.locked && w.bytes < bytes)
+        return set_error(MB_ERR_INVALID_ARG,
+                         "the k-point's H work buffers are locked by mb_problem_reserve and are smaller than "
+                         "this call needs (reserve more bands)");
+    return ensure_ws(w, bytes);
+}
+
+size_t hwork_part_bytes(const Problem* p, int nbands, int ld, int prec) {
+    const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
+    return (size_t)nbands * p->nint * 4 * ld * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+}
+
+size_t hwork_proj_bytes(const Problem* p, int nbands, int prec) {
+    const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
+    return (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+}
+
+size_t hwork_nlpart_bytes(const Problem* p, int nbands, int prec) {
+    if (p->np == 0) return 0;
+    const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
+    return nl_mfma_part_bytes(p, nbands, prec >= 3 ? 2 : lp == 0 ? 0 : 1);
+}
+
 mb_status upload(Problem* p) {
     MB_TRY(upload_vec(&p->d_bval, p->bval));
     MB_TRY(upload_f32(&p->d_bvalf, p->bval));
@@ -198,17 +222,26 @@ mb_status upload(Problem* p) {
 }
 
 // y = H c (sy = S c if non-null).  prec: 0 FP64, 1 FP32 (c64), 2 c128 vectors with FP32 local/nonlocal.
-mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec, hipStream_t s) {
+mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec, hipStream_t s,
+                  const HWork* ext) {
     if (nbands == 0) return MB_OK;
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;  // local / combine precision
-    size_t csz = lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>);
-    size_t part_bytes = (size_t)nbands * p->nint * 4 * ld * csz;
     KPoint& kp = p->kp[ik];
-    MB_TRY(ensure_ws(kp.ws_part, part_bytes));
+    void* part = ext ? ext->part : nullptr;
+    if (!ext) {
+        MB_TRY(ensure_hws(kp, kp.ws_part, hwork_part_bytes(p, nbands, ld, prec)));
+        part = kp.ws_part.ptr;
+    }
     void* proj = nullptr;
     if (p->np > 0) {
-        MB_TRY(ensure_ws(kp.ws_proj, (size_t)nbands * p->np * csz));
-        proj = kp.ws_proj.ptr;
+        if (ext && (!ext->proj || !ext->nlpart))
+            return set_error(MB_ERR_INVALID_ARG, "apply_h: caller work buffers lack the projection buffers");
+        if (ext) {
+            proj = ext->proj;
+        } else {
+            MB_TRY(ensure_hws(kp, kp.ws_proj, hwork_proj_bytes(p, nbands, prec)));
+            proj = kp.ws_proj.ptr;
+        }
         // FP32 and FP64 projections go to the matrix cores once there are enough
         // projectors to fill their 16-wide tiles (measured: with 8 or 32 projectors the
         // vector kernel is faster, with 256 the matrix cores are 2.7x faster in FP32);
@@ -224,16 +257,18 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         if (vector_path)
             MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, lp, s));
         else
-            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s));
+            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s,
+                                          ext ? ext->nlpart : nullptr));
     }
-    MB_TRY(launch_local(p, ik, c, kp.ws_part.ptr, nbands, ld, lp, s));
-    MB_TRY(launch_combine(p, ik, c, kp.ws_part.ptr, proj, y, sy, nbands, ld, lp, s));
+    MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
+    MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
     return MB_OK;
 }
 
 }  // namespace mb
 
 using mb::set_error;
+
 
 extern "C" {
 
@@ -390,6 +425,29 @@ mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply: c and y overlap");
     return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld,
                        prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream);
+}
+
+
+mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t ld, int lock) {
+    mb::Problem* p = mb::problem_of(h);
+    if (!p) return set_error(MB_ERR_INVALID_ARG, "mb_problem_reserve: problem is NULL");
+    if (p->device < 0) return set_error(MB_ERR_NO_DEVICE, "mb_problem_reserve: host-only problem");
+    if (ik < 0 || ik >= (int)p->kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_problem_reserve: ik out of range");
+    mb::KPoint& kp = p->kp[ik];
+    if (ld == 0) ld = kp.ld;
+    if (max_bands < 0 || max_bands > (1 << 20) || ld < kp.ng || ld > (1 << 24))
+        return set_error(MB_ERR_INVALID_ARG, "mb_problem_reserve: max_bands or ld out of range");
+    kp.locked = false;
+    if (max_bands > 0) {
+        const int nb = (int)max_bands;
+        // FP64 sizes cover every precision
+        mb_status st = mb::ensure_ws(kp.ws_part, mb::hwork_part_bytes(p, nb, (int)ld, 0));
+        if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_proj, mb::hwork_proj_bytes(p, nb, 0));
+        if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_nlpart, mb::hwork_nlpart_bytes(p, nb, 0));
+        if (st != MB_OK) return st;
+    }
+    kp.locked = lock != 0;
+    return MB_OK;
 }
 
 mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, void* stream, mb_tune_info* info) {

@@ -239,22 +239,30 @@ mb_status upload_group_windows(Problem* p) {
     return MB_OK;
 }
 
+size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode) {
+    const int npad = (p->np + 15) / 16 * 16;
+    const int nbpad = (nbands + 15) / 16 * 16;
+    return (size_t)p->nb * npad * nbpad * (mode == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+}
+
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
-                                 bool vin64, hipStream_t s) {
+                                 bool vin64, hipStream_t s, void* nlpart) {
     if (p->np == 0) return MB_OK;
     const KPoint& kp = p->kp[ik];
     const int ngrp = (p->np + 15) / 16;
     const int npad = ngrp * 16;
     const int nbpad = (nbands + 15) / 16 * 16;
     if (!p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
-    size_t pbytes = (size_t)p->nb * npad * nbpad * (mode == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
     KPoint& kw = p->kp[ik];
-    mb_status st = ensure_ws(kw.ws_nlpart, pbytes);
-    if (st != MB_OK) return st;
+    if (!nlpart) {
+        mb_status st = ensure_hws(kw, kw.ws_nlpart, nl_mfma_part_bytes(p, nbands, mode));
+        if (st != MB_OK) return st;
+        nlpart = kw.ws_nlpart.ptr;
+    }
     StageScope ts_(MB_STAGE_NL_PROJECT, s, nbands);
     dim3 grid(p->nb, nbpad / 16, ngrp);
     if (mode == 0) {
-        cx<double>* part64 = (cx<double>*)kw.ws_nlpart.ptr;
+        cx<double>* part64 = (cx<double>*)nlpart;
         hipLaunchKernelGGL(k_nlproj_f64, grid, dim3(64), 0, s, (const cx<double>*)c, (const cx<double>*)kp.d_F64,
                            p->d_Z, p->d_gwin, part64, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
         MB_HIP_TRY(hipGetLastError());
@@ -264,7 +272,7 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
         MB_HIP_TRY(hipGetLastError());
         return MB_OK;
     }
-    cx<float>* part = (cx<float>*)kw.ws_nlpart.ptr;
+    cx<float>* part = (cx<float>*)nlpart;
     const cx<float>* F = (const cx<float>*)kp.d_F32;
     if (mode == 1) {
         if (vin64)

@@ -460,6 +460,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
     if (kw.ws_lz.bytes > LZ_KEEP_BYTES) {
         // with it go the H-application work buffers sized for this solve
         for (Workspace* w : {&kw.ws_lz, &kw.ws_part, &kw.ws_nlpart}) {
+            if (kw.locked && w != &kw.ws_lz) continue;  // reserved H work buffers stay
             if (w->ptr) MB_HIP_TRY(hipFree(w->ptr));
             w->ptr = nullptr;
             w->bytes = 0;

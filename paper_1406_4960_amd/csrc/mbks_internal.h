@@ -47,6 +47,9 @@ struct KPoint {
     // preconditioner factors (T + sigma S) per G, [i][d][ld] doubles, built on demand
     double* d_pfac = nullptr;
     double pfac_sigma = -1.0;
+    // H work buffers (ws_part, ws_proj, ws_nlpart) sized once by mb_problem_reserve and
+    // locked: calls that need more fail instead of reallocating, and solves do not free them
+    bool locked = false;
     Workspace ws_part;    // local-potential partial projections
     Workspace ws_proj;    // projections <beta|c>
     Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
@@ -143,6 +146,20 @@ mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void
 Problem* problem_of(mb_problem* h);
 mb_status upload(Problem* p);
 mb_status ensure_ws(Workspace& w, size_t bytes);
+// ensure_ws for the H work buffers of a k-point; a locked k-point never reallocates them
+mb_status ensure_hws(KPoint& kp, Workspace& w, size_t bytes);
+
+// Caller-provided H work buffers (no allocation in apply_h): local partial rows, projections
+// and matrix-core partial projections, each large enough for the call's bands.
+struct HWork {
+    void* part = nullptr;
+    void* proj = nullptr;
+    void* nlpart = nullptr;
+};
+// bytes of each H work buffer for nbands vectors; prec as for apply_h
+size_t hwork_part_bytes(const Problem* p, int nbands, int ld, int prec);
+size_t hwork_proj_bytes(const Problem* p, int nbands, int prec);
+size_t hwork_nlpart_bytes(const Problem* p, int nbands, int prec);
 mb_status upload_group_windows(Problem* p);
 
 // kernel launchers (k_*.hip); prec 0 = fp64, 1 = fp32
@@ -158,7 +175,9 @@ mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int n
                             int prec, hipStream_t s);
 // matrix-core projections: mode 1 FP32 MFMA, mode 2 BF16x3 MFMA; vin64 = complex128 vectors
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
-                                 bool vin64, hipStream_t s);
+                                 bool vin64, hipStream_t s, void* nlpart = nullptr);
+// bytes of the matrix-core partial projections; mode 0 FP64, else FP32 partials
+size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode);
 // y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
                          void* y, void* sy, int nbands, int ld, int prec, hipStream_t s);
@@ -220,7 +239,8 @@ bool timer_enabled();
 // composite operator (capi.hip): y = H c (and sy = S c if non-null).
 // prec: 0 FP64; 1 FP32 (complex64 vectors); 2 complex128 vectors with FP32 local and
 // nonlocal arithmetic; 3 = 1 and 4 = 2 with BF16x3 projector contractions.
+// ext: caller-provided work buffers (nothing allocated), else the k-point's own.
 mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec,
-                  hipStream_t s);
+                  hipStream_t s, const HWork* ext = nullptr);
 
 }  // namespace mb

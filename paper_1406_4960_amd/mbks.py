@@ -25,7 +25,7 @@ MB_MAX_GAUSS = 4
 # every symbol the C header declares
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
-           "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
+           "mb_problem_reserve", "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
            "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.lanczos_lowest.argtypes = [vp, c_int, c_int, c_int, POINTER(LanczosOpts), vp, vp, vp,
                                    POINTER(LanczosInfo), vp]
     lib.mb_autotune.argtypes = [vp, c_int, c_int64, c_int, vp, POINTER(TuneInfo)]
+    lib.mb_problem_reserve.argtypes = [vp, c_int, c_int64, c_int64, c_int]
     lib.mb_batch_create.argtypes = [vp, vp, c_int, POINTER(vp)]
     lib.mb_batch_destroy.argtypes = [vp]
     lib.hpsi_apply_batched.argtypes = [vp, vp, vp, vp, vp, c_int, vp]
@@ -309,6 +310,10 @@ class Problem:
     def s_solve(self, ik, r, x, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, r, x, prec)
         _check(load().s_solve(self.h, ik, _ptr(r), _ptr(x), nbands, ld, _prec(prec), _stream(stream)))
+
+    def reserve(self, ik, max_bands, ld=0, lock=True):
+        """Size the k-point's H work buffers for max_bands vectors and (lock) keep them fixed."""
+        _check(load().mb_problem_reserve(self.h, ik, int(max_bands), int(ld), int(bool(lock))))
 
     def autotune(self, ik, nbands, prec="fp64", stream=None):
         """Measure the kernel choices for (ik, nbands, prec) and keep the fastest."""

@@ -53,3 +53,46 @@ def test_hpsi_graph_replays_match_eager(prec):
             assert float(torch.max(torch.abs(ye))) > 0
     del g
     p.close()
+
+
+def test_reserved_locked_buffers_keep_a_captured_graph_valid():
+    # a graph captured after mb_problem_reserve(lock) stays valid across a solve on the
+    # same k-point (which would otherwise size the work buffers for its own blocks),
+    # and a call that needs more than the reserved bands is refused instead of
+    # reallocating them
+    print("[case] graph with reserved, locked work buffers", flush=True)
+    d = workloads.tiny()
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    p.reserve(0, 24, lock=True)
+    x = torch.from_numpy(random_lib_block(75, 4, dm["nb"], dm["ng"], dm["ld"])).to(DEV)
+    y = torch.empty_like(x)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        p.hpsi(0, x, y)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        p.hpsi(0, x, y)
+    o = p.default_opts()
+    o.extra = 4
+    eig, xv, info, st = p.lanczos_lowest(0, 8, "fp64", opts=o)  # H on up to 8 + 4 + 2 vectors
+    assert st == 0
+    big = torch.zeros((40, dm["nb"], dm["ld"]), dtype=torch.complex128, device=DEV)  # > 24 + 1/8 headroom
+    with pytest.raises(mbks.MbError, match="locked"):
+        p.hpsi(0, big, torch.empty_like(big))
+    for rep in range(3):
+        x.mul_(complex(0.5, 0.1 * (rep + 1)))
+        g.replay()
+        torch.cuda.synchronize()
+        ye = torch.empty_like(x)
+        p.hpsi(0, x, ye)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ye), rep
+    del g
+    p.reserve(0, 0, lock=False)  # unlocked: larger calls grow the buffers again
+    p.hpsi(0, big, torch.empty_like(big))
+    torch.cuda.synchronize()
+    p.close()

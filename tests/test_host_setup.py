@@ -88,6 +88,7 @@ def test_gpu_calls_on_host_only_handle_fail():
     st = lib.s_solve(p.h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), 1, p.dims(0)["ld"], 0, None)
     assert st == -7
     assert b"host-only" in lib.mb_last_error()
+    assert lib.mb_problem_reserve(p.h, 0, 8, 0, 1) == -7
     p.close()
 
 
