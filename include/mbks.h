@@ -153,6 +153,21 @@ mb_status mb_problem_set_potential(mb_problem* p, const double* v_host);
 mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
+/* hpsi_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same operator
+ * and kernels as hpsi_apply, with every work buffer (local partial rows, projections,
+ * matrix-core partial projections) in a fixed 256 MiB array that the library holds on
+ * each GPU it runs on until the process ends.  No hipMalloc, hipFree or allocating
+ * library call is made.  Bands are processed in groups whose work space fits the
+ * array (a group holds e.g. 5 bands of a 128x64-grid, 192-spline slab in FP64, or all
+ * 32 of a 36x36-grid, 80-spline slab); MB_ERR_INVALID_ARG if a single band needs
+ * more than 256 MiB.  The array keeps the last call's contents and no kernel reads
+ * it before writing it.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads, any problem) race and give
+ * wrong results; serialise them.  Arguments and layout as for hpsi_apply. */
+mb_status hpsi_apply_noalloc(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                             mb_precision prec, void* stream);
+
 /* y = S c (banded overlap, Sec. II.B.1).  c and y must not overlap. */
 mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cplx.h"
@@ -95,8 +96,11 @@ void timer_clear() {
 
 bool timer_enabled() { return g_timer.on; }
 
+// set while a no-allocation call runs on this thread: the stage timer creates no events
+thread_local bool t_no_events = false;
+
 StageScope::StageScope(int st, hipStream_t str, int64_t u) : stage(st), s(str), units(u) {
-    if (!g_timer.on) return;
+    if (!g_timer.on || t_no_events) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     (void)hipEventRecord(e, s);
@@ -269,6 +273,44 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
 
 using mb::set_error;
 
+namespace mb {
+namespace {
+// Work buffers of hpsi_apply_noalloc: one array per GPU, held for the life of the process.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with that device
+// current (each GPU holds its own copy of the array).
+mb_status scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return set_error(MB_ERR_INVALID_ARG, "scratch: device index");
+    if (!g_scratch_ptr[device]) {
+        int prev = -1;
+        MB_HIP_TRY(hipGetDevice(&prev));
+        if (prev != device) MB_HIP_TRY(hipSetDevice(device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !ptr)
+            return set_error(MB_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return MB_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// scratch bytes of one apply_h call on n bands (part, proj, matrix-core partials)
+size_t noalloc_bytes(const Problem* p, int n, int ld, int prec) {
+    return align256(hwork_part_bytes(p, n, ld, prec)) + align256(hwork_proj_bytes(p, n, prec)) +
+           align256(hwork_nlpart_bytes(p, n, prec));
+}
+}  // namespace
+}  // namespace mb
 
 extern "C" {
 
@@ -427,6 +469,53 @@ mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
                        prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream);
 }
 
+
+mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                             mb_precision prec, void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, c, y, nbands, ld, "hpsi_apply_noalloc");
+    if (st != MB_OK) return st;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_noalloc: unknown precision");
+    mb::Problem* p = &h->p;
+    const size_t vsz = prec == MB_FP64 ? 16 : 8;
+    const size_t bytes = (size_t)nbands * p->nb * ld * vsz;
+    if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_noalloc: c and y overlap");
+    if (nbands == 0) return MB_OK;
+    const int iprec = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3;
+    const size_t one = mb::noalloc_bytes(p, 1, (int)ld, iprec);
+    if (one > mb::NOALLOC_SCRATCH_BYTES)
+        return set_error(MB_ERR_INVALID_ARG,
+                         "hpsi_apply_noalloc: one band needs " + std::to_string(one >> 20) +
+                             " MiB of work space, more than the " + std::to_string(mb::NOALLOC_SCRATCH_BYTES >> 20) +
+                             " MiB this entry point holds per GPU (use hpsi_apply)");
+    void* base = nullptr;
+    st = mb::scratch_address(p->device, &base);
+    if (st != MB_OK) return st;
+    // bands per group: the largest count whose work space fits the scratch array
+    int lo = 1, hi = (int)nbands;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (mb::noalloc_bytes(p, mid, (int)ld, iprec) <= mb::NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+    }
+    const int group = lo;
+    mb::t_no_events = true;
+    for (int b0 = 0; b0 < (int)nbands && st == MB_OK; b0 += group) {
+        const int n = std::min(group, (int)nbands - b0);
+        mb::HWork w;
+        char* q = (char*)base;
+        w.part = q;
+        q += mb::align256(mb::hwork_part_bytes(p, n, (int)ld, iprec));
+        w.proj = q;
+        q += mb::align256(mb::hwork_proj_bytes(p, n, iprec));
+        w.nlpart = q;
+        const size_t off = (size_t)b0 * p->nb * ld * vsz;
+        st = mb::apply_h(p, ik, (const char*)c + off, (char*)y + off, nullptr, n, (int)ld, iprec,
+                         (hipStream_t)stream, &w);
+    }
+    mb::t_no_events = false;
+    return st;
+}
 
 mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t ld, int lock) {
     mb::Problem* p = mb::problem_of(h);

@@ -25,7 +25,7 @@ MB_MAX_GAUSS = 4
 # every symbol the C header declares
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
-           "mb_problem_reserve", "hpsi_apply", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
+           "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
            "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
@@ -99,7 +99,7 @@ def load(path: str = LIB_PATH):
     lib.mb_problem_zbands.argtypes = [vp, vp, vp]
     lib.mb_problem_projectors.argtypes = [vp, c_int, vp, vp, vp]
     lib.mb_problem_set_potential.argtypes = [vp, vp]
-    for name in ("hpsi_apply", "spsi_apply", "s_solve"):
+    for name in ("hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve"):
         getattr(lib, name).argtypes = [vp, c_int, vp, vp, c_int64, c_int64, c_int, vp]
     lib.mb_lanczos_default_opts.argtypes = [POINTER(LanczosOpts)]
     lib.mb_lanczos_default_opts.restype = None
@@ -302,6 +302,10 @@ class Problem:
     def hpsi(self, ik, c, y, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, c, y, prec)
         _check(load().hpsi_apply(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
+
+    def hpsi_noalloc(self, ik, c, y, prec="fp64", stream=None):
+        nbands, ld = self._vec_args(ik, c, y, prec)
+        _check(load().hpsi_apply_noalloc(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
 
     def spsi(self, ik, c, y, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, c, y, prec)
