@@ -59,11 +59,11 @@ void free_all(Problem* p) {
     if (p->device < 0) return;
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
-                    p->d_V, p->d_Vf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin};
+                    p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& kp : p->kp) {
-        void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_F64, kp.d_F32, kp.d_pfac,
+        void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_gtab, kp.d_F64, kp.d_F32, kp.d_pfac,
                       kp.ws_part.ptr, kp.ws_proj.ptr, kp.ws_nlpart.ptr, kp.ws_lz.ptr, kp.ws_small.ptr};
         for (void* q : kq)
             if (q) (void)hipFree(q);
@@ -165,9 +165,10 @@ mb_status ensure_hws(KPoint& kp, Workspace& w, size_t bytes) {
     return ensure_ws(w, bytes);
 }
 
-size_t hwork_part_bytes(const Problem* p, int nbands, int ld, int prec) {
+size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec) {
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
-    return (size_t)nbands * p->nint * 4 * ld * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+    const size_t rows = local_uses_planes(p, ik, lp) ? (size_t)p->nzq : (size_t)p->nint * 4;
+    return (size_t)nbands * rows * ld * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
 }
 
 size_t hwork_proj_bytes(const Problem* p, int nbands, int prec) {
@@ -210,6 +211,17 @@ mb_status upload(Problem* p) {
         MB_TRY(upload_f32(&kp.d_kg2f, kp.kg2));
         MB_TRY(upload_vec(&kp.d_gmap, kp.gmap));
         MB_TRY(upload_vec(&kp.d_rows, kp.rows));
+        if (plane_kernel_grid(p)) {
+            // G index of every (sphere row, column) of the grid, -1 off the sphere
+            std::vector<int32_t> rowpos(p->N1, -1);
+            for (size_t r = 0; r < kp.rows.size(); ++r) rowpos[kp.rows[r]] = (int32_t)r;
+            kp.gtab.assign(kp.rows.size() * (size_t)p->N2, -1);
+            for (int g = 0; g < kp.ng; ++g) {
+                const int j1 = kp.gmap[g] / p->N2, j2 = kp.gmap[g] % p->N2;
+                kp.gtab[(size_t)rowpos[j1] * p->N2 + j2] = g;
+            }
+            MB_TRY(upload_vec(&kp.d_gtab, kp.gtab));
+        }
         if (p->np > 0) {
             std::vector<cx<double>> F(kp.F.size());
             std::vector<cx<float>> Ff(kp.F.size());
@@ -222,6 +234,7 @@ mb_status upload(Problem* p) {
         }
     }
     MB_TRY(launch_vgrid(p, 0));
+    MB_TRY(refresh_vt(p, 0));
     return MB_OK;
 }
 
@@ -233,7 +246,7 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
     KPoint& kp = p->kp[ik];
     void* part = ext ? ext->part : nullptr;
     if (!ext) {
-        MB_TRY(ensure_hws(kp, kp.ws_part, hwork_part_bytes(p, nbands, ld, prec)));
+        MB_TRY(ensure_hws(kp, kp.ws_part, hwork_part_bytes(p, ik, nbands, ld, prec)));
         part = kp.ws_part.ptr;
     }
     void* proj = nullptr;
@@ -264,8 +277,12 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
             MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s,
                                           ext ? ext->nlpart : nullptr));
     }
-    MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
-    MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
+    const bool planes = local_uses_planes(p, ik, lp);
+    if (planes)
+        MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s));
+    else
+        MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
+    MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, planes));
     return MB_OK;
 }
 
@@ -305,8 +322,8 @@ mb_status scratch_address(int device, void** out) {
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // scratch bytes of one apply_h call on n bands (part, proj, matrix-core partials)
-size_t noalloc_bytes(const Problem* p, int n, int ld, int prec) {
-    return align256(hwork_part_bytes(p, n, ld, prec)) + align256(hwork_proj_bytes(p, n, prec)) +
+size_t noalloc_bytes(const Problem* p, int ik, int n, int ld, int prec) {
+    return align256(hwork_part_bytes(p, ik, n, ld, prec)) + align256(hwork_proj_bytes(p, n, prec)) +
            align256(hwork_nlpart_bytes(p, n, prec));
 }
 }  // namespace
@@ -453,7 +470,7 @@ mb_status mb_problem_set_potential(mb_problem* h, const double* v) {
     std::vector<float> vf(v, v + n);
     MB_HIP_TRY(hipMemcpy(p.d_V, v, n * sizeof(double), hipMemcpyHostToDevice));
     MB_HIP_TRY(hipMemcpy(p.d_Vf, vf.data(), n * sizeof(float), hipMemcpyHostToDevice));
-    return MB_OK;
+    return mb::refresh_vt(&p, 0);
 }
 
 mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,
@@ -483,7 +500,7 @@ mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int6
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_noalloc: c and y overlap");
     if (nbands == 0) return MB_OK;
     const int iprec = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3;
-    const size_t one = mb::noalloc_bytes(p, 1, (int)ld, iprec);
+    const size_t one = mb::noalloc_bytes(p, ik, 1, (int)ld, iprec);
     if (one > mb::NOALLOC_SCRATCH_BYTES)
         return set_error(MB_ERR_INVALID_ARG,
                          "hpsi_apply_noalloc: one band needs " + std::to_string(one >> 20) +
@@ -496,7 +513,7 @@ mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int6
     int lo = 1, hi = (int)nbands;
     while (lo < hi) {
         const int mid = lo + (hi - lo + 1) / 2;
-        if (mb::noalloc_bytes(p, mid, (int)ld, iprec) <= mb::NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+        if (mb::noalloc_bytes(p, ik, mid, (int)ld, iprec) <= mb::NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
     }
     const int group = lo;
     mb::t_no_events = true;
@@ -505,7 +522,7 @@ mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int6
         mb::HWork w;
         char* q = (char*)base;
         w.part = q;
-        q += mb::align256(mb::hwork_part_bytes(p, n, (int)ld, iprec));
+        q += mb::align256(mb::hwork_part_bytes(p, ik, n, (int)ld, iprec));
         w.proj = q;
         q += mb::align256(mb::hwork_proj_bytes(p, n, iprec));
         w.nlpart = q;
@@ -529,8 +546,9 @@ mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t l
     kp.locked = false;
     if (max_bands > 0) {
         const int nb = (int)max_bands;
-        // FP64 sizes cover every precision
-        mb_status st = mb::ensure_ws(kp.ws_part, mb::hwork_part_bytes(p, nb, (int)ld, 0));
+        // FP64 sizes cover every precision; the larger of the two local layouts
+        const size_t part = (size_t)nb * std::max<size_t>((size_t)p->nzq, (size_t)p->nint * 4) * ld * 16;
+        mb_status st = mb::ensure_ws(kp.ws_part, part);
         if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_proj, mb::hwork_proj_bytes(p, nb, 0));
         if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_nlpart, mb::hwork_nlpart_bytes(p, nb, 0));
         if (st != MB_OK) return st;

@@ -456,6 +456,15 @@ mb_status launch_local(Problem* p, int ik, const void* c, void* part, int nbands
     return local_impl<double, float>(p, ik, c, part, nbands, ld, s);
 }
 
+bool local_uses_planes(const Problem* p, int ik, int lp) {
+    if (!plane_kernel_grid(p)) return false;
+    // MBKS_LOCAL_KERNEL=generic or =split select the partial-row kernels (cross-checks)
+    const char* sel = getenv("MBKS_LOCAL_KERNEL");
+    if (sel && (std::string(sel) == "generic" || std::string(sel) == "split")) return false;
+    const KPoint::Tune& tn = p->kp[ik].tune[lp];
+    return !(tn.set && tn.kind != 3);
+}
+
 mb_status launch_vgrid(Problem* p, hipStream_t s) {
     std::vector<VTerm> terms;
     double h1 = p->area / std::hypot(p->a2[0], p->a2[1]);

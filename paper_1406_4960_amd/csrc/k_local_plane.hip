@@ -1,0 +1,376 @@
+// Local-potential part of H c, one Gauss plane at a time, for in-plane grids whose FFT
+// lines are split over a few lanes (the 128 x 64 grid of the large surface slab):
+//   evaluate psi(G, z_q) = sum_t B_{s-1+t}(z_q) c(G, s-1+t), scatter on the sphere rows,
+//   inverse 2D FFT, multiply by V(rho, z_q), forward 2D FFT, gather, and write
+//   u_q(G) = (V psi_q)(G) / (N1 N2) for every Gauss plane q (local-potential matrix
+//   elements of Sec. II.B.1, taken on the grid); the combine pass projects the planes
+//   onto the spline rows, sum_q w_q B_i(z_q) u_q(G).
+// Every line of N = Q L points is held by Q neighbouring lanes, lane l owning the
+// points l + Q m (m < L).  Inverse transform: an L-point register FFT per lane, the
+// twiddle w_N^{l k}, then a radix-2 decimation-in-frequency network across the Q lanes
+// (lane exchanges), which leaves lane l holding the outputs k + L bitrev(l).  Forward
+// transform: the mirrored decimation-in-time network across the lanes, the conjugate
+// twiddle and the L-point register FFT, which returns the points l + Q m to lane l.  A
+// plane takes two passes through LDS: rows (only the rows that hold sphere points) and
+// columns; the potential multiply sits inside the column pass.  No thread keeps
+// accumulators across planes, so no registers spill at any plane count.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "cplx.h"
+#include "fft_line.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+constexpr int KORD = 4;
+using fftl::line_fft;
+
+template <typename TI, typename T>
+struct PlaneArgs {
+    const cx<TI>* c;       // [b][i][ld]
+    cx<T>* u;              // [b][q][ld]: (V psi_q)(G) / (N1 N2)
+    const T* bval;         // [q][kappa]
+    const T* Vt;           // [q][j2][j1]: the potential with the in-plane axes swapped
+    const int32_t* gtab;   // [nrows][N2]: G index at (sphere row, column), -1 outside the sphere
+    const int32_t* rows;   // [nrows]: grid row j1 of each sphere row
+    const cx<T>* tw1;      // [N1]: exp(+2 pi i k / N1)
+    const cx<T>* tw2;      // [N2]
+    int nbands, ld, nint, nq, nb, nrows, nzq;
+    T inv_n;
+};
+
+template <int Q>
+__device__ __forceinline__ int bitrev_lane(int l) {
+    int r = 0;
+#pragma unroll
+    for (int b = 1; b < Q; b <<= 1) r = (r << 1) | ((l & b) ? 1 : 0);
+    return r;
+}
+
+// Lane exchange v <- v of lane (l xor M) with DPP moves (VALU, no LDS traffic):
+// xor 1 and 2 are quad permutations, xor 8 the half-row rotation of a 16-lane row,
+// xor 4 a half-row mirror (l -> l xor 7) followed by a quad reversal (xor 3).
+template <int M>
+__device__ __forceinline__ int lane_xor_i32(int v) {
+    if constexpr (M == 1) {
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    } else if constexpr (M == 4) {
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+        return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, true);          // quad_perm [3,2,1,0]
+    } else if constexpr (M == 8) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true);  // row_ror:8
+    } else {
+        return __shfl_xor(v, M);
+    }
+}
+
+template <int M>
+__device__ __forceinline__ float lane_xor(float v) {
+    return __int_as_float(lane_xor_i32<M>(__float_as_int(v)));
+}
+
+template <int M>
+__device__ __forceinline__ double lane_xor(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor_i32<M>((int)(b & 0xffffffffll));
+    const int hi = lane_xor_i32<M>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int M, typename T>
+__device__ __forceinline__ cx<T> lane_xor_cx(cx<T> v) {
+    return mk<T>(lane_xor<M>(v.x), lane_xor<M>(v.y));
+}
+
+// w_N^{sign e} from the table exp(+2 pi i k / N)
+template <typename T, int SIGN>
+__device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, int e) {
+    const cx<T> w = tw[e];
+    return SIGN > 0 ? w : mk<T>(w.x, -w.y);
+}
+
+// Radix-2 decimation-in-frequency network over the Q lanes of a line (lane l of the
+// line = l): natural lane order in, lane l ends with the outputs of index bitrev(l).
+template <typename T, int L, int Q, int N, int SIGN, int QS = Q>
+__device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
+    if constexpr (QS >= 2) {
+        constexpr int m = QS >> 1;
+        const bool h = (l & m) != 0;
+        const cx<T> w = tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS));
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const cx<T> u = lane_xor_cx<m>(x[k]);
+            x[k] = h ? cmul(csub(u, x[k]), w) : cadd(x[k], u);
+        }
+        dif_lanes<T, L, Q, N, SIGN, QS / 2>(x, l, tw);
+    }
+}
+
+// The mirrored decimation-in-time network: bit-reversed lanes in, natural order out.
+template <typename T, int L, int Q, int N, int SIGN, int QS = 2>
+__device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw) {
+    if constexpr (QS <= Q) {
+        constexpr int m = QS >> 1;
+        const bool h = (l & m) != 0;
+        const cx<T> w = tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS));
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const cx<T> v = h ? cmul(x[k], w) : x[k];
+            const cx<T> u = lane_xor_cx<m>(v);
+            x[k] = h ? csub(u, v) : cadd(v, u);
+        }
+        dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw);
+    }
+}
+
+// LDS row pitch and column position: columns are stored in blocks of L2 with PADB
+// elements after each block, so the Q2 lanes of a row write their blocks to different banks
+template <int N2, int Q2, int PADB>
+constexpr int plane_pitch() { return N2 + Q2 * PADB + 1; }
+
+template <int N2, int Q2, int PADB>
+__device__ __forceinline__ int colpos(int j2) {
+    return j2 + (j2 / (N2 / Q2)) * PADB;
+}
+
+template <typename T, int N1, int N2>
+constexpr size_t plane_hdr() {
+    return ((sizeof(cx<T>) * (N1 + N2) + sizeof(uint32_t) * ((N1 + 31) / 32) + 255) / 256) * 256;
+}
+
+template <typename T, int N1, int N2, int Q2, int PADB>
+constexpr size_t plane_lds() {
+    return plane_hdr<T, N1, N2>() + sizeof(cx<T>) * (size_t)N1 * plane_pitch<N2, Q2, PADB>();
+}
+
+// One workgroup per (band, knot interval): the interval's Gauss planes one after another.
+template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+__global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
+    constexpr int L1 = N1 / Q1, L2 = N2 / Q2;
+    constexpr int P = plane_pitch<N2, Q2, PADB>();
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* tw1 = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* tw2 = tw1 + N1;
+    uint32_t* rmask = reinterpret_cast<uint32_t*>(tw2 + N2);
+    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + plane_hdr<T, N1, N2>());
+
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int b = (int)(L % (unsigned)a.nbands);
+    const int s = (int)(L / (unsigned)a.nbands);
+    if (s >= a.nint) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
+    for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
+    for (int e = tid; e < (N1 + 31) / 32; e += NT) rmask[e] = 0u;
+    __syncthreads();
+    for (int e = tid; e < a.nrows; e += NT) {
+        const int j1 = a.rows[e];
+        atomicOr(&rmask[j1 >> 5], 1u << (j1 & 31));
+    }
+    __syncthreads();
+
+    const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
+    cx<T>* ub = a.u + (size_t)b * a.nzq * a.ld;
+    const int nrt = a.nrows * Q2;
+
+    for (int jq = 0; jq < a.nq; ++jq) {
+        const int q = s * a.nq + jq;
+        T bv[KORD];
+#pragma unroll
+        for (int t = 0; t < KORD; ++t) bv[t] = a.bval[(size_t)q * KORD + t];
+
+        // rows: evaluate on the sphere row, inverse transform along j2
+        for (int task = tid; task < nrt; task += NT) {
+            const int rc = task / Q2, l = task % Q2;
+            const int j1 = a.rows[rc];
+            const int32_t* gr = a.gtab + (size_t)rc * N2;
+            cx<T> x[L2];
+            int gi[L2];
+#pragma unroll
+            for (int m = 0; m < L2; ++m) {
+                gi[m] = gr[l + Q2 * m];
+                x[m] = mk<T>(0, 0);
+            }
+            // one spline row at a time keeps L2 loads in flight, not kappa L2
+#pragma unroll 1
+            for (int t = 0; t < KORD; ++t) {
+                const int row = s - 1 + t;
+                if (row < 0 || row >= a.nb) continue;
+                const cx<TI>* cr = cb + (size_t)row * a.ld;
+#pragma unroll
+                for (int m = 0; m < L2; ++m) {
+                    // off the sphere: load G = 0 and weigh it by zero (no branch)
+                    const cx<TI> v = cr[gi[m] >= 0 ? gi[m] : 0];
+                    const T w = gi[m] >= 0 ? bv[t] : (T)0;
+                    x[m].x = fma(w, (T)v.x, x[m].x);
+                    x[m].y = fma(w, (T)v.y, x[m].y);
+                }
+            }
+            line_fft<T, L2, +1>(x);
+#pragma unroll
+            for (int k = 1; k < L2; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw2, l * k));
+            dif_lanes<T, L2, Q2, N2, +1>(x, l, tw2);
+            cx<T>* dst = grid + (size_t)j1 * P + colpos<N2, Q2, PADB>(L2 * bitrev_lane<Q2>(l));
+#pragma unroll
+            for (int k = 0; k < L2; ++k) dst[k] = x[k];
+        }
+        __syncthreads();
+
+        // columns: inverse transform along j1, potential multiply, forward transform
+        for (int task = tid; task < N2 * Q1; task += NT) {
+            const int j2 = task / Q1, l = task % Q1;
+            const int cp = colpos<N2, Q2, PADB>(j2);
+            uint32_t live = 0u;
+#pragma unroll
+            for (int m = 0; m < L1; ++m) {
+                const int j1 = l + Q1 * m;
+                if ((rmask[j1 >> 5] >> (j1 & 31)) & 1u) live |= 1u << m;
+            }
+            // rows without sphere points hold stale data: read them and select zero
+            cx<T> x[L1];
+#pragma unroll
+            for (int m = 0; m < L1; ++m) {
+                const cx<T> v = grid[(size_t)(l + Q1 * m) * P + cp];
+                x[m] = ((live >> m) & 1u) ? v : mk<T>(0, 0);
+            }
+            line_fft<T, L1, +1>(x);
+#pragma unroll
+            for (int k = 1; k < L1; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw1, l * k));
+            dif_lanes<T, L1, Q1, N1, +1>(x, l, tw1);
+            const T* vc = a.Vt + ((size_t)q * N2 + j2) * N1 + L1 * bitrev_lane<Q1>(l);
+#pragma unroll
+            for (int k = 0; k < L1; ++k) {
+                const T v = vc[k];
+                x[k] = mk<T>(x[k].x * v, x[k].y * v);
+            }
+            dit_lanes<T, L1, Q1, N1, -1>(x, l, tw1);
+#pragma unroll
+            for (int k = 1; k < L1; ++k) x[k] = cmul(x[k], tw_at<T, -1>(tw1, l * k));
+            line_fft<T, L1, -1>(x);
+#pragma unroll
+            for (int m = 0; m < L1; ++m) grid[(size_t)(l + Q1 * m) * P + cp] = x[m];
+        }
+        __syncthreads();
+
+        // rows: forward transform along j2, gather the sphere points.  Each task reads
+        // back exactly the LDS elements it wrote in the row pass above, so the next
+        // plane's row pass needs no barrier before it.
+        for (int task = tid; task < nrt; task += NT) {
+            const int rc = task / Q2, l = task % Q2;
+            const int j1 = a.rows[rc];
+            const int32_t* gr = a.gtab + (size_t)rc * N2;
+            const cx<T>* src = grid + (size_t)j1 * P + colpos<N2, Q2, PADB>(L2 * bitrev_lane<Q2>(l));
+            cx<T> x[L2];
+#pragma unroll
+            for (int k = 0; k < L2; ++k) x[k] = src[k];
+            dit_lanes<T, L2, Q2, N2, -1>(x, l, tw2);
+#pragma unroll
+            for (int k = 1; k < L2; ++k) x[k] = cmul(x[k], tw_at<T, -1>(tw2, l * k));
+            line_fft<T, L2, -1>(x);
+            cx<T>* uq = ub + (size_t)q * a.ld;
+#pragma unroll
+            for (int m = 0; m < L2; ++m) {
+                const int g = gr[l + Q2 * m];
+                if (g >= 0) uq[g] = mk<T>(x[m].x * a.inv_n, x[m].y * a.inv_n);
+            }
+        }
+    }
+}
+
+template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    if (!kp.d_gtab || !p->d_Vt) return set_error(MB_ERR_INVALID_ARG, "plane kernel tables missing");
+    if (kp.ng > 0 && (int)kp.rows.size() > N1) return set_error(MB_ERR_INVALID_ARG, "plane kernel: rows");
+    constexpr bool dbl = sizeof(T) == 8;
+    PlaneArgs<TI, T> a;
+    a.c = (const cx<TI>*)c;
+    a.u = (cx<T>*)u;
+    a.bval = (const T*)(dbl ? (const void*)p->d_bval : (const void*)p->d_bvalf);
+    a.Vt = (const T*)(dbl ? (const void*)p->d_Vt : (const void*)p->d_Vtf);
+    a.gtab = kp.d_gtab;
+    a.rows = kp.d_rows;
+    a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
+    a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
+    a.nbands = nbands;
+    a.ld = ld;
+    a.nint = p->nint;
+    a.nq = p->nq;
+    a.nb = p->nb;
+    a.nrows = (int)kp.rows.size();
+    a.nzq = p->nzq;
+    a.inv_n = (T)(1.0 / ((double)N1 * N2));
+    constexpr size_t lds = plane_lds<T, N1, N2, Q2, PADB>();
+    static_assert(lds <= 163840, "plane does not fit in LDS");
+    auto kern = k_local_plane<TI, T, N1, N2, Q1, Q2, NT, PADB>;
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const unsigned units = (unsigned)nbands * (unsigned)p->nint;
+    StageScope ts_(dbl ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, nbands);
+    hipLaunchKernelGGL(kern, dim3(units), dim3(NT), lds, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, int ld, hipStream_t s) {
+    // 16 lanes x 8 points per column and 8 x 8 per row, 512 threads (two tasks per
+    // thread and pass): FP64 planes fill one CU's LDS, FP32 planes two workgroups per CU
+    constexpr int NT = 512;
+    if (p->N1 == 128 && p->N2 == 64) return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
+    return MB_ERR_INVALID_ARG;
+}
+
+}  // namespace
+
+bool plane_kernel_grid(const Problem* p) { return p->order == KORD && p->N1 == 128 && p->N2 == 64; }
+
+// Returns MB_ERR_INVALID_ARG (no message) if the grid has no plane kernel.
+mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,
+                             hipStream_t s) {
+    if (!plane_kernel_grid(p)) return MB_ERR_INVALID_ARG;
+    if (nbands == 0) return MB_OK;
+    if (prec == 0) return plane_by_size<double, double>(p, ik, c, u, nbands, ld, s);
+    if (prec == 1) return plane_by_size<float, float>(p, ik, c, u, nbands, ld, s);
+    return plane_by_size<double, float>(p, ik, c, u, nbands, ld, s);
+}
+
+namespace {
+// Vt[q][j2][j1] = V[q][j1][j2]
+template <typename T>
+__global__ void k_vtranspose(const T* V, T* Vt, int N1, int N2, int nzq) {
+    const size_t n = (size_t)N1 * N2 * nzq;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const size_t q = idx / ((size_t)N1 * N2);
+    const int e = (int)(idx - q * N1 * N2);
+    const int j2 = e / N1, j1 = e - j2 * N1;
+    Vt[idx] = V[q * N1 * N2 + (size_t)j1 * N2 + j2];
+}
+}  // namespace
+
+// Transposed copies of the potential (both precisions) for the plane kernel; allocated
+// on first use, refreshed whenever the potential changes.
+mb_status refresh_vt(Problem* p, hipStream_t s) {
+    if (!plane_kernel_grid(p)) return MB_OK;
+    const size_t n = (size_t)p->nzq * p->N1 * p->N2;
+    if (!p->d_Vt && hipMalloc(&p->d_Vt, n * sizeof(double)) != hipSuccess)
+        return set_error(MB_ERR_OOM, "transposed potential grid");
+    if (!p->d_Vtf && hipMalloc(&p->d_Vtf, n * sizeof(float)) != hipSuccess)
+        return set_error(MB_ERR_OOM, "transposed potential grid");
+    const unsigned nblk = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_vtranspose<double>, dim3(nblk), dim3(256), 0, s, p->d_V, p->d_Vt, p->N1, p->N2, p->nzq);
+    MB_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_vtranspose<float>, dim3(nblk), dim3(256), 0, s, p->d_Vf, p->d_Vtf, p->N1, p->N2, p->nzq);
+    MB_HIP_TRY(hipGetLastError());
+    MB_HIP_TRY(hipStreamSynchronize(s));
+    return MB_OK;
+}
+
+}  // namespace mb

@@ -28,7 +28,8 @@ constexpr int64_t SOLVE_SMALL_WAVES = 1024;
 template <typename TI, typename T>
 struct CombineArgs {
     const cx<TI>* c;
-    const cx<T>* part;    // [b][s][t][ld] or null
+    const cx<T>* part;    // [b][s][t][ld] (kappa rows per interval), [b][q][ld] (planes) or null
+    const T* wb;          // planes: w_q B_{s-1+t}(z_q) as [q][kappa]
     const cx<T>* proj;    // [b][np] (already times E_p) or null
     const cx<T>* F;       // [np][ld]
     const T* Z;           // [np][nb]
@@ -39,6 +40,8 @@ struct CombineArgs {
     const double* dband;
     const double* kg2;
     int nbands, ld, ng, nb, nint, np;
+    int nq;      // Gauss points per interval
+    int planes;  // part holds one row per Gauss plane
 };
 
 // One block per (group of BB bands, chunk of CH rows, 256 columns); items == nullptr:
@@ -110,6 +113,39 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
             }
         }
     }
+    // local part of the chunk's rows.  Planes: y(G, i) += sum over the intervals s of
+    // B_i's support and their Gauss points q of w_q B_i(z_q) u_q(G); each plane row is
+    // loaded once for all rows of the chunk it serves
+    cx<T> loc[BB][CH];
+#pragma unroll
+    for (int bb = 0; bb < BB; ++bb)
+#pragma unroll
+        for (int r = 0; r < CH; ++r) loc[bb][r] = mk<T>(0, 0);
+    if (a.y && a.part && a.planes) {
+        const int s_lo = max(i0 - 2, 0), s_hi = min(i1, a.nint - 1);  // intervals i - 2 .. i + 1
+        for (int sv = s_lo; sv <= s_hi; ++sv) {
+            for (int jq = 0; jq < a.nq; ++jq) {
+                const int q = sv * a.nq + jq;
+                T w[CH];
+#pragma unroll
+                for (int r = 0; r < CH; ++r) {
+                    const int t = i0 + r + 1 - sv;  // spline s - 1 + t = i
+                    w[r] = (t >= 0 && t < KORD && i0 + r < i1) ? a.wb[(size_t)q * KORD + t] : (T)0;
+                }
+#pragma unroll
+                for (int bb = 0; bb < BB; ++bb) {
+                    if (bb < nbg) {
+                        const cx<T> v = a.part[((size_t)(b0 + bb) * a.nint * a.nq + q) * a.ld + g];
+#pragma unroll
+                        for (int r = 0; r < CH; ++r) {
+                            loc[bb][r].x = fma(w[r], v.x, loc[bb][r].x);
+                            loc[bb][r].y = fma(w[r], v.y, loc[bb][r].y);
+                        }
+                    }
+                }
+            }
+        }
+    }
     const double kk = a.y ? 0.5 * a.kg2[g] : 0.0;
 #pragma unroll
     for (int bb = 0; bb < BB; ++bb) {
@@ -148,7 +184,10 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
             if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
             if (a.y) {
                 double yr = tr + kk * sr, yi = ti + kk * si;
-                if (a.part) {
+                if (a.part && a.planes) {
+                    yr += (double)loc[bb][r].x;
+                    yi += (double)loc[bb][r].y;
+                } else if (a.part) {
                     T pr = 0, pi = 0;
 #pragma unroll
                     for (int t = 0; t < KORD; ++t) {
@@ -318,7 +357,7 @@ __global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx
 
 template <typename TI, typename T>
 CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const void* part, const void* proj,
-                                     void* y, void* sy, int nbands, int ld) {
+                                     void* y, void* sy, int nbands, int ld, bool planes = false) {
     const KPoint& kp = p->kp[ik];
     CombineArgs<TI, T> a;
     const bool dbl = sizeof(T) == 8;
@@ -339,6 +378,9 @@ CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const vo
     a.nb = p->nb;
     a.nint = p->nint;
     a.np = p->np;
+    a.nq = p->nq;
+    a.planes = planes ? 1 : 0;
+    a.wb = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
     if (p->np == 0) a.proj = nullptr;
     return a;
 }
@@ -353,8 +395,8 @@ constexpr int COMBINE_BB_NP = 64;
 
 template <typename TI, typename T>
 mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
-                       void* sy, int nbands, int ld, hipStream_t s) {
-    CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld);
+                       void* sy, int nbands, int ld, hipStream_t s, bool planes = false) {
+    CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld, planes);
     bool wide = y && a.proj && p->np >= COMBINE_BB_NP;
     if (wide) {
         const char* e = getenv("MBKS_COMBINE_BB");  // "1": one band per thread (cross-checks)
@@ -404,10 +446,10 @@ mb_status combine_batch_impl(const std::vector<BatchItem>& items, TableUploader&
 
 // prec: 0 = FP64 (c128), 1 = FP32 (c64), 2 = c128 vectors with FP32 local / nonlocal parts
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
-                         void* sy, int nbands, int ld, int prec, hipStream_t s) {
-    if (prec == 0) return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s);
-    if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
-    return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s);
+                         void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes) {
+    if (prec == 0) return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
+    if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
+    return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
 }
 
 mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s) {

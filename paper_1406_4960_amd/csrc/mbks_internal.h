@@ -37,11 +37,13 @@ struct KPoint {
     std::vector<int32_t> gmap;    // ng: grid index j1 * N2 + j2 of G
     std::vector<int32_t> rows;    // grid rows j1 that hold sphere points
     std::vector<zd> F;            // np x ld, in-plane projector factors (padding zero)
+    std::vector<int32_t> gtab;    // rows.size() x N2: G index at (sphere row, column j2), -1 outside
     // device copies
     double* d_kg2 = nullptr;
     float* d_kg2f = nullptr;
     int32_t* d_gmap = nullptr;
     int32_t* d_rows = nullptr;
+    int32_t* d_gtab = nullptr;
     void* d_F64 = nullptr;        // np x ld complex128
     void* d_F32 = nullptr;        // np x ld complex64
     // preconditioner factors (T + sigma S) per G, [i][d][ld] doubles, built on demand
@@ -59,7 +61,7 @@ struct KPoint {
     // (0: FP64, 1: FP32 with complex64 vectors, 2: FP32 with complex128 vectors)
     struct Tune {
         int set = 0;
-        int kind = -1;        // local kernel: 0 line-per-thread, 1 two-step, 2 generic
+        int kind = -1;        // local kernel: 0 line-per-thread, 1 two-step, 2 generic, 3 plane
         int budget_kb = 110;  // LDS budget of the line-per-thread kernel (planes per group)
         int nl_mfma = -1;     // FP32 projector path: 1 matrix cores, 0 vector kernel, -1 default
     } tune[3];
@@ -109,6 +111,7 @@ struct Problem {
     int32_t* d_zwin = nullptr;
     int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors
     double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
+    double* d_Vt = nullptr;    float* d_Vtf = nullptr;  // nzq x N2 x N1 (plane kernel grids only)
     void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)
     void* d_tw2 = nullptr; void* d_tw2f = nullptr;
 
@@ -157,7 +160,7 @@ struct HWork {
     void* nlpart = nullptr;
 };
 // bytes of each H work buffer for nbands vectors; prec as for apply_h
-size_t hwork_part_bytes(const Problem* p, int nbands, int ld, int prec);
+size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec);
 size_t hwork_proj_bytes(const Problem* p, int nbands, int prec);
 size_t hwork_nlpart_bytes(const Problem* p, int nbands, int prec);
 mb_status upload_group_windows(Problem* p);
@@ -173,14 +176,24 @@ mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int 
                              int prec, hipStream_t s, int budget_kb = 110);
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
                             int prec, hipStream_t s);
+// plane kernel (one output row per Gauss plane); MB_ERR_INVALID_ARG = no variant for this grid
+bool plane_kernel_grid(const Problem* p);
+mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,
+                             hipStream_t s);
+// transposed potential copies for the plane kernel (after the potential changes)
+mb_status refresh_vt(Problem* p, hipStream_t s);
+// the local kernel apply_h runs for (k-point, local precision) writes one row per Gauss
+// plane (true) or kappa partial rows per knot interval (false)
+bool local_uses_planes(const Problem* p, int ik, int lp);
 // matrix-core projections: mode 1 FP32 MFMA, mode 2 BF16x3 MFMA; vin64 = complex128 vectors
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
                                  bool vin64, hipStream_t s, void* nlpart = nullptr);
 // bytes of the matrix-core partial projections; mode 0 FP64, else FP32 partials
 size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode);
-// y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null
+// y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null;
+// planes: part holds one row per Gauss plane (plane kernel) instead of kappa rows per interval
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
-                         void* y, void* sy, int nbands, int ld, int prec, hipStream_t s);
+                         void* y, void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes = false);
 mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
                       hipStream_t s);
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,

@@ -303,26 +303,30 @@ def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
     p.close()
 
 
-@pytest.mark.parametrize("cfg,prec,nbands", [("graphene_2x2", "fp64", 5), ("graphene_2x2", "fp32", 5),
-                                             ("surface", "fp64", 2),
-                                             pytest.param("surface", "fp32", 2, marks=pytest.mark.skip(
-                                                 reason="the FP32 two-step kernel for the 128x64 grid failed this "
-                                                        "comparison in a run that left the GPU faulted; that "
-                                                        "instantiation is switched off until the cause is found")),
-                                             ("member-00", "fp64", 3), ("member-19", "fp64", 3),
-                                             ("member-33", "fp32", 3)])
-def test_split_kernel_matches_generic_kernel(cfg, prec, nbands, monkeypatch):
-    # the two-step line kernel of the larger grids (72^2, 128x64, 45^2, 75^2, 80^2)
-    # against the generic LDS-stage kernel; both compute the same operator, and the
-    # two-step kernel is also checked against the oracle through the sampled-row tests
+@pytest.mark.parametrize("cfg,prec,nbands,kernel", [("graphene_2x2", "fp64", 5, "default"),
+                                                    ("graphene_2x2", "fp32", 5, "default"),
+                                                    ("surface", "fp64", 2, "default"), ("surface", "fp32", 3, "default"),
+                                                    ("surface", "bf16x3", 3, "default"),
+                                                    ("surface", "fp64", 2, "split"),
+                                                    ("member-00", "fp64", 3, "default"),
+                                                    ("member-19", "fp64", 3, "default"),
+                                                    ("member-33", "fp32", 3, "default")])
+def test_local_kernels_match_generic_kernel(cfg, prec, nbands, kernel, monkeypatch):
+    # the two-step line kernel of the larger grids (72^2, 45^2, 75^2, 80^2; and the
+    # 128x64 grid in FP64 with MBKS_LOCAL_KERNEL=split) and the plane kernel of the
+    # 128x64 grid (default there, one output row per Gauss plane, projected by the
+    # combine pass) against the generic LDS-stage kernel; all compute the same
+    # operator, and each is also checked against the oracle through the sampled rows
     d = workloads.batched_member(int(cfg[-2:])) if cfg.startswith("member") else workloads.CONFIGS[cfg]()
-    print(f"[case] split vs generic {cfg} {prec}", flush=True)
+    print(f"[case] {kernel} local kernel vs generic {cfg} {prec}", flush=True)
     p, dm, _ = _setup(d, 0)
     x = random_lib_block(33, nbands, dm["nb"], dm["ng"], dm["ld"])
-    y_split = _run(p, "hpsi", 0, x, prec)
+    if kernel != "default":
+        monkeypatch.setenv("MBKS_LOCAL_KERNEL", kernel)
+    y_k = _run(p, "hpsi", 0, x, prec)
     monkeypatch.setenv("MBKS_LOCAL_KERNEL", "generic")
     y_gen = _run(p, "hpsi", 0, x, prec)
     monkeypatch.delenv("MBKS_LOCAL_KERNEL")
     tol = 1e-12 if prec == "fp64" else 1e-5
-    assert rel_err(y_split, y_gen) < tol
+    assert rel_err(y_k, y_gen) < tol
     p.close()
