@@ -188,22 +188,24 @@ mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nban
 mb_status mb_problem_reserve(mb_problem* p, int ik, int64_t max_bands, int64_t ld, int lock);
 
 /* Autotuner of the operator's kernel choices for one k-point, block size and
- * precision: times the local-potential kernels that support the grid (the
- * line-per-thread kernel at LDS budgets of 22-160 KB per workgroup, i.e. 1 to all
- * Gauss planes of an interval per workgroup; the two-step line kernel; the generic
- * kernel) and, in FP32, the two projector paths (vector kernel, matrix cores), on
+ * precision: times the local-potential kernels that support the grid, each with the
+ * combine pass that projects its output (the line-per-thread kernel at LDS budgets of
+ * 22-160 KB per workgroup, i.e. 1 to all Gauss planes of an interval per workgroup;
+ * the two-step line kernel; the generic kernel; the plane kernel in its two lane
+ * splits) and, in FP32, the two projector paths (vector kernel, matrix cores), on
  * nbands scratch vectors, and makes the fastest the choice of later hpsi_apply and
  * eigensolver calls on that k-point (MB_FP32 / MB_BF16X3 also set it for the
  * eigensolver's FP32 arithmetic on complex128 vectors).  A measurement call: it
  * allocates and frees scratch memory and synchronises `stream`; it must not overlap
  * other calls on the same k-point.  info may be NULL. */
 typedef struct {
-    int32_t local_kernel;     /* 0 line-per-thread, 1 two-step line, 2 generic */
+    int32_t local_kernel;     /* 0 line-per-thread, 1 two-step line, 2 generic, 3 plane */
     int32_t lds_budget_kb;    /* line-per-thread kernel: LDS budget per workgroup */
+    int32_t plane_variant;    /* plane kernel: 0 8 points per lane, 1 16 points per lane */
     int32_t nl_matrix_cores;  /* FP32 projectors: 1 matrix cores, 0 vector kernel, -1 not tuned */
     int32_t candidates;       /* configurations timed */
-    double local_ms;          /* chosen local kernel, per call of nbands vectors */
-    double local_default_ms;  /* the untuned choice, per call */
+    double local_ms;          /* chosen local kernel + combine pass, per call of nbands vectors */
+    double local_default_ms;  /* the untuned choice (local kernel + combine pass), per call */
     double nl_ms;             /* chosen projector path, per call (0 if not tuned) */
 } mb_tune_info;
 mb_status mb_autotune(mb_problem* p, int ik, int64_t nbands, mb_precision prec, void* stream,

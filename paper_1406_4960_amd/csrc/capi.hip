@@ -277,12 +277,13 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
             MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s,
                                           ext ? ext->nlpart : nullptr));
     }
-    const bool planes = local_uses_planes(p, ik, lp);
-    if (planes)
+    if (local_uses_planes(p, ik, lp)) {
         MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s));
-    else
+        MB_TRY(launch_zcombine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
+    } else {
         MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
-    MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, planes));
+        MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
+    }
     return MB_OK;
 }
 
@@ -571,7 +572,7 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
     const int cls = prec == MB_FP64 ? 0 : 1;
     const int nb = (int)nbands, ld = kp.ld;
     const size_t csz = cls == 0 ? 16 : 8;
-    void *c = nullptr, *part = nullptr, *proj = nullptr;
+    void *c = nullptr, *part = nullptr, *proj = nullptr, *y = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     mb_status st = MB_OK;
     const mb::KPoint::Tune saved = kp.tune[cls];
@@ -579,18 +580,21 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         if (c) (void)hipFree(c);
         if (part) (void)hipFree(part);
         if (proj) (void)hipFree(proj);
+        if (y) (void)hipFree(y);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    if (hipMalloc(&c, (size_t)nb * p->nb * ld * csz) != hipSuccess ||
-        hipMalloc(&part, (size_t)nb * p->nint * 4 * ld * csz) != hipSuccess ||
+    const size_t vbytes = (size_t)nb * p->nb * ld * csz;
+    const size_t prows = std::max<size_t>((size_t)p->nzq, (size_t)p->nint * 4);  // either local layout
+    if (hipMalloc(&c, vbytes) != hipSuccess || hipMalloc(&y, vbytes) != hipSuccess ||
+        hipMalloc(&part, (size_t)nb * prows * ld * csz) != hipSuccess ||
         hipMalloc(&proj, std::max<size_t>(16, (size_t)nb * p->np * csz)) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
         return set_error(MB_ERR_OOM, "mb_autotune: scratch allocation failed");
     }
-    (void)hipMemsetAsync(c, 0, (size_t)nb * p->nb * ld * csz, s);
+    (void)hipMemsetAsync(c, 0, vbytes, s);
     // average time of 3 calls after one warm-up; < 0 when the configuration is unsupported
     auto timeit = [&](auto&& call) -> double {
         mb_status r = call();
@@ -607,27 +611,46 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         (void)hipEventElapsedTime(&ms, e0, e1);
         return ms / 3.0;
     };
-    // each candidate through its own launcher, which reports a grid it cannot take
-    auto local_with = [&](int kind, int budget) {
-        if (kind == 0) return mb::launch_local_lines(p, ik, c, part, nb, ld, cls, s, budget);
-        if (kind == 1) return mb::launch_local_split(p, ik, c, part, nb, ld, cls, s);
-        kp.tune[cls] = mb::KPoint::Tune{1, 2, 110, -1};
-        return mb::launch_local(p, ik, c, part, nb, ld, cls, s);
+    // a candidate = a local kernel (kind 0 line-per-thread at an LDS budget, 1 two-step,
+    // 2 generic, 3 plane kernel in lane split var) followed by the combine pass that
+    // projects its output (the plane kernel's rows per Gauss plane lengthen that pass);
+    // each launcher reports a grid it cannot take
+    auto candidate = [&](int kind, int budget, int var) -> mb_status {
+        kp.tune[cls] = mb::KPoint::Tune{1, kind, budget, -1, var};
+        mb_status r;
+        if (kind == 0) r = mb::launch_local_lines(p, ik, c, part, nb, ld, cls, s, budget);
+        else if (kind == 1) r = mb::launch_local_split(p, ik, c, part, nb, ld, cls, s);
+        else if (kind == 2) r = mb::launch_local(p, ik, c, part, nb, ld, cls, s);
+        else r = mb::launch_local_plane(p, ik, c, part, nb, ld, cls, s);
+        if (r != MB_OK) return r;
+        if (kind == 3) return mb::launch_zcombine(p, ik, c, part, nullptr, y, nullptr, nb, ld, cls, s);
+        return mb::launch_combine(p, ik, c, part, nullptr, y, nullptr, nb, ld, cls, s);
     };
     // the untuned choice first
     kp.tune[cls] = mb::KPoint::Tune{};
-    const double t_default = timeit([&]() { return mb::launch_local(p, ik, c, part, nb, ld, cls, s); });
-    int best_kind = -1, best_budget = 110, ncand = 0;
+    const double t_default = timeit([&]() {
+        const bool planes = mb::local_uses_planes(p, ik, cls);
+        mb_status r = planes ? mb::launch_local_plane(p, ik, c, part, nb, ld, cls, s)
+                             : mb::launch_local(p, ik, c, part, nb, ld, cls, s);
+        if (r != MB_OK) return r;
+        if (planes) return mb::launch_zcombine(p, ik, c, part, nullptr, y, nullptr, nb, ld, cls, s);
+        return mb::launch_combine(p, ik, c, part, nullptr, y, nullptr, nb, ld, cls, s);
+    });
+    int best_kind = -1, best_budget = 110, best_var = 0, ncand = 0;
     double best = 1e300;
     const int budgets[] = {22, 44, 66, 88, 110, 160};
     for (int bk : budgets) {
-        const double t = timeit([&]() { return local_with(0, bk); });
+        const double t = timeit([&]() { return candidate(0, bk, 0); });
         if (st != MB_OK) break;
         if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = 0; best_budget = bk; } }
     }
     for (int kind = 1; kind <= 2 && st == MB_OK; ++kind) {
-        const double t = timeit([&]() { return local_with(kind, 110); });
+        const double t = timeit([&]() { return candidate(kind, 110, 0); });
         if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = kind; best_budget = 110; } }
+    }
+    for (int var = 0; var <= 1 && st == MB_OK; ++var) {
+        const double t = timeit([&]() { return candidate(3, 110, var); });
+        if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = 3; best_budget = 110; best_var = var; } }
     }
     int nl_mfma = -1;
     double nl_best = 0.0;
@@ -645,12 +668,13 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         cleanup();
         return st != MB_OK ? st : set_error(MB_ERR_INVALID_ARG, "mb_autotune: no local kernel ran");
     }
-    kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, nl_mfma};
+    kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, nl_mfma, best_var};
     if (cls == 1) kp.tune[2] = kp.tune[1];  // complex128 vectors with FP32 arithmetic (mixed solver)
     cleanup();
     if (info) {
         info->local_kernel = best_kind;
         info->lds_budget_kb = best_budget;
+        info->plane_variant = best_var;
         info->nl_matrix_cores = nl_mfma;
         info->candidates = ncand;
         info->local_ms = best;

@@ -97,16 +97,25 @@ __device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, int e) {
 
 // Radix-2 decimation-in-frequency network over the Q lanes of a line (lane l of the
 // line = l): natural lane order in, lane l ends with the outputs of index bitrev(l).
+// Each stage of both networks is one fused form for every lane: y = u + s x with
+// s = -1 on the upper lane of a pair (bit m of l set) and +1 on the lower, and the
+// stage twiddle on the upper lane only (w = 1 on the lower lanes and in the last
+// stage of the DIF network / the first of the DIT network, which have none).
 template <typename T, int L, int Q, int N, int SIGN, int QS = Q>
 __device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
     if constexpr (QS >= 2) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
-        const cx<T> w = tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS));
+        const T sg = h ? (T)-1 : (T)1;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             const cx<T> u = lane_xor_cx<m>(x[k]);
-            x[k] = h ? cmul(csub(u, x[k]), w) : cadd(x[k], u);
+            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
+        }
+        if constexpr (QS > 2) {
+            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+#pragma unroll
+            for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
         }
         dif_lanes<T, L, Q, N, SIGN, QS / 2>(x, l, tw);
     }
@@ -118,12 +127,16 @@ __device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw) {
     if constexpr (QS <= Q) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
-        const cx<T> w = tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS));
+        const T sg = h ? (T)-1 : (T)1;
+        if constexpr (QS > 2) {
+            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+#pragma unroll
+            for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
+        }
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-            const cx<T> v = h ? cmul(x[k], w) : x[k];
-            const cx<T> u = lane_xor_cx<m>(v);
-            x[k] = h ? csub(u, v) : cadd(v, u);
+            const cx<T> u = lane_xor_cx<m>(x[k]);
+            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
         }
         dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw);
     }
@@ -320,10 +333,19 @@ mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, i
 
 template <typename TI, typename T>
 mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, int ld, hipStream_t s) {
-    // 16 lanes x 8 points per column and 8 x 8 per row, 512 threads (two tasks per
-    // thread and pass): FP64 planes fill one CU's LDS, FP32 planes two workgroups per CU
+    // Two lane splits, 512 threads each (FP64 planes fill one CU's LDS, FP32 planes two
+    // workgroups per CU): variant 0 holds 8 points per lane (16 lanes per 128-point
+    // column, 8 per 64-point row; fewer registers), variant 1 holds 16 (8 and 4 lanes;
+    // one lane-exchange stage less per line).  mb_autotune may pick either.
     constexpr int NT = 512;
-    if (p->N1 == 128 && p->N2 == 64) return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
+    // untuned: 16 points per lane in FP64 (30 ms against 50 ms per 320 bands of the
+    // surface slab), 8 in FP32 (16 ms against 19 ms)
+    const KPoint::Tune& tn = p->kp[ik].tune[sizeof(T) == 8 ? 0 : (sizeof(TI) == 8 ? 2 : 1)];
+    const int var = (tn.set && tn.kind == 3) ? tn.plane_var : (sizeof(T) == 8 ? 1 : 0);
+    if (p->N1 == 128 && p->N2 == 64) {
+        if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1>(p, ik, c, u, nbands, ld, s);
+        return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
+    }
     return MB_ERR_INVALID_ARG;
 }
 

@@ -1,0 +1,216 @@
+// Combine pass of H c for the plane layout of the local part, with both contractions
+// along z on the matrix cores:
+//   y(G, i) = 1/2 sum_j (D_z[i][j] + |k+G|^2 S_z[i][j]) c(G, j)        kinetic (banded)
+//           + sum_q w_q B_i(z_q) u_q(G)                                 local part, planes q
+//           + sum_p Z_p(i) F_p(G) P'_p                                  Kleinman-Bylander
+//   sy(G, i) = sum_j S_z[i][j] c(G, j)                                  overlap (optional)
+// (kinetic, local and nonlocal matrix elements of Sec. II.B.1; P'_p = E_p <beta_p|c>).
+// The last two terms are real (z) x complex (G) products C = A X with A[i][k] the
+// spline weights w_q B_i(z_q) (k = plane q) or Z_p(i) (k = projector p) and
+// X[k][G] = u_q(G) or F_p(G) P'_p, computed per 16-row x 16-column tile by
+// v_mfma_f32_16x16x4_f32 / v_mfma_f64_16x16x4_f64 (real and imaginary parts of X as
+// two products with the same A).  Only the planes of the intervals that hold the
+// tile's splines and the projector groups whose z-window meets the tile enter.  The
+// banded kinetic and overlap terms run on the vector units, in FP64, for the rows
+// each lane holds in the matrix-core output layout.
+// Lane layouts (gfx950): A[l%16][l/16], B[l/16][l%16]; output f32: D[4(l/16)+r][l%16],
+// f64: D[4r + l/16][l%16], r < 4.
+#include <algorithm>
+#include <vector>
+
+#include "cplx.h"
+#include "mbks_internal.h"
+
+namespace mb {
+
+namespace {
+
+constexpr int KORD = 4;
+constexpr int ZC_BB = 4;  // bands per wave
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+    using type = v4f;
+    __device__ static v4f step(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // output row of accumulator element r for lane group g
+    __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct MfmaAcc<double> {
+    using type = v4d;
+    __device__ static v4d step(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int g, int r) { return 4 * r + g; }
+};
+
+template <typename TI, typename T>
+struct ZArgs {
+    const cx<TI>* c;       // [b][i][ld]
+    const cx<T>* u;        // [b][q][ld] plane rows of the local part
+    const T* wb;           // [q][kappa]: w_q B_{s-1+t}(z_q)
+    const cx<T>* proj;     // [b][np]: E_p <beta_p|c> (null: no projectors)
+    const cx<T>* F;        // [np][ld]
+    const T* Z;            // [np][nb]
+    const int32_t* gwin;   // [ngrp][2]: union z-window of each group of 16 projectors
+    cx<TI>* y;
+    cx<TI>* sy;            // may be null
+    const double* sband;
+    const double* dband;
+    const double* kg2;
+    int nbands, ld, ng, nb, nint, nq, nzq, np;
+};
+
+// One workgroup = 4 waves = 4 consecutive 16-column tiles of one 16-row tile, for
+// ZC_BB bands.
+template <typename TI, typename T>
+__global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
+    using A = MfmaAcc<T>;
+    using V = typename A::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int G0 = ((int)blockIdx.x * 4 + wave) * 16;
+    if (G0 >= a.ld) return;
+    const int i0 = (int)blockIdx.y * 16;
+    const int b0 = (int)blockIdx.z * ZC_BB;
+    const int nbg = min(ZC_BB, a.nbands - b0);
+    const int Gm = G0 + m;
+    const bool gv = Gm < a.ng;
+    const int ia = i0 + m;  // row of this lane's A operand
+
+    V acc[ZC_BB][2];
+#pragma unroll
+    for (int bb = 0; bb < ZC_BB; ++bb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[bb][h] = V{0, 0, 0, 0};
+
+    // local part: planes of the intervals s = i - 2 .. i + 1 of the tile's rows
+    {
+        const int s_lo = max(i0 - 2, 0), s_hi = min(i0 + 16, a.nint - 1);
+        const int q_lo = s_lo * a.nq, q_hi = (s_hi + 1) * a.nq;
+        for (int qk = q_lo; qk < q_hi; qk += 4) {
+            const int q = qk + g;
+            T w = 0;
+            if (q < q_hi && ia < a.nb) {
+                const int t = ia + 1 - q / a.nq;
+                if (t >= 0 && t < KORD) w = a.wb[(size_t)q * KORD + t];
+            }
+            const int qc = q < q_hi ? q : q_lo;
+#pragma unroll
+            for (int bb = 0; bb < ZC_BB; ++bb) {
+                cx<T> v = mk<T>(0, 0);
+                if (bb < nbg && gv) v = a.u[((size_t)(b0 + bb) * a.nzq + qc) * a.ld + Gm];
+                acc[bb][0] = A::step(w, v.x, acc[bb][0]);
+                acc[bb][1] = A::step(w, v.y, acc[bb][1]);
+            }
+        }
+    }
+    // Kleinman-Bylander expansion: projector groups whose window meets the tile
+    if (a.proj) {
+        const int ngrp = (a.np + 15) / 16;
+        for (int grp = 0; grp < ngrp; ++grp) {
+            if (a.gwin[2 * grp] > i0 + 15 || a.gwin[2 * grp + 1] < i0) continue;
+#pragma unroll
+            for (int pk = 0; pk < 16; pk += 4) {
+                const int p = grp * 16 + pk + g;
+                const bool pv = p < a.np;
+                const T z = (pv && ia < a.nb) ? a.Z[(size_t)p * a.nb + ia] : (T)0;
+                const cx<T> f = (pv && gv) ? a.F[(size_t)p * a.ld + Gm] : mk<T>(0, 0);
+#pragma unroll
+                for (int bb = 0; bb < ZC_BB; ++bb) {
+                    const cx<T> pp = (pv && bb < nbg) ? a.proj[(size_t)(b0 + bb) * a.np + p] : mk<T>(0, 0);
+                    const cx<T> v = cmul(f, pp);
+                    acc[bb][0] = A::step(z, v.x, acc[bb][0]);
+                    acc[bb][1] = A::step(z, v.y, acc[bb][1]);
+                }
+            }
+        }
+    }
+    if (Gm >= a.ld) return;
+    const double kk = gv ? 0.5 * a.kg2[Gm] : 0.0;
+#pragma unroll
+    for (int bb = 0; bb < ZC_BB; ++bb) {
+        if (bb >= nbg) break;
+        const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + A::row(g, r);
+            if (i >= a.nb) continue;
+            if (!gv) {
+                a.y[vb + (size_t)i * a.ld + Gm] = mk<TI>(0, 0);
+                if (a.sy) a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>(0, 0);
+                continue;
+            }
+            double sr = 0, si = 0, tr = 0, ti = 0;
+#pragma unroll
+            for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
+                const int j = i + d;
+                if (j < 0 || j >= a.nb) continue;
+                const int lo = d >= 0 ? i : j;
+                const int dd = d >= 0 ? d : -d;
+                const cx<TI> cv = a.c[vb + (size_t)j * a.ld + Gm];
+                const double sv = a.sband[lo * KORD + dd];
+                const double tv = 0.5 * a.dband[lo * KORD + dd];
+                sr += sv * (double)cv.x;
+                si += sv * (double)cv.y;
+                tr += tv * (double)cv.x;
+                ti += tv * (double)cv.y;
+            }
+            if (a.sy) a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)sr, (TI)si);
+            const double yr = tr + kk * sr + (double)acc[bb][0][r];
+            const double yi = ti + kk * si + (double)acc[bb][1][r];
+            a.y[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)yr, (TI)yi);
+        }
+    }
+}
+
+template <typename TI, typename T>
+mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
+                        int nbands, int ld, hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    constexpr bool dbl = sizeof(T) == 8;
+    ZArgs<TI, T> a;
+    a.c = (const cx<TI>*)c;
+    a.u = (const cx<T>*)u;
+    a.wb = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
+    a.proj = p->np > 0 ? (const cx<T>*)proj : nullptr;
+    a.F = (const cx<T>*)(dbl ? kp.d_F64 : kp.d_F32);
+    a.Z = (const T*)(dbl ? (const void*)p->d_Z : (const void*)p->d_Zf);
+    a.gwin = p->d_gwin;
+    a.y = (cx<TI>*)y;
+    a.sy = (cx<TI>*)sy;
+    a.sband = p->d_sband;
+    a.dband = p->d_dband;
+    a.kg2 = kp.d_kg2;
+    a.nbands = nbands;
+    a.ld = ld;
+    a.ng = kp.ng;
+    a.nb = p->nb;
+    a.nint = p->nint;
+    a.nq = p->nq;
+    a.nzq = p->nzq;
+    a.np = p->np;
+    if (p->np > 0 && !p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
+    const dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((p->nb + 15) / 16), (unsigned)((nbands + ZC_BB - 1) / ZC_BB));
+    StageScope ts_(MB_STAGE_COMBINE, s, nbands);
+    hipLaunchKernelGGL((k_zcombine<TI, T>), grid, dim3(256), 0, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+}  // namespace
+
+// y = H c from the plane rows u of the local part (sy = S c if non-null); prec as
+// launch_combine
+mb_status launch_zcombine(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
+                          int nbands, int ld, int prec, hipStream_t s) {
+    if (nbands == 0) return MB_OK;
+    if (prec == 0) return zcombine_impl<double, double>(p, ik, c, u, proj, y, sy, nbands, ld, s);
+    if (prec == 1) return zcombine_impl<float, float>(p, ik, c, u, proj, y, sy, nbands, ld, s);
+    return zcombine_impl<double, float>(p, ik, c, u, proj, y, sy, nbands, ld, s);
+}
+
+}  // namespace mb

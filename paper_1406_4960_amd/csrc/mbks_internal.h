@@ -64,6 +64,7 @@ struct KPoint {
         int kind = -1;        // local kernel: 0 line-per-thread, 1 two-step, 2 generic, 3 plane
         int budget_kb = 110;  // LDS budget of the line-per-thread kernel (planes per group)
         int nl_mfma = -1;     // FP32 projector path: 1 matrix cores, 0 vector kernel, -1 default
+        int plane_var = 0;    // plane kernel lane split: 0 8 points per lane, 1 16 points per lane
     } tune[3];
 };
 
@@ -194,6 +195,9 @@ size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode);
 // planes: part holds one row per Gauss plane (plane kernel) instead of kappa rows per interval
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
                          void* y, void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes = false);
+// the combine pass of the plane layout with the z contractions on the matrix cores
+mb_status launch_zcombine(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
+                          int nbands, int ld, int prec, hipStream_t s);
 mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
                       hipStream_t s);
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,

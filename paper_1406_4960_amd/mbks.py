@@ -61,8 +61,9 @@ class LanczosOpts(ctypes.Structure):
 
 
 class TuneInfo(ctypes.Structure):
-    _fields_ = [("local_kernel", c_int32), ("lds_budget_kb", c_int32), ("nl_matrix_cores", c_int32),
-                ("candidates", c_int32), ("local_ms", c_double), ("local_default_ms", c_double), ("nl_ms", c_double)]
+    _fields_ = [("local_kernel", c_int32), ("lds_budget_kb", c_int32), ("plane_variant", c_int32),
+                ("nl_matrix_cores", c_int32), ("candidates", c_int32), ("local_ms", c_double),
+                ("local_default_ms", c_double), ("nl_ms", c_double)]
 
 
 class LanczosInfo(ctypes.Structure):

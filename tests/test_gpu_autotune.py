@@ -12,7 +12,8 @@ DEV = "cuda:0"
 
 
 @pytest.mark.parametrize("cfg,prec,kinds", [("graphene", "fp64", {0, 2}), ("graphene", "fp32", {0, 2}),
-                                            ("graphene_2x2", "fp32", {1, 2}), ("graphene_2x2", "fp64", {1, 2})])
+                                            ("graphene_2x2", "fp32", {1, 2}), ("graphene_2x2", "fp64", {1, 2}),
+                                            ("surface", "fp32", {2, 3}), ("surface", "fp64", {1, 2, 3})])
 def test_autotune_keeps_operator(cfg, prec, kinds):
     print(f"[case] autotune {cfg} {prec}", flush=True)
     d = workloads.CONFIGS[cfg]()
