@@ -1,35 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the mixed-basis eigen-search hot path on one MI355X.
 
-Workload: the graphene-like slab (hexagonal a = 4.65 bohr, 36x36 in-plane grid,
-~483 G per k-point, 80 graded cubic B-splines on [-20, 20] with 5 Gauss points
-per interval, 2 atoms with Gaussian local parts and 4 Kleinman-Bylander
-projectors each, 2x2 Monkhorst-Pack k-points, 32 bands; n = 38,640 per k),
-synthetic and seeded.
+Headline workload: the large surface slab (4x2 surface cell of 19.07 x 9.534 bohr,
+128x64 in-plane grid, ~3,990 G per k-point, 192 graded cubic B-splines on
+[-30, 30] with 6 Gauss points per interval, 64 atoms in 8 layers with 4
+Kleinman-Bylander projectors each, 4x2 Monkhorst-Pack k-points, 320 bands;
+n = 766,656 per k-point), synthetic and seeded.
 
-One step = the 32 lowest eigenpairs of every k-point from a seeded random start
-(lanczos_lowest_batched over the 4 k-points, which runs them concurrently on
-streams of their own), in the headline precision (mixed: FP32 local / nonlocal
-parts of H until the residual reaches 1e-4, then FP64; FP64 orthonormalisation,
-Krylov coefficients and projected problems throughout), to residual 1e-7.
+One step = H applied to all 8 x 320 band-vectors (one hpsi_apply per k-point on
+its 320 vectors, inputs resident in HBM) in the mixed form's reduced precision:
+FP32 FFTs, potential multiply, projector contractions and spline projections,
+FP64 banded kinetic and overlap sums.
 
 Printed JSON line:
-  value            H band-vectors applied per second over the timed steps
-  ms_per_step      time to the 4 x 32 eigenpairs (all k-points)
-  fp64             the same step in plain FP64 (time, eigenvalue errors)
-  hpsi             pure hpsi_apply throughput (32 bands x 4 k per call) in FP64 / FP32,
-                   eager and replayed from a captured HIP graph
-  batched_48       the 48-problem uneven batch: hpsi_apply_batched throughput per
-                   precision, and mixed vs FP64 time to the eigenpairs of its first
-                   problems
+  value            band-vectors of H per second over the timed steps (8 x 320 per step)
+  ms_per_step      time of one step
+  surface          per-stage times of a step, the BF16x3 step, FP64 hpsi_apply on
+                   k-point 0 (320 vectors), and the time to the 320 lowest eigenpairs of
+                   k-point 0 mixed vs FP64 (with errors against the stored oracle values)
+  graphene         the graphene-like slab (36x36 grid, 4 k-points x 32 bands): hpsi_apply
+                   per precision and the time to all its eigenpairs mixed vs FP64
+  batched_48       the 48-problem uneven batch: hpsi_apply_batched per precision and the
+                   time to the eigenpairs of its first problems mixed vs FP64
   supercell_2x2    the 2x2 supercell (72x72 grid, 64 bands, 4 k-points): time to its
                    eigenpairs mixed vs FP64
-  surface          the large surface slab (128x64 grid, 256 projectors, 320 bands),
-                   k-point 0: hpsi_apply throughput per precision and time to its
-                   320 eigenpairs mixed vs FP64
-  roofline         the fused local-potential kernel (dominant kernel), from its
-                   launches in the FP64 hpsi leg
-  cpu_baseline     the CPU FP64 oracle's matrix-free H application, bounded sample
+  roofline         the local-potential plane kernel (largest share of a step), from HIP
+                   events around its launches on the library's stream in the timed steps
+  cpu_baseline     the CPU FP64 oracle's matrix-free H (FFT local part) on a bounded
+                   sample of the same workload
 """
 from __future__ import annotations
 
@@ -55,48 +53,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def local_model(p, ik, csz_in, csz):
-    """Algorithmic flops and bytes per band-vector of the fused local kernel
-    (B-spline evaluate, inverse FFT, V multiply, forward FFT, project)."""
+def local_model(p, ik, csz_in, csz, planes=True):
+    """Algorithmic flops and HBM bytes per band-vector of the local-potential kernel
+    (B-spline evaluate, inverse 2D FFT, V multiply, forward 2D FFT, and either the
+    per-plane output rows (plane kernel) or the kappa partial rows per interval)."""
     dm = p.dims(ik)
     N1, N2 = p.desc["grid"]
     N = N1 * N2
     nzq, ng, nb = dm["nzq"], dm["ng"], dm["nb"]
     nint = len(p.desc["breakpoints"]) - 1
     flops = nzq * (32 * ng + 10 * N * math.log2(N) + 2 * N)
-    bytes_ = nb * ng * csz_in + 4 * nint * ng * csz
+    rows_out = nzq if planes else 4 * nint
+    bytes_ = nb * ng * csz_in + rows_out * ng * csz
     vbytes = nzq * N * (csz // 2)
     return flops, bytes_, vbytes
 
 
 def traffic_record(name):
     """HBM traffic per launch measured with rocprofv3 counters, if the kernel
-    source has not changed since (compared by hash)."""
+    sources have not changed since (compared by hash)."""
     path = os.path.join(ROOT, "profiles", f"{name}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    files = rec.get("sources", [rec.get("source", "k_local.hip")])
     h = hashlib.sha256()
-    for f in files:
+    for f in rec.get("sources", []):
         h.update(open(os.path.join(ROOT, "paper_1406_4960_amd", "csrc", f), "rb").read())
     if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec
 
 
-def cpu_baseline(desc, budget_s=15.0):
-    """Oracle matrix-free FP64 H application on the same workload (k-point 0),
-    bounded sample: blocks of 8 band-vectors until ~budget_s seconds."""
-    from oracle import matfree
+def cpu_baseline(desc, nbands=8, budget_s=15.0):
+    """Oracle matrix-free FP64 H application (local part through numpy FFTs) on the
+    same workload, k-point 0, blocks of nbands band-vectors until ~budget_s seconds."""
+    from oracle import matfree, operators
+    from oracle.bspline import ZBasis
     from paper_1406_4960_amd import workloads
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    mf = matfree.MatFree(desc, 0)
-    x = workloads.random_block(99, 8, mf.ng, mf.nb)
+    threads = max(threads, len(os.sched_getaffinity(0)))
+    zb = ZBasis(desc["breakpoints"], desc["order"], desc["nq"])
+    vg = operators.gaussian_potential_on_grid_separable(desc, zb.zq)
+    mf = matfree.MatFree(desc, 0, local="fft", vgrid=vg)
+    x = np.transpose(workloads.random_block(99, nbands, mf.nb, mf.ng), (0, 2, 1))
     mf.apply(x[:1])  # warm
     done, t0 = 0, time.perf_counter()
     while True:
@@ -105,9 +108,10 @@ def cpu_baseline(desc, budget_s=15.0):
         el = time.perf_counter() - t0
         if el > budget_s:
             break
-    return {"value": done / el, "unit": "band-vectors/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} band-vectors of H (k-point 0, FP64 matrix-free oracle) in {el:.1f} s; "
-                      f"potential tables built before timing"}
+    return {"value": round(done / el, 3), "unit": "band-vectors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} band-vectors of H on k-point 0 of {desc['name']} in blocks of {nbands} "
+                      f"(FP64 matrix-free oracle, local part through numpy FFTs) in {el:.1f} s; "
+                      f"potential grid and tables built before timing"}
 
 
 def batched_leg(args, torch, mbks, workloads):
@@ -204,50 +208,106 @@ def c3_leg(torch, mbks, workloads):
     return res
 
 
-def surface_leg(torch, mbks, workloads):
-    """The large surface slab (128x64 grid, ~3,990 G, 192 splines with 6 Gauss
-    points, 64 atoms / 256 projectors, 320 bands) at k-point 0 of its 8: pure
-    hpsi_apply throughput per precision on 320 band-vectors, and the time to its
-    320 lowest eigenpairs in the mixed form and in plain FP64."""
-    d = workloads.surface()
+def graphene_leg(torch, mbks, workloads, steps=2):
+    """The graphene-like slab (36x36 grid, 4 k-points x 32 bands): hpsi_apply per
+    precision (32 bands per call) and the time to all 4 x 32 eigenpairs solved
+    together, mixed vs FP64, with errors against the stored oracle eigenvalues."""
+    d = workloads.graphene()
     p = mbks.Problem(d, device=0)
-    dm = p.dims(0)
-    M = d["nbands"]
-    res = {"workload": d["name"], "kpoint": 0, "bands": M, "n_per_k": dm["ng"] * dm["nb"],
-           "projectors": dm["np"], "gauss_planes": dm["nzq"]}
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(14064964)
-    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64), ("bf16x3", torch.complex64)):
-        x = torch.randn((M, dm["nb"], dm["ld"]), dtype=ct, device="cuda:0", generator=gen)
-        x[:, :, dm["ng"]:] = 0
-        y = torch.empty_like(x)
-        p.hpsi(0, x, y, prec)
+    nk, M = len(d["kpts"]), d["nbands"]
+    res = {"workload": d["name"], "kpoints": nk, "bands": M}
+    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+        xs, ys = [], []
+        for ik in range(nk):
+            dm = p.dims(ik)
+            xt = torch.zeros((M, dm["nb"], dm["ld"]), dtype=ct, device="cuda:0")
+            xt[:, :, :dm["ng"]] = torch.from_numpy(workloads.random_block(ik, M, dm["nb"], dm["ng"])).to("cuda:0").to(ct)
+            xs.append(xt)
+            ys.append(torch.empty_like(xt))
+        for ik in range(nk):
+            p.hpsi(ik, xs[ik], ys[ik], prec)
         torch.cuda.synchronize()
-        reps = 3
-        mbks.timer_enable(True)
+        reps = 10
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            p.hpsi(0, x, y, prec)
+            for ik in range(nk):
+                p.hpsi(ik, xs[ik], ys[ik], prec)
         e1.record()
         torch.cuda.synchronize()
-        st = mbks.timer_read()
-        mbks.timer_enable(False)
-        ms = e0.elapsed_time(e1) / reps
-        res[f"hpsi_{prec}"] = {"band_vectors_per_s": round(M / (ms * 1e-3), 1), "ms_per_call": round(ms, 3),
-                               "stages_ms_per_call": {k: round(v[0] / reps, 3) for k, v in st.items() if v[1]}}
-        # the fused local kernel against the vector ALU peak of its arithmetic type
-        lname = "local" if prec == "fp64" else "local32"
-        if st.get(lname, (0, 0, 0))[1]:
-            lms, _, lunits = st[lname]
-            flops_b = local_model(p, 0, 16, 16)[0]
-            ach = flops_b * lunits / (lms * 1e-3) / 1e12
-            peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
-            res[f"hpsi_{prec}"]["local_kernel_alu"] = {"achieved_tflops": round(ach, 3), "peak": peak,
-                                                       "frac": round(ach / peak, 4)}
-        log("surface hpsi", prec, res[f"hpsi_{prec}"])
-        del x, y
-        torch.cuda.empty_cache()
+        ms = e0.elapsed_time(e1)
+        res[f"hpsi_{prec}"] = {"band_vectors_per_s": round(reps * nk * M / (ms * 1e-3), 1),
+                               "ms_per_call": round(ms / (reps * nk), 4)}
+        del xs, ys
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "graphene_eigs.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath))
+    kb = mbks.Batch([(p, ik) for ik in range(nk)])
+    kb.lanczos_lowest([M] * nk, "fp32")  # workspaces, factors
+    for prec in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            eigs, xs, infos, st = kb.lanczos_lowest([M] * nk, prec)
+            del xs
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        err = None
+        if golden:
+            err = max(float(np.max(np.abs(eigs[ik] - np.array(golden["kpoints"][str(ik)]["eps"]))))
+                      for ik in range(nk) if str(ik) in golden["kpoints"])
+        res[prec] = {"ms_to_eigenpairs": round(ms, 2), "max_eig_err_vs_oracle": err,
+                     "max_resid": max(i["max_resid"] for i in infos),
+                     "h_applies": sum(i["h_applies"] for i in infos)}
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_to_eigenpairs"] / res["fp32"]["ms_to_eigenpairs"], 3)
+    log("graphene", res)
+    kb.close()
+    p.close()
+    return res
+
+
+def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
+    """FP64 hpsi_apply on k-point 0 (320 vectors), and the time to the 320 lowest
+    eigenpairs of k-point 0 (the share of one GPU in a k-point split over 8) in the
+    mixed form and in plain FP64, with the errors of the lowest ones against the
+    stored oracle eigenvalues; optionally all 8 k-points (lanczos_lowest_batched)."""
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    M = d["nbands"]
+    res = {}
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(14064965)
+    x = torch.randn((M, dm["nb"], dm["ld"]), dtype=torch.complex128, device="cuda:0", generator=gen)
+    x[:, :, dm["ng"]:] = 0
+    y = torch.empty_like(x)
+    p.hpsi(0, x, y, "fp64")
+    torch.cuda.synchronize()
+    reps = 3
+    mbks.timer_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        p.hpsi(0, x, y, "fp64")
+    e1.record()
+    torch.cuda.synchronize()
+    st = mbks.timer_read()
+    mbks.timer_enable(False)
+    ms = e0.elapsed_time(e1) / reps
+    flops_b = local_model(p, 0, 16, 16)[0]
+    lms, lcount, lunits = st["local"]
+    ach = flops_b * lunits / (lms * 1e-3) / 1e12
+    res["hpsi_fp64_k0"] = {"band_vectors_per_s": round(M / (ms * 1e-3), 1), "ms_per_call": round(ms, 3),
+                           "stages_ms_per_call": {k: round(v[0] / reps, 3) for k, v in st.items() if v[1]},
+                           "local_kernel_alu": {"achieved_tflops": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                                                "frac": round(ach / PEAK_FP64_TFLOPS, 4)}}
+    log("surface fp64 hpsi", res["hpsi_fp64_k0"])
+    del x, y
+    torch.cuda.empty_cache()
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "surface_eigs.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath))
     o = p.default_opts()
     o.max_iter = 1
     xs = p.lanczos_lowest(0, M, "fp64", opts=o, raise_not_converged=False)[1]  # workspaces, factors
@@ -256,17 +316,37 @@ def surface_leg(torch, mbks, workloads):
     for prec in ("fp32", "fp64"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        e, xs, info, st = p.lanczos_lowest(0, M, prec, raise_not_converged=False)
+        e, xs, info, stt = p.lanczos_lowest(0, M, prec, raise_not_converged=False)
         torch.cuda.synchronize()
-        res[prec] = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": st, "iters": info["iters"],
-                     "iters_reduced_precision": info["iters_low"], "h_applies": info["h_applies"],
-                     "max_resid": info["max_resid"]}
+        rec = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": stt, "iters": info["iters"],
+               "iters_reduced_precision": info["iters_low"], "h_applies": info["h_applies"],
+               "max_resid": info["max_resid"]}
+        if golden and "0" in golden["kpoints"]:
+            ref = np.array(golden["kpoints"]["0"]["eps"])
+            err = np.abs(e[:len(ref)] - ref)
+            rec["eig_err_vs_oracle_lowest"] = {"count": len(ref), "max": float(err.max()),
+                                               "per_eigenvalue": [float(v) for v in err]}
         eigs[prec] = e
+        res[f"eig_k0_{prec}"] = rec
         del xs
         torch.cuda.empty_cache()
-        log("surface solve", prec, res[prec])
-    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
-    res["max_eig_diff_mixed_vs_fp64"] = float(np.max(np.abs(eigs["fp32"] - eigs["fp64"])))
+        log("surface solve k0", prec, rec)
+    res["eig_k0_speedup_mixed_vs_fp64"] = round(res["eig_k0_fp64"]["ms"] / res["eig_k0_fp32"]["ms"], 3)
+    res["eig_k0_max_diff_mixed_vs_fp64"] = float(np.max(np.abs(eigs["fp32"] - eigs["fp64"])))
+    if full_eig:
+        nk = len(d["kpts"])
+        b = mbks.Batch([(p, ik) for ik in range(nk)])
+        for prec in ("fp32", "fp64"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, xs, infos, stt = b.lanczos_lowest([M] * nk, prec, raise_not_converged=False)
+            torch.cuda.synchronize()
+            res[f"eig_all_{prec}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": stt,
+                                      "max_resid": max(i["max_resid"] for i in infos)}
+            del xs
+            torch.cuda.empty_cache()
+            log("surface solve all k", prec, res[f"eig_all_{prec}"])
+        b.close()
     p.close()
     return res
 
@@ -274,18 +354,18 @@ def surface_leg(torch, mbks, workloads):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="graphene")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
-                    help="reduced precision of the headline step (fp32 = mixed FP32/FP64)")
-    ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--hpsi-reps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3", "fp64"],
+                    help="precision of the headline H application (fp32: the mixed form's reduced precision)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the surface FP64 / eigenpair leg")
+    ap.add_argument("--full-eig", action="store_true",
+                    help="also time all 8 x 320 eigenpairs of the surface slab, mixed and FP64 (minutes)")
+    ap.add_argument("--no-graphene", action="store_true", help="skip the graphene-like slab leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
-    ap.add_argument("--no-surface", action="store_true",
-                    help="skip the surface-slab leg (320 bands: hpsi per precision, eigenpairs of one k-point)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
                     help="problems of the uneven batch whose eigenpairs are timed (all their k-points)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -307,174 +387,109 @@ def main(argv=None):
         print(json.dumps({"copy_bytes": 4 * n}))
         return 0
 
-    desc = workloads.CONFIGS[args.workload]()
-    nk = len(desc["kpts"])
-    M = desc["nbands"]
+    d = workloads.surface()
+    nk, M = len(d["kpts"]), d["nbands"]
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    p = mbks.Problem(desc, device=0)
-    dims = [p.dims(ik) for ik in range(nk)]
-    log("workload", desc["name"], dims[0])
-
-    # ---- kernel choices measured per k-point (mb_autotune), kept for the run ----
-    tuned = {}
-    for prec in ("fp64", "fp32"):
-        tuned[prec] = [p.autotune(ik, M, prec) for ik in range(nk)]
-    log("autotune", tuned)
-
-    # ---- pure H application throughput (inputs resident in HBM) ---------------
-    hp = {}
-    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64)):
-        xs, ys = [], []
-        for ik in range(nk):
-            x = workloads.random_block(ik, M, dims[ik]["nb"], dims[ik]["ng"])
-            xt = torch.zeros((M, dims[ik]["nb"], dims[ik]["ld"]), dtype=ct, device=dev)
-            xt[:, :, :dims[ik]["ng"]] = torch.from_numpy(x).to(dev).to(ct)
-            xs.append(xt)
-            ys.append(torch.empty_like(xt))
-        for _ in range(3):
-            for ik in range(nk):
-                p.hpsi(ik, xs[ik], ys[ik], prec)
-        torch.cuda.synchronize()
-        mbks.timer_enable(True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.hpsi_reps):
-            for ik in range(nk):
-                p.hpsi(ik, xs[ik], ys[ik], prec)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        st = mbks.timer_read()
-        mbks.timer_enable(False)
-        # the same calls captured once in a HIP graph and replayed
-        gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr):
-            for ik in range(nk):
-                p.hpsi(ik, xs[ik], ys[ik], prec)
-        gr.replay()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.hpsi_reps):
-            gr.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ms_graph = e0.elapsed_time(e1)
-        del gr
-        hp[prec] = {"band_vectors_per_s": args.hpsi_reps * nk * M / (ms * 1e-3),
-                    "ms_per_call": ms / (args.hpsi_reps * nk),
-                    "graph_band_vectors_per_s": args.hpsi_reps * nk * M / (ms_graph * 1e-3),
-                    "stages_ms": {k: round(v[0], 4) for k, v in st.items() if v[1]},
-                    "stage_raw": st}
-        log("hpsi", prec, {k: v for k, v in hp[prec].items() if k != "stage_raw"})
-        del xs, ys
-
-    # ---- eigen-search steps --------------------------------------------------
-    # all k-points of the step are solved together (lanczos_lowest_batched: one
-    # stream per k-point, so their latency-bound small kernels overlap)
-    kbatch = mbks.Batch([(p, ik) for ik in range(nk)])
-
-    def solve_all(prec):
-        eigs, xs, infos, stc = kbatch.lanczos_lowest([M] * nk, prec)
-        del xs
-        return eigs, infos
-
-    golden = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_eigs.json")
-    if os.path.exists(gpath):
-        golden = json.load(open(gpath))
-
-    def errors(eigs):
-        if golden is None:
-            return None
-        errs = [float(np.max(np.abs(eigs[ik] - np.array(golden["kpoints"][str(ik)]["eps"]))))
-                for ik in range(nk) if str(ik) in golden["kpoints"]]
-        return max(errs) if errs else None
-
     head = args.prec
+    ct = torch.complex128 if head == "fp64" else torch.complex64
+    p = mbks.Problem(d, device=0)
+    dims = [p.dims(ik) for ik in range(nk)]
+    log("workload", d["name"], dims[0])
+    tuned = None
+    if not args.no_autotune:
+        tuned = [p.autotune(ik, 64, head) for ik in range(nk)]
+        log("autotune k0", tuned[0])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(14064964)
+    xs, ys = [], []
+    for ik in range(nk):
+        x = torch.randn((M, dims[ik]["nb"], dims[ik]["ld"]), dtype=ct, device=dev, generator=gen)
+        x[:, :, dims[ik]["ng"]:] = 0
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+
+    def step(prec):
+        for ik in range(nk):
+            p.hpsi(ik, xs[ik], ys[ik], prec)
+
     for _ in range(args.warmup):
-        solve_all(head)
+        step(head)
+    torch.cuda.synchronize()
+    # timed steps; the stage timer brackets every kernel launch with HIP events on the
+    # stream it is launched on (the library's stream argument = torch's current stream)
+    mbks.timer_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    applies = 0
-    infos_all = []
-    eigs = None
     for _ in range(args.steps):
-        eigs, infos = solve_all(head)
-        applies += sum(i["h_applies"] for i in infos)
-        infos_all += infos
+        step(head)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
-    ms_per_step = 1e3 * t_steps / args.steps
-    head_err = errors(eigs)
-    head_res = max(i["max_resid"] for i in infos_all)
-    log("step", head, ms_per_step, "ms; applies/step", applies / args.steps, "err", head_err)
-    # one more, untimed step with the per-kernel stage timer (HIP events on the library's stream)
-    mbks.timer_enable(True)
-    solve_all(head)
-    torch.cuda.synchronize()
     stages = mbks.timer_read()
     mbks.timer_enable(False)
+    ms_per_step = 1e3 * t_steps / args.steps
+    value = args.steps * nk * M / t_steps
+    log("headline", head, round(ms_per_step, 3), "ms/step", round(value, 1), "band-vectors/s")
+    stage_ms = {k: round(v[0] / args.steps, 3) for k, v in stages.items() if v[1]}
 
-    # plain FP64 form of the same step
-    fp64 = None
-    if head != "fp64" and args.fp64_steps > 0:
-        solve_all("fp64")
+    # BF16x3 projector contractions (same vectors)
+    bf = None
+    if head == "fp32":
+        step("bf16x3")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        a64 = 0
-        for _ in range(args.fp64_steps):
-            e64, i64 = solve_all("fp64")
-            a64 += sum(i["h_applies"] for i in i64)
+        for _ in range(max(2, args.steps // 3)):
+            step("bf16x3")
         torch.cuda.synchronize()
-        t64 = 1e3 * (time.perf_counter() - t1) / args.fp64_steps
-        fp64 = {"ms_per_step": t64, "h_applies_per_step": a64 / args.fp64_steps,
-                "max_eig_err_vs_oracle": errors(e64), "max_resid": max(i["max_resid"] for i in i64),
-                "speedup_mixed_vs_fp64": t64 / ms_per_step}
-        log("fp64 step", fp64)
+        tb = (time.perf_counter() - t1) / max(2, args.steps // 3)
+        bf = {"ms_per_step": round(1e3 * tb, 3), "band_vectors_per_s": round(nk * M / tb, 1)}
 
-    # ---- roofline of the dominant kernel ----------------------------------------
-    # The fused local-potential kernel (k_local_lines, FP64 instantiation) takes the
-    # largest share of the benchmark's kernel time.  Its launches in the pure hpsi_apply
-    # leg all have one shape (32 bands, every knot interval), so the per-launch
-    # figures are those of that leg: HIP events around each launch on the library's
-    # stream (stage timer), algorithmic flops from the operation count model.
-    def local_roofline(prec):
-        name = "local" if prec == "fp64" else "local32"
-        lms, lcount, lunits = hp[prec]["stage_raw"][name]
-        csz = 16 if prec == "fp64" else 8
-        flops_b, bytes_b, vbytes = local_model(p, 0, csz, csz)
-        achieved = flops_b * lunits / (lms * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS
-        per_launch = lunits / lcount
-        return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4),
-                "avg_launch_ms": round(lms / lcount, 5), "launches": lcount, "bands_per_launch": per_launch,
+    # roofline of the dominant kernel: the local-potential plane kernel
+    lname = "local" if head == "fp64" else "local32"
+    lms, lcount, lunits = stages[lname]
+    csz = 16 if head == "fp64" else 8
+    flops_b, bytes_b, vbytes = local_model(p, 0, csz, csz)
+    per_launch = lunits / lcount
+    avg_ms = lms / lcount
+    achieved = flops_b * per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if head == "fp64" else PEAK_FP32_TFLOPS
+    T = "double" if head == "fp64" else "float"
+    var = (tuned[0]["plane_variant"] if tuned else (1 if head == "fp64" else 0))
+    q1q2 = "8, 4" if var == 1 else "16, 8"
+    tr = traffic_record(f"k_local_plane_surface_{'fp64' if head == 'fp64' else 'fp32'}_traffic")
+    alg_bytes = bytes_b * per_launch + vbytes
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": tr["bytes_per_launch"] if tr else None,
+                "kernel": f"k_local_plane<{T}, {T}, 128, 64, {q1q2}, 512, 1> (evaluate / 2D FFT / V / "
+                          f"2D FFT / gather, one output row per Gauss plane)",
+                "avg_launch_ms": round(avg_ms, 4), "launches": lcount, "bands_per_launch": per_launch,
                 "flops_per_launch": flops_b * per_launch,
-                "algorithmic_bytes_per_launch": bytes_b * per_launch + vbytes,
-                "hbm_gbs_algorithmic": round((bytes_b * per_launch + vbytes) / (lms / lcount * 1e-3) / 1e9, 1)}
+                "flop_model": "per Gauss plane 10 N log2 N (two 2D FFTs of N = N1 N2 points) + 2 N "
+                              "(potential) + 32 N_G (evaluate, gather)",
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "hbm_gbs_algorithmic": round(alg_bytes / (avg_ms * 1e-3) / 1e9, 1)}
+    if tr:
+        roofline["traffic_over_algorithmic"] = round(tr["bytes_per_launch"] / alg_bytes, 3)
+    del xs, ys
+    torch.cuda.empty_cache()
+    p.close()
 
-    roofline = local_roofline("fp64")
-    tr = traffic_record(f"k_local_lines_{args.workload}_traffic")
-    roofline["traffic"] = tr["bytes_per_launch"] if tr else None
-    roofline["kernel"] = "k_local_lines<double, double, 36, 36, 256, 3> (fused evaluate / FFT / V / FFT / project)"
-    roofline["fp32_instantiation"] = local_roofline("fp32")
-    tot = {k: v for k, v in stages.items() if v[1]}
-    roofline["step_stage_ms"] = {k: round(v[0], 3) for k, v in tot.items()}
-
+    surf = {"workload": d["name"], "stages_ms_per_step": stage_ms, "bf16x3": bf,
+            "autotune_k0": tuned[0] if tuned else None}
+    if not args.no_eigen:
+        surf.update(surface_fp64_and_eigen_leg(torch, mbks, workloads, d, args.full_eig))
+    graphene = None if args.no_graphene else graphene_leg(torch, mbks, workloads)
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
     c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
-    surf = None if args.no_surface else surface_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(desc)
+            cpu = cpu_baseline(d)
         except Exception as exc:  # report, do not fail the benchmark line
             cpu = {"value": None, "unit": "band-vectors/s", "cores": None, "kind": "oracle",
                    "sample": f"failed: {exc}"}
 
-    value = applies / t_steps
     out = {
         "metric": "Hψ band-vectors/s + time to N eigenpairs at 1e-6 Ha: mixed/batched vs FP64",
         "value": round(value, 1),
@@ -482,31 +497,23 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 2),
+        "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head == "fp32" else "f64",
+        "dtype": "f64" if head == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": desc["name"], "kpoints": nk, "bands": M, "n_per_k": dims[0]["ng"] * dims[0]["nb"],
-                   "grid": desc["grid"], "splines": dims[0]["nb"], "projectors": dims[0]["np"],
-                   "tol_resid": 1e-7},
-        "time_to_eigenpairs_ms": round(ms_per_step, 2),
-        "max_eig_err_vs_oracle": head_err,
-        "max_resid": head_res,
-        "h_applies_per_step": applies / args.steps,
-        "fp64": fp64,
-        "hpsi": {k: {kk: vv for kk, vv in v.items() if kk != "stage_raw"} for k, v in hp.items()},
-        "autotune_k0": {k: v[0] for k, v in tuned.items()},
+        "config": {"workload": d["name"], "kpoints": nk, "bands": M, "band_vectors_per_step": nk * M,
+                   "n_per_k": dims[0]["ng"] * dims[0]["nb"], "grid": d["grid"], "splines": dims[0]["nb"],
+                   "gauss_planes": dims[0]["nzq"], "projectors": dims[0]["np"], "precision": head},
+        "surface": surf,
+        "graphene": graphene,
         "batched_48": batched,
         "supercell_2x2": c3,
-        "surface": surf,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    kbatch.close()
-    p.close()
     return 0
 
 
