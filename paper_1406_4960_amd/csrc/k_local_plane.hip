@@ -27,6 +27,7 @@ namespace mb {
 namespace {
 
 constexpr int KORD = 4;
+constexpr int PLANE_BG = 8;  // bands per group of the work order
 using fftl::line_fft;
 
 template <typename TI, typename T>
@@ -173,10 +174,25 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     uint32_t* rmask = reinterpret_cast<uint32_t*>(tw2 + N2);
     cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + plane_hdr<T, N1, N2>());
 
+    // Work order: groups of PLANE_BG bands walk the knot intervals together, the bands
+    // of a group side by side.  Consecutive logical workgroups share an XCD, so the
+    // workgroups resident on one XCD cover a few bands x a few neighbouring intervals:
+    // the coefficient rows of a band (used by the kappa intervals around them) and the
+    // potential planes of an interval (used by every band of the group) stay in its L2.
     const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
-    const int b = (int)(L % (unsigned)a.nbands);
-    const int s = (int)(L / (unsigned)a.nbands);
-    if (s >= a.nint) return;
+    const unsigned full = (unsigned)(a.nbands / PLANE_BG) * PLANE_BG;
+    const unsigned span = (unsigned)PLANE_BG * (unsigned)a.nint;
+    int b, s;
+    if (L < full * (unsigned)a.nint) {
+        const unsigned r = L % span;
+        b = (int)((L / span) * PLANE_BG + r % PLANE_BG);
+        s = (int)(r / PLANE_BG);
+    } else {
+        const unsigned rb = (unsigned)a.nbands - full, r = L - full * (unsigned)a.nint;
+        b = (int)(full + r % rb);
+        s = (int)(r / rb);
+    }
+    if (s >= a.nint || b >= a.nbands) return;
     const int tid = threadIdx.x;
     for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
     for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
