@@ -52,9 +52,10 @@ __device__ __forceinline__ int bitrev_lane(int l) {
     return r;
 }
 
-// Lane exchange v <- v of lane (l xor M) with DPP moves (VALU, no LDS traffic):
-// xor 1 and 2 are quad permutations, xor 8 the half-row rotation of a 16-lane row,
-// xor 4 a half-row mirror (l -> l xor 7) followed by a quad reversal (xor 3).
+// Lane exchange v <- v of physical lane (p xor M) with DPP moves (VALU, no LDS
+// traffic): xor 1 and 2 are quad permutations, xor 8 the half-row rotation of a
+// 16-lane row, xor 4 two masked row shifts (lanes 0-3 and 8-11 of a row take
+// p + 4, lanes 4-7 and 12-15 take p - 4).
 template <int M>
 __device__ __forceinline__ int lane_xor_i32(int v) {
     if constexpr (M == 1) {
@@ -62,14 +63,36 @@ __device__ __forceinline__ int lane_xor_i32(int v) {
     } else if constexpr (M == 2) {
         return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
     } else if constexpr (M == 4) {
-        const int t = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
-        return __builtin_amdgcn_update_dpp(0, t, 0x1B, 0xF, 0xF, true);          // quad_perm [3,2,1,0]
+        const int t = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);  // row_shl:4, banks 0, 2
+        return __builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false);         // row_shr:4, banks 1, 3
     } else if constexpr (M == 8) {
         return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true);  // row_ror:8
     } else {
         return __shfl_xor(v, M);
     }
 }
+
+// Lanes of a line of Q <= 16 points within a 16-lane row: logical lane bits 0, 1, 2,
+// 3 sit on physical bits 0, 1, 3, 2, so lines of up to 8 lanes exchange only through
+// single DPP moves (xor 1, 2, 8).
+template <int Q>
+struct LaneMap {
+    static_assert(Q == 2 || Q == 4 || Q == 8 || Q == 16, "lanes per line");
+    // logical lane of physical position p (0..15) in its line
+    __device__ static int lane(int p) {
+        if constexpr (Q <= 4) return p & (Q - 1);
+        else if constexpr (Q == 8) return (p & 3) | (((p >> 3) & 1) << 2);
+        else return (p & 3) | (((p >> 3) & 1) << 2) | (((p >> 2) & 1) << 3);
+    }
+    // line of physical position p within its 16-lane row
+    __device__ static int line(int p) {
+        if constexpr (Q <= 4) return p / Q;
+        else if constexpr (Q == 8) return (p >> 2) & 1;
+        else return 0;
+    }
+    // physical xor mask of logical mask m
+    static constexpr int phys(int m) { return m == 4 ? 8 : m == 8 ? 4 : m; }
+};
 
 template <int M>
 __device__ __forceinline__ float lane_xor(float v) {
@@ -84,9 +107,11 @@ __device__ __forceinline__ double lane_xor(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <int M, typename T>
+// exchange with the lane of logical index (l xor M) of the same line
+template <int M, int Q, typename T>
 __device__ __forceinline__ cx<T> lane_xor_cx(cx<T> v) {
-    return mk<T>(lane_xor<M>(v.x), lane_xor<M>(v.y));
+    constexpr int P = LaneMap<Q>::phys(M);
+    return mk<T>(lane_xor<P>(v.x), lane_xor<P>(v.y));
 }
 
 // w_N^{sign e} from the table exp(+2 pi i k / N)
@@ -110,7 +135,7 @@ __device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
         const T sg = h ? (T)-1 : (T)1;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m>(x[k]);
+            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
             x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
         }
         if constexpr (QS > 2) {
@@ -136,7 +161,7 @@ __device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw) {
         }
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m>(x[k]);
+            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
             x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
         }
         dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw);
@@ -206,7 +231,8 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
 
     const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
     cx<T>* ub = a.u + (size_t)b * a.nzq * a.ld;
-    const int nrt = a.nrows * Q2;
+    // row tasks in whole 16-lane rows (a line's lanes are active or idle together)
+    const int nrt = (a.nrows * Q2 + 15) / 16 * 16;
 
     for (int jq = 0; jq < a.nq; ++jq) {
         const int q = s * a.nq + jq;
@@ -216,7 +242,9 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
 
         // rows: evaluate on the sphere row, inverse transform along j2
         for (int task = tid; task < nrt; task += NT) {
-            const int rc = task / Q2, l = task % Q2;
+            const int rc = (task >> 4) * (16 / Q2) + LaneMap<Q2>::line(task & 15);
+            const int l = LaneMap<Q2>::lane(task & 15);
+            if (rc >= a.nrows) continue;
             const int j1 = a.rows[rc];
             const int32_t* gr = a.gtab + (size_t)rc * N2;
             cx<T> x[L2];
@@ -253,7 +281,8 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
 
         // columns: inverse transform along j1, potential multiply, forward transform
         for (int task = tid; task < N2 * Q1; task += NT) {
-            const int j2 = task / Q1, l = task % Q1;
+            const int j2 = (task >> 4) * (16 / Q1) + LaneMap<Q1>::line(task & 15);
+            const int l = LaneMap<Q1>::lane(task & 15);
             const int cp = colpos<N2, Q2, PADB>(j2);
             uint32_t live = 0u;
 #pragma unroll
@@ -291,7 +320,9 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
         // back exactly the LDS elements it wrote in the row pass above, so the next
         // plane's row pass needs no barrier before it.
         for (int task = tid; task < nrt; task += NT) {
-            const int rc = task / Q2, l = task % Q2;
+            const int rc = (task >> 4) * (16 / Q2) + LaneMap<Q2>::line(task & 15);
+            const int l = LaneMap<Q2>::lane(task & 15);
+            if (rc >= a.nrows) continue;
             const int j1 = a.rows[rc];
             const int32_t* gr = a.gtab + (size_t)rc * N2;
             const cx<T>* src = grid + (size_t)j1 * P + colpos<N2, Q2, PADB>(L2 * bitrev_lane<Q2>(l));
@@ -358,6 +389,7 @@ mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, 
     // surface slab), 8 in FP32 (16 ms against 19 ms)
     const KPoint::Tune& tn = p->kp[ik].tune[sizeof(T) == 8 ? 0 : (sizeof(TI) == 8 ? 2 : 1)];
     const int var = (tn.set && tn.kind == 3) ? tn.plane_var : (sizeof(T) == 8 ? 1 : 0);
+    static_assert(64 * 16 % 16 == 0, "column tasks fill whole 16-lane rows");
     if (p->N1 == 128 && p->N2 == 64) {
         if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1>(p, ik, c, u, nbands, ld, s);
         return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
