@@ -28,6 +28,11 @@ namespace {
 
 constexpr int KORD = 4;
 constexpr int PLANE_BG = 8;  // bands per group of the work order
+// consecutive knot intervals per workgroup: 1.  With 4, each workgroup re-reads fewer
+// rows itself, but the rows resident on an XCD (8 bands x 8 chunks x 4 intervals) no
+// longer fit its L2 and the HBM fetch per 320-band launch of the surface slab rose from
+// 11.3 GB to 46.7 GB (measured)
+constexpr int PLANE_NI = 1;
 using fftl::line_fft;
 
 template <typename TI, typename T>
@@ -188,7 +193,8 @@ constexpr size_t plane_lds() {
     return plane_hdr<T, N1, N2>() + sizeof(cx<T>) * (size_t)N1 * plane_pitch<N2, Q2, PADB>();
 }
 
-// One workgroup per (band, knot interval): the interval's Gauss planes one after another.
+// One workgroup per (band, chunk of PLANE_NI knot intervals): their Gauss planes one
+// after another.
 template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB>
 __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     constexpr int L1 = N1 / Q1, L2 = N2 / Q2;
@@ -199,25 +205,28 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     uint32_t* rmask = reinterpret_cast<uint32_t*>(tw2 + N2);
     cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + plane_hdr<T, N1, N2>());
 
-    // Work order: groups of PLANE_BG bands walk the knot intervals together, the bands
-    // of a group side by side.  Consecutive logical workgroups share an XCD, so the
-    // workgroups resident on one XCD cover a few bands x a few neighbouring intervals:
-    // the coefficient rows of a band (used by the kappa intervals around them) and the
-    // potential planes of an interval (used by every band of the group) stay in its L2.
+    // Work order: a workgroup takes PLANE_NI consecutive knot intervals of one band.
+    // Groups of PLANE_BG bands walk the interval chunks together, the bands of a group
+    // side by side; consecutive logical workgroups share an XCD, so the workgroups
+    // resident on one XCD cover a few bands x neighbouring intervals: a band's
+    // coefficient rows (used by the kappa intervals around them) and an interval's
+    // potential planes (used by every band of the group) stay in its L2.
     const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int nch = (a.nint + PLANE_NI - 1) / PLANE_NI;
     const unsigned full = (unsigned)(a.nbands / PLANE_BG) * PLANE_BG;
-    const unsigned span = (unsigned)PLANE_BG * (unsigned)a.nint;
-    int b, s;
-    if (L < full * (unsigned)a.nint) {
+    const unsigned span = (unsigned)PLANE_BG * (unsigned)nch;
+    int b, ch;
+    if (L < full * (unsigned)nch) {
         const unsigned r = L % span;
         b = (int)((L / span) * PLANE_BG + r % PLANE_BG);
-        s = (int)(r / PLANE_BG);
+        ch = (int)(r / PLANE_BG);
     } else {
-        const unsigned rb = (unsigned)a.nbands - full, r = L - full * (unsigned)a.nint;
+        const unsigned rb = (unsigned)a.nbands - full, r = L - full * (unsigned)nch;
         b = (int)(full + r % rb);
-        s = (int)(r / rb);
+        ch = (int)(r / rb);
     }
-    if (s >= a.nint || b >= a.nbands) return;
+    if (ch >= nch || b >= a.nbands) return;
+    const int s_begin = ch * PLANE_NI, s_end = min(s_begin + PLANE_NI, a.nint);
     const int tid = threadIdx.x;
     for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
     for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
@@ -234,8 +243,8 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     // row tasks in whole 16-lane rows (a line's lanes are active or idle together)
     const int nrt = (a.nrows * Q2 + 15) / 16 * 16;
 
-    for (int jq = 0; jq < a.nq; ++jq) {
-        const int q = s * a.nq + jq;
+    for (int q = s_begin * a.nq; q < s_end * a.nq; ++q) {
+        const int s = q / a.nq;
         T bv[KORD];
 #pragma unroll
         for (int t = 0; t < KORD; ++t) bv[t] = a.bval[(size_t)q * KORD + t];
@@ -371,7 +380,7 @@ mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, i
     auto kern = k_local_plane<TI, T, N1, N2, Q1, Q2, NT, PADB>;
     if (lds > 65536)
         MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const unsigned units = (unsigned)nbands * (unsigned)p->nint;
+    const unsigned units = (unsigned)nbands * (unsigned)((p->nint + PLANE_NI - 1) / PLANE_NI);
     StageScope ts_(dbl ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, nbands);
     hipLaunchKernelGGL(kern, dim3(units), dim3(NT), lds, s, a);
     MB_HIP_TRY(hipGetLastError());

@@ -87,24 +87,50 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) acc[bb][h] = V{0, 0, 0, 0};
 
-    // local part: planes of the intervals s = i - 2 .. i + 1 of the tile's rows
+    // Band rows of the loads are clamped into the call's bands and columns into the
+    // row stride: lanes past N_G (padding) and bands past nbands load valid memory whose
+    // products only reach outputs that are never written (padding columns get zeros).
+    int brow[ZC_BB];
+#pragma unroll
+    for (int bb = 0; bb < ZC_BB; ++bb) brow[bb] = min(b0 + bb, a.nbands - 1);
+    const int Gl = gv ? Gm : 0;
+    // local part: planes of the intervals s = i - 2 .. i + 1 of the tile's rows, four
+    // planes per step (lane group g takes plane qk + g); the next step's operands are
+    // loaded before the current step's products are issued
     {
         const int s_lo = max(i0 - 2, 0), s_hi = min(i0 + 16, a.nint - 1);
         const int q_lo = s_lo * a.nq, q_hi = (s_hi + 1) * a.nq;
+        int q = q_lo + g;
+        int sq = q / a.nq, rq = q - sq * a.nq;  // interval and Gauss point of plane q
+        auto weight = [&](int qq, int ss) -> T {
+            if (qq >= q_hi || ia >= a.nb) return (T)0;
+            const int t = ia + 1 - ss;
+            return (t >= 0 && t < KORD) ? a.wb[(size_t)qq * KORD + t] : (T)0;
+        };
+        auto load = [&](int qq, cx<T>* v) {
+            const int qc = qq < q_hi ? qq : q_lo;
+#pragma unroll
+            for (int bb = 0; bb < ZC_BB; ++bb) v[bb] = a.u[((size_t)brow[bb] * a.nzq + qc) * a.ld + Gl];
+        };
+        cx<T> vn[ZC_BB];
+        T wn = weight(q, sq);
+        load(q, vn);
         for (int qk = q_lo; qk < q_hi; qk += 4) {
-            const int q = qk + g;
-            T w = 0;
-            if (q < q_hi && ia < a.nb) {
-                const int t = ia + 1 - q / a.nq;
-                if (t >= 0 && t < KORD) w = a.wb[(size_t)q * KORD + t];
+            cx<T> v[ZC_BB];
+#pragma unroll
+            for (int bb = 0; bb < ZC_BB; ++bb) v[bb] = vn[bb];
+            const T w = wn;
+            q += 4;
+            rq += 4;
+            while (rq >= a.nq) { rq -= a.nq; ++sq; }
+            if (qk + 4 < q_hi) {
+                wn = weight(q, sq);
+                load(q, vn);
             }
-            const int qc = q < q_hi ? q : q_lo;
 #pragma unroll
             for (int bb = 0; bb < ZC_BB; ++bb) {
-                cx<T> v = mk<T>(0, 0);
-                if (bb < nbg && gv) v = a.u[((size_t)(b0 + bb) * a.nzq + qc) * a.ld + Gm];
-                acc[bb][0] = A::step(w, v.x, acc[bb][0]);
-                acc[bb][1] = A::step(w, v.y, acc[bb][1]);
+                acc[bb][0] = A::step(w, v[bb].x, acc[bb][0]);
+                acc[bb][1] = A::step(w, v[bb].y, acc[bb][1]);
             }
         }
     }
@@ -113,18 +139,24 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
         const int ngrp = (a.np + 15) / 16;
         for (int grp = 0; grp < ngrp; ++grp) {
             if (a.gwin[2 * grp] > i0 + 15 || a.gwin[2 * grp + 1] < i0) continue;
+            T z[4];
+            cx<T> f[4], pp[4][ZC_BB];
 #pragma unroll
-            for (int pk = 0; pk < 16; pk += 4) {
-                const int p = grp * 16 + pk + g;
-                const bool pv = p < a.np;
-                const T z = (pv && ia < a.nb) ? a.Z[(size_t)p * a.nb + ia] : (T)0;
-                const cx<T> f = (pv && gv) ? a.F[(size_t)p * a.ld + Gm] : mk<T>(0, 0);
+            for (int st = 0; st < 4; ++st) {
+                const int p = grp * 16 + 4 * st + g;
+                const int pc = min(p, a.np - 1);
+                z[st] = (p < a.np && ia < a.nb) ? a.Z[(size_t)pc * a.nb + ia] : (T)0;
+                f[st] = a.F[(size_t)pc * a.ld + Gl];
+#pragma unroll
+                for (int bb = 0; bb < ZC_BB; ++bb) pp[st][bb] = a.proj[(size_t)brow[bb] * a.np + pc];
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
 #pragma unroll
                 for (int bb = 0; bb < ZC_BB; ++bb) {
-                    const cx<T> pp = (pv && bb < nbg) ? a.proj[(size_t)(b0 + bb) * a.np + p] : mk<T>(0, 0);
-                    const cx<T> v = cmul(f, pp);
-                    acc[bb][0] = A::step(z, v.x, acc[bb][0]);
-                    acc[bb][1] = A::step(z, v.y, acc[bb][1]);
+                    const cx<T> v = cmul(f[st], pp[st][bb]);
+                    acc[bb][0] = A::step(z[st], v.x, acc[bb][0]);
+                    acc[bb][1] = A::step(z[st], v.y, acc[bb][1]);
                 }
             }
         }
