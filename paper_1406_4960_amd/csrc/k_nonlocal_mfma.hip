@@ -46,20 +46,32 @@ __global__ __launch_bounds__(64) void k_nlproj_f32(const cx<TI>* c, const cx<flo
     const int m = lane % 16, g = lane / 16;
     const int p = grp * 16 + m;
     const int b = b0 + m;
+    // rows of projectors past np and bands past nbands are clamped: their products only
+    // reach padding entries of the partial sums; columns past N_G are zero (the padding
+    // of the vectors is not read)
     const cx<float>* Fp = F + (size_t)min(p, np - 1) * ld;
     const cx<TI>* cb = c + ((size_t)min(b, nbands - 1) * nb + i) * ld;
-    const bool pv = p < np, bv = b < nbands;
     v4f accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < ng; k0 += 16) {
-        // this lane group's 4 consecutive k of the 16-wide chunk
-        cx<float> fa[4], cv[4];
+    // this lane group's 4 consecutive k of a 16-wide chunk; the next chunk is loaded
+    // before the current chunk's products are issued
+    auto load = [&](int k0, cx<float>* fa, cx<float>* cv) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * g + s;
             const bool in = k < ng;
-            fa[s] = (pv && in) ? Fp[k] : mk<float>(0, 0);
-            cv[s] = (bv && in) ? ldc<TI>(cb + k) : mk<float>(0, 0);
+            const int kc = in ? k : 0;
+            const cx<float> fv = Fp[kc], v = ldc<TI>(cb + kc);
+            fa[s] = in ? fv : mk<float>(0, 0);
+            cv[s] = in ? v : mk<float>(0, 0);
         }
+    };
+    cx<float> fn[4], cn[4];
+    load(0, fn, cn);
+    for (int k0 = 0; k0 < ng; k0 += 16) {
+        cx<float> fa[4], cv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) { fa[s] = fn[s]; cv[s] = cn[s]; }
+        if (k0 + 16 < ng) load(k0 + 16, fn, cn);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             accr = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s].x, cv[s].x, accr, 0, 0, 0);
@@ -94,17 +106,25 @@ __global__ __launch_bounds__(64) void k_nlproj_f64(const cx<double>* c, const cx
     const int b = b0 + m;
     const cx<double>* Fp = F + (size_t)min(p, np - 1) * ld;
     const cx<double>* cb = c + ((size_t)min(b, nbands - 1) * nb + i) * ld;
-    const bool pv = p < np, bv = b < nbands;
     v4d accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < ng; k0 += 16) {
-        cx<double> fa[4], cv[4];
+    auto load = [&](int k0, cx<double>* fa, cx<double>* cv) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int k = k0 + 4 * g + s;
             const bool in = k < ng;
-            fa[s] = (pv && in) ? Fp[k] : mk<double>(0, 0);
-            cv[s] = (bv && in) ? cb[k] : mk<double>(0, 0);
+            const int kc = in ? k : 0;
+            const cx<double> fv = Fp[kc], v = cb[kc];
+            fa[s] = in ? fv : mk<double>(0, 0);
+            cv[s] = in ? v : mk<double>(0, 0);
         }
+    };
+    cx<double> fn[4], cn[4];
+    load(0, fn, cn);
+    for (int k0 = 0; k0 < ng; k0 += 16) {
+        cx<double> fa[4], cv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) { fa[s] = fn[s]; cv[s] = cn[s]; }
+        if (k0 + 16 < ng) load(k0 + 16, fn, cn);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             accr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].x, cv[s].x, accr, 0, 0, 0);
