@@ -14,7 +14,8 @@ H x is the same sum of matrix elements as the dense operator of
         fft2 / (N1 N2), gathered back on the G set (numpy's FFT is the
         library step; the identity is the convolution theorem of the DFT);
   nonlocal: sum_p E_p F_p(G) Z_p(i) <beta_p|x>, with <beta_p|x> =
-    sum_G conj(F_p(G)) sum_i Z_p(i) x(G, i).
+    sum_G conj(F_p(G)) sum_i Z_p(i) x(G, i);
+  ultrasoft overlap (Sec. II.B.2): S x gains sum_p q_p F_p(G) Z_p(i) <beta_p|x>.
 The lowest eigenpairs come from scipy's LOBPCG (a library routine) for the
 generalized problem H c = eps S c, with the per-G kinetic solve
 (T + sigma S)^{-1} as preconditioner, to a stated residual.
@@ -34,7 +35,7 @@ import scipy.sparse.linalg
 
 from .bspline import ZBasis
 from .lattice import gset
-from .operators import potential_on_grid, projector_factors, vtilde_grid
+from .operators import potential_on_grid, projector_augmentation, projector_factors, vtilde_grid
 
 
 class MatFree:
@@ -73,10 +74,22 @@ class MatFree:
         self.Bsp = scipy.sparse.csr_matrix(self.zb.B)
         self.WBsp = scipy.sparse.csr_matrix(self.zb.B * self.zb.wq[:, None])
         self.F, self.Z, self.E = projector_factors(desc, ik, self.zb)
+        self.Q = projector_augmentation(desc)
+        self.uspp = bool(len(self.Q)) and bool(np.any(self.Q != 0))
+
+    def _expand(self, x: np.ndarray, coef: np.ndarray) -> np.ndarray:
+        """sum_p coef_p |beta_p><beta_p|x> for x of shape (nvec, NG, Nb)."""
+        xz = x @ self.Z.T                                   # (nvec, NG, Np)
+        proj = np.einsum("pg,bgp->pb", self.F.conj(), xz)   # <beta_p|x_b>
+        fz = np.einsum("pg,pb->bgp", self.F, coef[:, None] * proj)
+        return fz @ self.Z
 
     # vectors as [nvec][G][i]
     def apply_s(self, x: np.ndarray) -> np.ndarray:
-        return x @ self.Sz
+        Sx = x @ self.Sz
+        if self.uspp:
+            Sx = Sx + self._expand(x, self.Q)
+        return Sx
 
     def _local_dense(self, psi):
         # psi (Nq, NG, nvec) -> per plane Vt(G - G') psi(G')
@@ -106,8 +119,9 @@ class MatFree:
     def apply(self, x: np.ndarray):
         """(H x, S x) for x of shape (nvec, NG, Nb)."""
         nv = x.shape[0]
-        Sx = x @ self.Sz
-        Hx = 0.5 * (x @ self.Dz) + 0.5 * self.kg2[None, :, None] * Sx
+        Sz_x = x @ self.Sz
+        Hx = 0.5 * (x @ self.Dz) + 0.5 * self.kg2[None, :, None] * Sz_x
+        Sx = Sz_x + self._expand(x, self.Q) if self.uspp else Sz_x
         if self.has_v:
             # psi(G', z_q) = sum_j B_j(z_q) x(G', j), as (Nq, NG, nvec)
             xt = np.ascontiguousarray(np.transpose(x, (2, 1, 0))).reshape(self.nb, -1)  # (Nb, NG*nvec)
@@ -116,12 +130,8 @@ class MatFree:
             out = np.asarray(self.WBsp.T @ vpsi.reshape(vpsi.shape[0], -1))  # (Nb, NG*nvec)
             Hx = Hx + np.transpose(out.reshape(self.nb, self.ng, nv), (2, 1, 0))
         if len(self.E):
-            # <beta_p|x_b> = sum_G conj(F_p(G)) sum_i Z_p(i) x_b(G, i)
-            xz = x @ self.Z.T                                   # (nvec, NG, Np)
-            proj = np.einsum("pg,bgp->pb", self.F.conj(), xz)   # (Np, nvec)
-            coef = self.E[:, None] * proj                       # (Np, nvec)
-            fz = np.einsum("pg,pb->bgp", self.F, coef)          # (nvec, NG, Np)
-            Hx = Hx + fz @ self.Z
+            # sum_p E_p |beta_p><beta_p|x>, <beta_p|x_b> = sum_G conj(F_p(G)) sum_i Z_p(i) x_b(G, i)
+            Hx = Hx + self._expand(x, self.E)
         return Hx, Sx
 
     def _linop(self, which: str):

@@ -1,4 +1,5 @@
-"""Dense matrix elements of S and H in the mixed basis (Sec. II.B.1).
+"""Dense matrix elements of S and H in the mixed basis (Sec. II.B.1), and the
+ultrasoft overlap of Sec. II.B.2.
 
 Index of a basis function (G, i): G * N_b + i (the oracle's own order).
 
@@ -232,6 +233,20 @@ def projector_factors(desc, ik: int, zb: ZBasis):
     return np.array(Fs), np.array(Zs), np.array(energies, dtype=np.float64)
 
 
+def projector_augmentation(desc) -> np.ndarray:
+    """Augmentation charge q_p of every projector, in the order of projector_factors
+    (ultrasoft overlap S = I_G (x) S_z + sum_p q_p |beta_p><beta_p|, Sec. II.B.2; the
+    paper's q_nm matrix taken diagonal, with one charge per projector channel)."""
+    qs = []
+    for at in desc["atoms"]:
+        sp = desc["species"][at["species"]]
+        if not sp.get("nonlocal", False):
+            continue
+        for kind in PROJ_NAMES:
+            qs.append(float(sp.get("q_s" if kind == "s" else "q_p", 0.0)))
+    return np.array(qs, dtype=np.float64)
+
+
 def projectors(desc, ik: int, zb: ZBasis):
     """Dense overlaps <G,i|beta_{a,p}>, shape (Np, NG, Nb), and energies (Np,)."""
     F, Z, E = projector_factors(desc, ik, zb)
@@ -262,7 +277,15 @@ class Problem:
         self.with_nonlocal = with_nonlocal
 
     def overlap(self) -> np.ndarray:
-        return np.kron(np.eye(self.ng), self.Sz).astype(np.complex128)
+        """S = I_G (x) S_z (+ sum_p q_p |beta_p><beta_p| in the ultrasoft form)."""
+        S = np.kron(np.eye(self.ng), self.Sz).astype(np.complex128)
+        q = projector_augmentation(self.desc)
+        if np.any(q != 0):
+            beta, _ = self.projectors()
+            for p in range(len(q)):
+                b = beta[p].reshape(-1)
+                S += q[p] * np.outer(b, b.conj())
+        return S
 
     def kinetic(self) -> np.ndarray:
         T = np.zeros((self.n, self.n), dtype=np.complex128)

@@ -7,6 +7,7 @@ operator of ``operators.Problem`` (Sec. II.B.1), evaluated directly:
   (T x)(G,i) = 1/2 sum_j (D_z[i,j] + |k+G|^2 S_z[i,j]) x(G,j)
   (V x)(G,i) = sum_q w_q B_i(z_q) sum_G' Vt(G - G', z_q) sum_j B_j(z_q) x(G',j)
   (N x)(G,i) = sum_p E_p F_p(G) Z_p(i) sum_{G',j} conj(F_p(G') Z_p(j)) x(G',j)
+  ultrasoft overlap: (S x)(G,i) gains the same sum with q_p in place of E_p
 
 with Vt the grid-consistent transform of the sampled potential.  The potential
 is sampled only on the z-planes that the requested rows touch (Gaussian wells
@@ -19,8 +20,8 @@ import numpy as np
 
 from .bspline import ZBasis
 from .lattice import gset
-from .operators import (gaussian_potential_on_grid_separable, potential_on_grid, projector_factors,
-                        vtilde_grid)
+from .operators import (gaussian_potential_on_grid_separable, potential_on_grid, projector_augmentation,
+                        projector_factors, vtilde_grid)
 
 
 class RowOracle:
@@ -35,6 +36,7 @@ class RowOracle:
         self.Dz = self.zb.deriv_overlap()
         self.kg2 = np.sum(self.kg * self.kg, axis=1)
         self.F, self.Z, self.E = projector_factors(desc, ik, self.zb)
+        self.Q = projector_augmentation(desc)
         self.vfunc = vfunc
         self._vt = {}
 
@@ -85,4 +87,6 @@ class RowOracle:
             if len(self.E):
                 coef = self.E * self.F[:, g] * self.Z[:, i]
                 Hx[:, r] += coef @ proj
+                if np.any(self.Q != 0):
+                    Sx[:, r] += (self.Q * self.F[:, g] * self.Z[:, i]) @ proj
         return Hx, Sx

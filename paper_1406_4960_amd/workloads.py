@@ -23,6 +23,9 @@ Conventions of the dictionary (Hartree atomic units, lengths in bohr):
   ``E_s``, ``E_p`` (projector energies, Ha) for one s and three p projectors.
 * ``atoms``: list of dicts ``{"species": s, "pos": [x, y, z]}`` (Cartesian).
 * ``nbands``: number of lowest eigenpairs wanted per k-point.
+* Optional species keys ``q_s``, ``q_p`` (ultrasoft form): augmentation charges of the
+  s and p projectors, so that the overlap gains sum_p q_p |beta_p><beta_p| (the
+  generalized problem of the ultrasoft scheme); absent or zero = norm-conserving.
 
 The seeds follow one rule: problem family index ``idx`` uses
 ``numpy.random.Generator(PCG64(14064960 + idx))``; member p of the batched
@@ -255,6 +258,27 @@ def surface() -> dict:
     }
 
 
+def with_augmentation(desc: dict, offset: int = 7, lo: float = 0.1, hi: float = 0.5) -> dict:
+    """The same description with seeded augmentation charges q_s, q_p ~ U[lo, hi] on
+    every nonlocal species (the ultrasoft overlap; positive charges keep S positive
+    definite)."""
+    rng = _rng(offset)
+    species = []
+    for sp in desc["species"]:
+        sp = dict(sp)
+        if sp.get("nonlocal", False):
+            sp["q_s"] = float(rng.uniform(lo, hi))
+            sp["q_p"] = float(rng.uniform(lo, hi))
+        species.append(sp)
+    return dict(desc, species=species, name=desc["name"] + "-uspp")
+
+
+def graphene_uspp() -> dict:
+    """The graphene-like slab in the ultrasoft form: the same cell, grid, splines,
+    atoms and projectors, plus augmentation charges q_s, q_p ~ U[0.1, 0.5]."""
+    return with_augmentation(graphene(), offset=11)
+
+
 def micro(seed: int = 7, nonlocal_: bool = True, nint: int = 7, mmax: int = 1,
           kfrac=(0.1, 0.2), natoms: int = 1, grid: int = 8) -> dict:
     """A very small cell (3x3 G box, 8 B-splines by default) for brute-force
@@ -292,6 +316,7 @@ def micro(seed: int = 7, nonlocal_: bool = True, nint: int = 7, mmax: int = 1,
 CONFIGS = {
     "tiny": tiny,
     "graphene": graphene,
+    "graphene_uspp": graphene_uspp,
     "graphene_2x2": graphene_2x2,
     "surface": surface,
 }
