@@ -8,6 +8,8 @@
  * N_b = N_int + kappa - 3 basis splines.  The discrete problem is the generalized
  * Hermitian eigenproblem H c = eps S c (Sec. II.B.2 form) with
  *   S = I_G (x) S_z                           (overlap elements, Sec. II.B.1)
+ *       + sum_p q_p |beta_p><beta_p|          (ultrasoft form, Sec. II.B.2; only when a
+ *                                              species carries augmentation charges)
  *   T = 1/2 (D_z + |k+G|^2 S_z) per G         (kinetic elements, Sec. II.B.1; Hartree)
  *   V_loc: Gaussian local potential applied through the in-plane grid
  *          (matrix elements of Sec. II.B.1 with the transform taken on the grid)
@@ -67,7 +69,12 @@ typedef enum {
 /* One species: local part sum_t gauss_A[t] exp(-r^2 / gauss_w[t]^2) (the Gaussian
  * terms of the local pseudopotential, Sec. II.B.1) and, if nonlocal != 0, one s and
  * three real Cartesian p Kleinman-Bylander projectors (eq. KBeq; Gaussian radial
- * parts exp(-alpha r^2), normalised to one) with energies E_s, E_p. */
+ * parts exp(-alpha r^2), normalised to one) with energies E_s, E_p.
+ * q_s, q_p: augmentation charges of the s and p projectors in the ultrasoft overlap
+ * S = I_G (x) S_z + sum_p q_p |beta_p><beta_p| (Sec. II.B.2, with the charge matrix
+ * q_nm of an atom taken diagonal, one charge per projector channel).  Both zero: the
+ * norm-conserving problem.  Must be finite and >= 0 (S then stays positive definite);
+ * ignored when nonlocal == 0. */
 typedef struct {
     int32_t ngauss;
     double gauss_A[MB_MAX_GAUSS];
@@ -75,6 +82,7 @@ typedef struct {
     int32_t nonlocal;
     double alpha_s, alpha_p;
     double E_s, E_p;
+    double q_s, q_p;
 } mb_species;
 
 typedef struct {
@@ -139,6 +147,9 @@ mb_status mb_problem_gvectors(const mb_problem* p, int ik, int32_t* m, double* k
 mb_status mb_problem_zrule(const mb_problem* p, double* zq, double* wq);
 mb_status mb_problem_zbands(const mb_problem* p, double* sband, double* dband);
 mb_status mb_problem_projectors(const mb_problem* p, int ik, double* F, double* Z, double* E);
+/* Augmentation charge q_p of every projector (N_p doubles, projector order of
+ * mb_problem_projectors); all zero for a norm-conserving description. */
+mb_status mb_problem_augmentation(const mb_problem* p, double* q);
 
 /* Replace the local potential by a caller-given real grid V[q][j1][j2]
  * (N_q x N1 x N2 doubles, host memory, V at rho = j1/N1 a1 + j2/N2 a2, z = z_q).
@@ -168,14 +179,20 @@ mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nban
 mb_status hpsi_apply_noalloc(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                              mb_precision prec, void* stream);
 
-/* y = S c (banded overlap, Sec. II.B.1).  c and y must not overlap. */
+/* y = S c (banded overlap, Sec. II.B.1).  With augmentation charges (ultrasoft form,
+ * Sec. II.B.2) y = S_z c + sum_p q_p |beta_p> <beta_p|c>: the projections <beta_p|c>
+ * run through the same projection kernels as hpsi_apply and the expansion is fused
+ * into the banded pass; the projections use the k-point's projection work buffers
+ * (allocated on first use like hpsi_apply's, or reserved by mb_problem_reserve).
+ * c and y must not overlap. */
 mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
 /* Reserve the H work buffers of k-point ik (local partial rows, projections, matrix-core
- * partial projections) for calls of up to max_bands vectors with row stride ld (0: the
+ * partial projections; with augmentation charges also s_solve's in-place copy of r) for
+ * calls of up to max_bands vectors with row stride ld (0: the
  * recommended ld), in any precision.  With lock != 0 they are also locked: later
- * hpsi_apply / lanczos_lowest calls on this k-point that would need larger buffers
+ * hpsi_apply / spsi_apply / s_solve / lanczos_lowest calls on this k-point that would need larger buffers
  * return MB_ERR_INVALID_ARG instead of reallocating them, and solves do not release
  * them, so their device addresses stay fixed until mb_problem_reserve is called again
  * (lock = 0 unlocks) or the problem is destroyed.  A HIP graph that captured
@@ -212,7 +229,14 @@ mb_status mb_autotune(mb_problem* p, int ik, int64_t nbands, mb_precision prec, 
                       mb_tune_info* info);
 
 /* x = S^{-1} r by forward and back substitution with the banded Cholesky factor
- * of S_z, shared by every G and band.  x may equal r (in place). */
+ * of S_z, shared by every G and band.  With augmentation charges (ultrasoft overlap
+ * S = S_0 + B Q B^H, S_0 = I_G (x) S_z, B = [beta_1 .. beta_Np], Q = diag(q_p)) the
+ * Woodbury identity gives S^{-1} = S_0^{-1} - S_0^{-1} B W B^H S_0^{-1} with
+ * W = Q (I + (B^H S_0^{-1} B) Q)^{-1}, an N_p x N_p matrix built per k-point on the
+ * host in FP64 at creation (B^H S_0^{-1} B factors into in-plane and z sums).  The
+ * call then runs: x = S_0^{-1} r, P = B^H x, P' = -W P (FP64), t = r + B P',
+ * x = S_0^{-1} t; work buffers as for spsi_apply, plus one vector block when x == r
+ * (a copy of r).  x may equal r (in place). */
 mb_status s_solve(mb_problem* p, int ik, const void* r, void* x, int64_t nbands, int64_t ld,
                   mb_precision prec, void* stream);
 
@@ -222,7 +246,9 @@ typedef struct {
     int32_t krylov_global;/* Krylov vectors of the global cycle (>= 0) */
     int32_t max_iter;     /* grand cycles (>= 1) */
     double tol;           /* converged when every ||H x - eps S x||_2 <= tol (x^H S x = 1) */
-    double sigma;         /* shift of the kinetic preconditioner (T + sigma S)^{-1}, Ha (default 0.05); <= 0: S^{-1} */
+    double sigma;         /* shift of the kinetic preconditioner (T + sigma S_0)^{-1}, Ha (default 0.05);
+                             <= 0: S_0^{-1} (S_0 = I_G (x) S_z; augmentation charges are left out of the
+                             preconditioner, not out of H, S or the Rayleigh-Ritz step) */
     double switch_tol;    /* MB_FP32/MB_BF16X3: residual at which the solve continues in FP64 */
     uint64_t seed;        /* seed of the random start when x0 is NULL */
     int32_t extra;        /* buffer vectors iterated above the nev wanted ones (not required to

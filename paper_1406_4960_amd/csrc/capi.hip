@@ -59,12 +59,14 @@ void free_all(Problem* p) {
     if (p->device < 0) return;
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
-                    p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin};
+                    p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin,
+                    p->d_Q, p->d_Qf, p->d_one, p->d_onef, p->d_iband};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& kp : p->kp) {
         void* kq[] = {kp.d_kg2, kp.d_kg2f, kp.d_gmap, kp.d_rows, kp.d_gtab, kp.d_F64, kp.d_F32, kp.d_pfac,
-                      kp.ws_part.ptr, kp.ws_proj.ptr, kp.ws_nlpart.ptr, kp.ws_lz.ptr, kp.ws_small.ptr};
+                      kp.d_W, kp.ws_part.ptr, kp.ws_proj.ptr, kp.ws_nlpart.ptr, kp.ws_aux.ptr, kp.ws_lz.ptr,
+                      kp.ws_small.ptr};
         for (void* q : kq)
             if (q) (void)hipFree(q);
     }
@@ -171,9 +173,16 @@ size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec) 
     return (size_t)nbands * rows * ld * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
 }
 
+// projections [b][p]; with augmentation charges a second block of q-scaled ones follows
 size_t hwork_proj_bytes(const Problem* p, int nbands, int prec) {
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
-    return (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+    return (p->uspp ? 2 : 1) * (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+}
+
+size_t aux_bytes(const Problem* p, int ik, int nbands, int ld, int prec) {
+    if (!p->uspp) return 0;
+    (void)ik;
+    return (size_t)nbands * p->nb * ld * (prec == 1 ? sizeof(cx<float>) : sizeof(cx<double>));
 }
 
 size_t hwork_nlpart_bytes(const Problem* p, int nbands, int prec) {
@@ -193,11 +202,21 @@ mb_status upload(Problem* p) {
     MB_TRY(upload_f32(&p->d_dbandf, p->dband));
     MB_TRY(upload_vec(&p->d_lband, p->lband));
     MB_TRY(upload_f32(&p->d_lbandf, p->lband));
+    {
+        std::vector<double> ib((size_t)p->nb * p->order, 0.0);
+        for (int i = 0; i < p->nb; ++i) ib[(size_t)i * p->order] = 1.0;
+        MB_TRY(upload_vec(&p->d_iband, ib));
+    }
     if (p->np > 0) {
         MB_TRY(upload_vec(&p->d_Z, p->Zp));
         MB_TRY(upload_f32(&p->d_Zf, p->Zp));
         MB_TRY(upload_vec(&p->d_E, p->Ep));
         MB_TRY(upload_f32(&p->d_Ef, p->Ep));
+        MB_TRY(upload_vec(&p->d_Q, p->Qp));
+        MB_TRY(upload_f32(&p->d_Qf, p->Qp));
+        const std::vector<double> ones(p->np, 1.0);
+        MB_TRY(upload_vec(&p->d_one, ones));
+        MB_TRY(upload_f32(&p->d_onef, ones));
         MB_TRY(upload_vec(&p->d_zwin, p->zwin));
         MB_TRY(upload_group_windows(p));
     }
@@ -232,6 +251,11 @@ mb_status upload(Problem* p) {
             MB_TRY(upload_vec((cx<double>**)&kp.d_F64, F));
             MB_TRY(upload_vec((cx<float>**)&kp.d_F32, Ff));
         }
+        if (!kp.W.empty()) {
+            std::vector<cx<double>> W(kp.W.size());
+            for (size_t e = 0; e < kp.W.size(); ++e) W[e] = mk<double>(kp.W[e].real(), kp.W[e].imag());
+            MB_TRY(upload_vec((cx<double>**)&kp.d_W, W));
+        }
     }
     MB_TRY(launch_vgrid(p, 0));
     MB_TRY(refresh_vt(p, 0));
@@ -250,6 +274,7 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         part = kp.ws_part.ptr;
     }
     void* proj = nullptr;
+    void* projq = nullptr;  // q-scaled projections for sy (ultrasoft overlap)
     if (p->np > 0) {
         if (ext && (!ext->proj || !ext->nlpart))
             return set_error(MB_ERR_INVALID_ARG, "apply_h: caller work buffers lack the projection buffers");
@@ -259,32 +284,39 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
             MB_TRY(ensure_hws(kp, kp.ws_proj, hwork_proj_bytes(p, nbands, prec)));
             proj = kp.ws_proj.ptr;
         }
-        // FP32 and FP64 projections go to the matrix cores once there are enough
-        // projectors to fill their 16-wide tiles (measured: with 8 or 32 projectors the
-        // vector kernel is faster, with 256 the matrix cores are 2.7x faster in FP32);
-        // BF16x3 always uses them.  MBKS_NL_KERNEL=vector / =mfma forces one path (used
-        // to cross-check them).
-        const char* sel = getenv("MBKS_NL_KERNEL");
-        bool vector_path = p->np < 64;
-        const KPoint::Tune& tn = kp.tune[lp];
-        if (tn.set && tn.nl_mfma >= 0 && lp != 0) vector_path = tn.nl_mfma == 0;
-        if (sel && std::string(sel) == "vector") vector_path = true;
-        if (sel && std::string(sel) == "mfma") vector_path = false;
-        if (prec >= 3) vector_path = false;
-        if (vector_path)
-            MB_TRY(launch_nl_project(p, ik, c, proj, nbands, ld, lp, s));
-        else
-            MB_TRY(launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s,
-                                          ext ? ext->nlpart : nullptr));
+        if (sy && p->uspp)
+            projq = (char*)proj + (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+        MB_TRY(project(p, ik, c, proj, nbands, ld, prec, s, ext ? ext->nlpart : nullptr, PROJ_E, projq));
     }
     if (local_uses_planes(p, ik, lp)) {
         MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s));
-        MB_TRY(launch_zcombine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
+        MB_TRY(launch_zcombine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, projq));
     } else {
         MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
-        MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s));
+        MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, false, projq));
     }
     return MB_OK;
+}
+
+mb_status project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int prec, hipStream_t s,
+                  void* nlpart, int scale, void* projq) {
+    if (p->np == 0 || nbands == 0) return MB_OK;
+    const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
+    // FP32 and FP64 projections go to the matrix cores once there are enough
+    // projectors to fill their 16-wide tiles (measured: with 8 or 32 projectors the
+    // vector kernel is faster, with 256 the matrix cores are 2.7x faster in FP32);
+    // BF16x3 always uses them.  MBKS_NL_KERNEL=vector / =mfma forces one path (used
+    // to cross-check them).
+    const char* sel = getenv("MBKS_NL_KERNEL");
+    bool vector_path = p->np < 64;
+    const KPoint::Tune& tn = p->kp[ik].tune[lp];
+    if (tn.set && tn.nl_mfma >= 0 && lp != 0) vector_path = tn.nl_mfma == 0;
+    if (sel && std::string(sel) == "vector") vector_path = true;
+    if (sel && std::string(sel) == "mfma") vector_path = false;
+    if (prec >= 3) vector_path = false;
+    if (vector_path) return launch_nl_project(p, ik, c, proj, nbands, ld, lp, s, scale, projq);
+    return launch_nl_project_mfma(p, ik, c, proj, nbands, ld, prec >= 3 ? 2 : lp == 0 ? 0 : 1, lp == 2, s, nlpart,
+                                  scale, projq);
 }
 
 }  // namespace mb
@@ -461,6 +493,12 @@ mb_status mb_problem_projectors(const mb_problem* h, int ik, double* F, double* 
     return MB_OK;
 }
 
+mb_status mb_problem_augmentation(const mb_problem* h, double* q) {
+    if (!h || !q) return set_error(MB_ERR_INVALID_ARG, "NULL argument");
+    std::memcpy(q, h->p.Qp.data(), h->p.Qp.size() * sizeof(double));
+    return MB_OK;
+}
+
 mb_status mb_problem_set_potential(mb_problem* h, const double* v) {
     if (!h || !v) return set_error(MB_ERR_INVALID_ARG, "NULL argument");
     auto& p = h->p;
@@ -552,6 +590,7 @@ mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t l
         mb_status st = mb::ensure_ws(kp.ws_part, part);
         if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_proj, mb::hwork_proj_bytes(p, nb, 0));
         if (st == MB_OK && p->np > 0) st = mb::ensure_ws(kp.ws_nlpart, mb::hwork_nlpart_bytes(p, nb, 0));
+        if (st == MB_OK && p->uspp) st = mb::ensure_ws(kp.ws_aux, mb::aux_bytes(p, ik, nb, (int)ld, 0));
         if (st != MB_OK) return st;
     }
     kp.locked = lock != 0;

@@ -201,9 +201,10 @@ __global__ __launch_bounds__(64) void k_nlproj_bf16x3(const cx<TI>* c, const cx<
     }
 }
 
-// proj[b][p] = E_p sum_{i in group window} partial[i][p][b] (fixed order over i)
+// proj[b][p] = E_p sum_{i in group window} partial[i][p][b] (fixed order over i), and
+// projq[b][p] = Q_p times the same sum when projq is given (ultrasoft overlap)
 __global__ void k_nlproj_reduce(const cx<float>* partial, const int32_t* gwin, const float* E, cx<float>* proj,
-                                int nbands, int np, int npad, int nbpad) {
+                                const float* Q, cx<float>* projq, int nbands, int np, int npad, int nbpad) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nbands * np) return;
     const int b = idx / np, p = idx % np;
@@ -216,11 +217,12 @@ __global__ void k_nlproj_reduce(const cx<float>* partial, const int32_t* gwin, c
         im += v.y;
     }
     proj[(size_t)b * np + p] = mk<float>(E[p] * re, E[p] * im);
+    if (projq) projq[(size_t)b * np + p] = mk<float>(Q[p] * re, Q[p] * im);
 }
 
 // FP64 form of the reduction (energies E_p in FP64)
 __global__ void k_nlproj_reduce64(const cx<double>* partial, const int32_t* gwin, const double* E, cx<double>* proj,
-                                  int nbands, int np, int npad, int nbpad) {
+                                  const double* Q, cx<double>* projq, int nbands, int np, int npad, int nbpad) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nbands * np) return;
     const int b = idx / np, p = idx % np;
@@ -233,6 +235,7 @@ __global__ void k_nlproj_reduce64(const cx<double>* partial, const int32_t* gwin
         im += v.y;
     }
     proj[(size_t)b * np + p] = mk<double>(E[p] * re, E[p] * im);
+    if (projq) projq[(size_t)b * np + p] = mk<double>(Q[p] * re, Q[p] * im);
 }
 
 }  // namespace
@@ -266,7 +269,7 @@ size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode) {
 }
 
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
-                                 bool vin64, hipStream_t s, void* nlpart) {
+                                 bool vin64, hipStream_t s, void* nlpart, int scale, void* projq) {
     if (p->np == 0) return MB_OK;
     const KPoint& kp = p->kp[ik];
     const int ngrp = (p->np + 15) / 16;
@@ -287,8 +290,9 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
                            p->d_Z, p->d_gwin, part64, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
         MB_HIP_TRY(hipGetLastError());
         const int tot = nbands * p->np;
-        hipLaunchKernelGGL(k_nlproj_reduce64, dim3((tot + 255) / 256), dim3(256), 0, s, part64, p->d_gwin, p->d_E,
-                           (cx<double>*)proj, nbands, p->np, npad, nbpad);
+        const double* sc = scale == PROJ_Q ? p->d_Q : scale == PROJ_ONE ? p->d_one : p->d_E;
+        hipLaunchKernelGGL(k_nlproj_reduce64, dim3((tot + 255) / 256), dim3(256), 0, s, part64, p->d_gwin, sc,
+                           (cx<double>*)proj, p->d_Q, (cx<double>*)projq, nbands, p->np, npad, nbpad);
         MB_HIP_TRY(hipGetLastError());
         return MB_OK;
     }
@@ -311,8 +315,9 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
     }
     MB_HIP_TRY(hipGetLastError());
     const int tot = nbands * p->np;
-    hipLaunchKernelGGL(k_nlproj_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, part, p->d_gwin, p->d_Ef,
-                       (cx<float>*)proj, nbands, p->np, npad, nbpad);
+    const float* scf = scale == PROJ_Q ? p->d_Qf : scale == PROJ_ONE ? p->d_onef : p->d_Ef;
+    hipLaunchKernelGGL(k_nlproj_reduce, dim3((tot + 255) / 256), dim3(256), 0, s, part, p->d_gwin, scf,
+                       (cx<float>*)proj, p->d_Qf, (cx<float>*)projq, nbands, p->np, npad, nbpad);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }

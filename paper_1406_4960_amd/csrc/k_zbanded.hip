@@ -5,8 +5,10 @@
 //   y(G,i) = (T c)(G,i) + sum of the local partials of row i
 //            + sum_p F_p(G) Z_p(i) E_p <beta_p|c>
 // so the kinetic term, the projection of the local potential and the
-// Kleinman-Bylander expansion leave in one pass.  s_solve and the
-// preconditioner are forward / back substitutions with banded Cholesky factors.
+// Kleinman-Bylander expansion leave in one pass; with augmentation charges the overlap
+// output gains the ultrasoft term sum_p F_p(G) Z_p(i) q_p <beta_p|c> (Sec. II.B.2) in
+// the same pass.  s_solve and the preconditioner are forward / back substitutions with
+// banded Cholesky factors.
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -31,12 +33,13 @@ struct CombineArgs {
     const cx<T>* part;    // [b][s][t][ld] (kappa rows per interval), [b][q][ld] (planes) or null
     const T* wb;          // planes: w_q B_{s-1+t}(z_q) as [q][kappa]
     const cx<T>* proj;    // [b][np] (already times E_p) or null
+    const cx<T>* projq;   // [b][np] (already times q_p) or null: ultrasoft term of sy
     const cx<T>* F;       // [np][ld]
     const T* Z;           // [np][nb]
     const int32_t* zwin;  // [np][2]
     cx<TI>* y;            // may be null
     cx<TI>* sy;           // may be null
-    const double* sband;
+    const double* sband;  // band of the sy product: S_z (or the identity: sy = c + ultrasoft term)
     const double* dband;
     const double* kg2;
     int nbands, ld, ng, nb, nint, np;
@@ -48,7 +51,8 @@ struct CombineArgs {
 // one problem described by a0, else a batch (item t owns blocks [unit_begin[t],
 // unit_begin[t+1])).  With BB > 1 every F_p(G) and Z_p(i) loaded for the projector
 // expansion serves BB bands (many projectors: the expansion dominates the pass).
-template <typename TI, typename T, int BB>
+// AUG: sy also takes the expansion of projq (ultrasoft overlap).
+template <typename TI, typename T, int BB, bool AUG>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const CombineArgs<TI, T>* items,
                                                  const int32_t* unit_begin, int nitems) {
     unsigned L = blockIdx.x;
@@ -80,12 +84,19 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
     }
     // projector expansion of the chunk's rows, sum_p F_p(G) Z_p(i) P'_p(b): each
     // F_p(G) is loaded once for all CH rows and BB bands
-    cx<T> nl[BB][CH];
+    constexpr int BQ = AUG ? BB : 1, CQ = AUG ? CH : 1;
+    cx<T> nl[BB][CH], nq[BQ][CQ];
 #pragma unroll
     for (int bb = 0; bb < BB; ++bb)
 #pragma unroll
         for (int r = 0; r < CH; ++r) nl[bb][r] = mk<T>(0, 0);
-    if (a.y && a.proj) {
+#pragma unroll
+    for (int bb = 0; bb < BQ; ++bb)
+#pragma unroll
+        for (int r = 0; r < CQ; ++r) nq[bb][r] = mk<T>(0, 0);
+    const bool doy = a.y && a.proj;
+    const bool doq = AUG && a.sy && a.projq;
+    if (doy || doq) {
         for (int p = 0; p < a.np; ++p) {
             const int lo = max(a.zwin[2 * p], i0), hi = min(a.zwin[2 * p + 1], i1 - 1);
             if (lo > hi) continue;
@@ -99,7 +110,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
             }
 #pragma unroll
             for (int bb = 0; bb < BB; ++bb) {
-                if (bb < nbg) {
+                if (bb < nbg && doy) {
                     const cx<T> fp = cmul(f, a.proj[(size_t)(b0 + bb) * a.np + p]);
 #pragma unroll
                     for (int r = 0; r < CH; ++r) {
@@ -107,6 +118,19 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
                         if (i >= lo && i <= hi) {
                             nl[bb][r].x = fma(z[r], fp.x, nl[bb][r].x);
                             nl[bb][r].y = fma(z[r], fp.y, nl[bb][r].y);
+                        }
+                    }
+                }
+                if constexpr (AUG) {
+                    if (bb < nbg && doq) {
+                        const cx<T> fq = cmul(f, a.projq[(size_t)(b0 + bb) * a.np + p]);
+#pragma unroll
+                        for (int r = 0; r < CH; ++r) {
+                            const int i = i0 + r;
+                            if (i >= lo && i <= hi) {
+                                nq[bb][r].x = fma(z[r], fq.x, nq[bb][r].x);
+                                nq[bb][r].y = fma(z[r], fq.y, nq[bb][r].y);
+                            }
                         }
                     }
                 }
@@ -181,7 +205,14 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs<TI, T> a0, const Co
                     ti += tv * (double)cv.y;
                 }
             }
-            if (a.sy) a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)sr, (TI)si);
+            if (a.sy) {
+                double qr = 0.0, qi = 0.0;
+                if constexpr (AUG) {
+                    qr = (double)nq[bb][r].x;
+                    qi = (double)nq[bb][r].y;
+                }
+                a.sy[vb + (size_t)i * a.ld + g] = mk<TI>((TI)(sr + qr), (TI)(si + qi));
+            }
             if (a.y) {
                 double yr = tr + kk * sr, yi = ti + kk * si;
                 if (a.part && a.planes) {
@@ -357,19 +388,21 @@ __global__ __launch_bounds__(64) void k_prec_apply(const cx<double>* h, const cx
 
 template <typename TI, typename T>
 CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const void* part, const void* proj,
-                                     void* y, void* sy, int nbands, int ld, bool planes = false) {
+                                     void* y, void* sy, int nbands, int ld, bool planes = false,
+                                     const void* projq = nullptr, const double* sband = nullptr) {
     const KPoint& kp = p->kp[ik];
     CombineArgs<TI, T> a;
     const bool dbl = sizeof(T) == 8;
     a.c = (const cx<TI>*)c;
     a.part = (const cx<T>*)part;
     a.proj = (const cx<T>*)proj;
+    a.projq = (const cx<T>*)projq;
     a.F = (const cx<T>*)(dbl ? kp.d_F64 : kp.d_F32);
     a.Z = (const T*)(dbl ? (const void*)p->d_Z : (const void*)p->d_Zf);
     a.zwin = p->d_zwin;
     a.y = (cx<TI>*)y;
     a.sy = (cx<TI>*)sy;
-    a.sband = p->d_sband;
+    a.sband = sband ? sband : p->d_sband;
     a.dband = p->d_dband;
     a.kg2 = kp.d_kg2;
     a.nbands = nbands;
@@ -381,7 +414,10 @@ CombineArgs<TI, T> make_combine_args(Problem* p, int ik, const void* c, const vo
     a.nq = p->nq;
     a.planes = planes ? 1 : 0;
     a.wb = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
-    if (p->np == 0) a.proj = nullptr;
+    if (p->np == 0) {
+        a.proj = nullptr;
+        a.projq = nullptr;
+    }
     return a;
 }
 
@@ -395,9 +431,11 @@ constexpr int COMBINE_BB_NP = 64;
 
 template <typename TI, typename T>
 mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
-                       void* sy, int nbands, int ld, hipStream_t s, bool planes = false) {
-    CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld, planes);
-    bool wide = y && a.proj && p->np >= COMBINE_BB_NP;
+                       void* sy, int nbands, int ld, hipStream_t s, bool planes = false, const void* projq = nullptr,
+                       const double* sband = nullptr) {
+    CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld, planes, projq, sband);
+    const bool aug = sy && a.projq;
+    bool wide = ((y && a.proj) || aug) && p->np >= COMBINE_BB_NP;
     if (wide) {
         const char* e = getenv("MBKS_COMBINE_BB");  // "1": one band per thread (cross-checks)
         if (e && e[0] == '1' && e[1] == 0) wide = false;
@@ -406,10 +444,14 @@ mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, cons
     if (nblk == 0) return MB_OK;
     if (nblk > (int64_t)1 << 24) return set_error(MB_ERR_INVALID_ARG, "block too large for the combine kernel");
     StageScope ts_(y ? MB_STAGE_COMBINE : MB_STAGE_SPSI, s, nbands);
-    if (wide)
-        hipLaunchKernelGGL((k_combine<TI, T, 4>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    if (aug && wide)
+        hipLaunchKernelGGL((k_combine<TI, T, 4, true>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    else if (aug)
+        hipLaunchKernelGGL((k_combine<TI, T, 1, true>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+    else if (wide)
+        hipLaunchKernelGGL((k_combine<TI, T, 4, false>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
     else
-        hipLaunchKernelGGL((k_combine<TI, T, 1>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
+        hipLaunchKernelGGL((k_combine<TI, T, 1, false>), dim3((unsigned)nblk), dim3(256), 0, s, a, nullptr, nullptr, 0);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -436,7 +478,7 @@ mb_status combine_batch_impl(const std::vector<BatchItem>& items, TableUploader&
     MB_HIP_TRY(hipMemcpyAsync(da, ha, args.size() * sizeof(args[0]), hipMemcpyHostToDevice, s));
     MB_HIP_TRY(hipMemcpyAsync(db, hb, begin.size() * 4, hipMemcpyHostToDevice, s));
     StageScope ts_(MB_STAGE_COMBINE, s, tot_bands);
-    hipLaunchKernelGGL((k_combine<TI, T, 1>), dim3((unsigned)units), dim3(256), 0, s, args[0],
+    hipLaunchKernelGGL((k_combine<TI, T, 1, false>), dim3((unsigned)units), dim3(256), 0, s, args[0],
                        (const CombineArgs<TI, T>*)da, (const int32_t*)db, (int)args.size());
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
@@ -446,10 +488,12 @@ mb_status combine_batch_impl(const std::vector<BatchItem>& items, TableUploader&
 
 // prec: 0 = FP64 (c128), 1 = FP32 (c64), 2 = c128 vectors with FP32 local / nonlocal parts
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj, void* y,
-                         void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes) {
-    if (prec == 0) return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
-    if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
-    return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes);
+                         void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes, const void* projq,
+                         const double* sband) {
+    if (prec == 0)
+        return combine_impl<double, double>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes, projq, sband);
+    if (prec == 1) return combine_impl<float, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes, projq, sband);
+    return combine_impl<double, float>(p, ik, c, part, proj, y, sy, nbands, ld, s, planes, projq, sband);
 }
 
 mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, TableUploader& up, hipStream_t s) {
@@ -459,12 +503,14 @@ mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, Ta
     return combine_batch_impl<double, float>(items, up, s);
 }
 
-mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec, hipStream_t s) {
+mb_status launch_spsi_banded(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
+                             hipStream_t s) {
     if (prec == 1) return combine_impl<float, float>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
     return combine_impl<double, double>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
 }
 
-mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s) {
+mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
+                               hipStream_t s) {
     const KPoint& kp = p->kp[ik];
     dim3 grid((ld + 63) / 64, nbands);
     StageScope ts_(MB_STAGE_SSOLVE, s, nbands);

@@ -4,7 +4,9 @@
 //           + sum_q w_q B_i(z_q) u_q(G)                                 local part, planes q
 //           + sum_p Z_p(i) F_p(G) P'_p                                  Kleinman-Bylander
 //   sy(G, i) = sum_j S_z[i][j] c(G, j)                                  overlap (optional)
-// (kinetic, local and nonlocal matrix elements of Sec. II.B.1; P'_p = E_p <beta_p|c>).
+//            + sum_p Z_p(i) F_p(G) q_p <beta_p|c>                       ultrasoft term
+// (kinetic, local and nonlocal matrix elements of Sec. II.B.1; P'_p = E_p <beta_p|c>;
+// the ultrasoft term of Sec. II.B.2 only with augmentation charges).
 // The last two terms are real (z) x complex (G) products C = A X with A[i][k] the
 // spline weights w_q B_i(z_q) (k = plane q) or Z_p(i) (k = projector p) and
 // X[k][G] = u_q(G) or F_p(G) P'_p, computed per 16-row x 16-column tile by
@@ -53,6 +55,7 @@ struct ZArgs {
     const cx<T>* u;        // [b][q][ld] plane rows of the local part
     const T* wb;           // [q][kappa]: w_q B_{s-1+t}(z_q)
     const cx<T>* proj;     // [b][np]: E_p <beta_p|c> (null: no projectors)
+    const cx<T>* projq;    // [b][np]: q_p <beta_p|c> (ultrasoft term of sy; AUG only)
     const cx<T>* F;        // [np][ld]
     const T* Z;            // [np][nb]
     const int32_t* gwin;   // [ngrp][2]: union z-window of each group of 16 projectors
@@ -65,8 +68,8 @@ struct ZArgs {
 };
 
 // One workgroup = 4 waves = 4 consecutive 16-column tiles of one 16-row tile, for
-// ZC_BB bands.
-template <typename TI, typename T>
+// ZC_BB bands.  AUG: sy also takes the projector expansion of projq.
+template <typename TI, typename T, bool AUG>
 __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
     using A = MfmaAcc<T>;
     using V = typename A::type;
@@ -82,10 +85,16 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
     const int ia = i0 + m;  // row of this lane's A operand
 
     V acc[ZC_BB][2];
+    constexpr int BQ = AUG ? ZC_BB : 1;
+    V accq[BQ][2];
 #pragma unroll
     for (int bb = 0; bb < ZC_BB; ++bb)
 #pragma unroll
         for (int h = 0; h < 2; ++h) acc[bb][h] = V{0, 0, 0, 0};
+#pragma unroll
+    for (int bb = 0; bb < BQ; ++bb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) accq[bb][h] = V{0, 0, 0, 0};
 
     // Band rows of the loads are clamped into the call's bands and columns into the
     // row stride: lanes past N_G (padding) and bands past nbands load valid memory whose
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
         for (int grp = 0; grp < ngrp; ++grp) {
             if (a.gwin[2 * grp] > i0 + 15 || a.gwin[2 * grp + 1] < i0) continue;
             T z[4];
-            cx<T> f[4], pp[4][ZC_BB];
+            cx<T> f[4], pp[4][ZC_BB], pq[4][BQ];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int p = grp * 16 + 4 * st + g;
@@ -149,6 +158,10 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
                 f[st] = a.F[(size_t)pc * a.ld + Gl];
 #pragma unroll
                 for (int bb = 0; bb < ZC_BB; ++bb) pp[st][bb] = a.proj[(size_t)brow[bb] * a.np + pc];
+                if constexpr (AUG) {
+#pragma unroll
+                    for (int bb = 0; bb < ZC_BB; ++bb) pq[st][bb] = a.projq[(size_t)brow[bb] * a.np + pc];
+                }
             }
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
@@ -157,6 +170,14 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
                     const cx<T> v = cmul(f[st], pp[st][bb]);
                     acc[bb][0] = A::step(z[st], v.x, acc[bb][0]);
                     acc[bb][1] = A::step(z[st], v.y, acc[bb][1]);
+                }
+                if constexpr (AUG) {
+#pragma unroll
+                    for (int bb = 0; bb < ZC_BB; ++bb) {
+                        const cx<T> v = cmul(f[st], pq[st][bb]);
+                        accq[bb][0] = A::step(z[st], v.x, accq[bb][0]);
+                        accq[bb][1] = A::step(z[st], v.y, accq[bb][1]);
+                    }
                 }
             }
         }
@@ -191,7 +212,14 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
                 tr += tv * (double)cv.x;
                 ti += tv * (double)cv.y;
             }
-            if (a.sy) a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)sr, (TI)si);
+            if (a.sy) {
+                double qr = 0.0, qi = 0.0;
+                if constexpr (AUG) {
+                    qr = (double)accq[bb][0][r];
+                    qi = (double)accq[bb][1][r];
+                }
+                a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)(sr + qr), (TI)(si + qi));
+            }
             const double yr = tr + kk * sr + (double)acc[bb][0][r];
             const double yi = ti + kk * si + (double)acc[bb][1][r];
             a.y[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)yr, (TI)yi);
@@ -201,7 +229,7 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
 
 template <typename TI, typename T>
 mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
-                        int nbands, int ld, hipStream_t s) {
+                        int nbands, int ld, hipStream_t s, const void* projq) {
     const KPoint& kp = p->kp[ik];
     constexpr bool dbl = sizeof(T) == 8;
     ZArgs<TI, T> a;
@@ -209,6 +237,8 @@ mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const 
     a.u = (const cx<T>*)u;
     a.wb = (const T*)(dbl ? (const void*)p->d_wbval : (const void*)p->d_wbvalf);
     a.proj = p->np > 0 ? (const cx<T>*)proj : nullptr;
+    a.projq = p->np > 0 && sy ? (const cx<T>*)projq : nullptr;
+    if (a.projq && !a.proj) return set_error(MB_ERR_INVALID_ARG, "zcombine: ultrasoft term without projections");
     a.F = (const cx<T>*)(dbl ? kp.d_F64 : kp.d_F32);
     a.Z = (const T*)(dbl ? (const void*)p->d_Z : (const void*)p->d_Zf);
     a.gwin = p->d_gwin;
@@ -228,7 +258,10 @@ mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const 
     if (p->np > 0 && !p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
     const dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((p->nb + 15) / 16), (unsigned)((nbands + ZC_BB - 1) / ZC_BB));
     StageScope ts_(MB_STAGE_COMBINE, s, nbands);
-    hipLaunchKernelGGL((k_zcombine<TI, T>), grid, dim3(256), 0, s, a);
+    if (a.projq)
+        hipLaunchKernelGGL((k_zcombine<TI, T, true>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_zcombine<TI, T, false>), grid, dim3(256), 0, s, a);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
@@ -238,11 +271,11 @@ mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const 
 // y = H c from the plane rows u of the local part (sy = S c if non-null); prec as
 // launch_combine
 mb_status launch_zcombine(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
-                          int nbands, int ld, int prec, hipStream_t s) {
+                          int nbands, int ld, int prec, hipStream_t s, const void* projq) {
     if (nbands == 0) return MB_OK;
-    if (prec == 0) return zcombine_impl<double, double>(p, ik, c, u, proj, y, sy, nbands, ld, s);
-    if (prec == 1) return zcombine_impl<float, float>(p, ik, c, u, proj, y, sy, nbands, ld, s);
-    return zcombine_impl<double, float>(p, ik, c, u, proj, y, sy, nbands, ld, s);
+    if (prec == 0) return zcombine_impl<double, double>(p, ik, c, u, proj, y, sy, nbands, ld, s, projq);
+    if (prec == 1) return zcombine_impl<float, float>(p, ik, c, u, proj, y, sy, nbands, ld, s, projq);
+    return zcombine_impl<double, float>(p, ik, c, u, proj, y, sy, nbands, ld, s, projq);
 }
 
 }  // namespace mb

@@ -46,7 +46,11 @@ struct KPoint {
     int32_t* d_gtab = nullptr;
     void* d_F64 = nullptr;        // np x ld complex128
     void* d_F32 = nullptr;        // np x ld complex64
-    // preconditioner factors (T + sigma S) per G, [i][d][ld] doubles, built on demand
+    // ultrasoft overlap: W = Q (I + (B^H S_0^{-1} B) Q)^{-1}, np x np complex128 row-major
+    // (empty without augmentation charges)
+    std::vector<zd> W;
+    void* d_W = nullptr;
+    // preconditioner factors (T + sigma S_0) per G, [i][d][ld] doubles, built on demand
     double* d_pfac = nullptr;
     double pfac_sigma = -1.0;
     // H work buffers (ws_part, ws_proj, ws_nlpart) sized once by mb_problem_reserve and
@@ -55,6 +59,7 @@ struct KPoint {
     Workspace ws_part;    // local-potential partial projections
     Workspace ws_proj;    // projections <beta|c>
     Workspace ws_nlpart;  // per-row partial projections of the matrix-core kernels
+    Workspace ws_aux;     // s_solve with augmentation charges in place: copy of r
     Workspace ws_lz;      // eigensolver vectors
     Workspace ws_small;   // eigensolver small matrices
     // kernel choices measured by mb_autotune, per arithmetic class of the local part
@@ -95,6 +100,8 @@ struct Problem {
     // projectors
     std::vector<double> Zp;      // np x nb
     std::vector<double> Ep;      // np
+    std::vector<double> Qp;      // np: augmentation charges of the ultrasoft overlap
+    bool uspp = false;           // some q_p != 0
     std::vector<int32_t> zwin;   // np x 2: first, last row with a non-negligible Z
     std::vector<KPoint> kp;
 
@@ -109,6 +116,9 @@ struct Problem {
     double* d_lband = nullptr; float* d_lbandf = nullptr;
     double* d_Z = nullptr;     float* d_Zf = nullptr;
     double* d_E = nullptr;     float* d_Ef = nullptr;
+    double* d_Q = nullptr;     float* d_Qf = nullptr;   // augmentation charges
+    double* d_one = nullptr;   float* d_onef = nullptr; // np ones (unscaled projections)
+    double* d_iband = nullptr;  // identity band (nb x kappa): the combine pass as y = c + expansion
     int32_t* d_zwin = nullptr;
     int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors
     double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
@@ -175,8 +185,11 @@ mb_status launch_local_split(Problem* p, int ik, const void* c, void* part, int 
                              hipStream_t s);
 mb_status launch_local_lines(Problem* p, int ik, const void* c, void* part, int nbands, int ld,
                              int prec, hipStream_t s, int budget_kb = 110);
+// scaling of the projections <beta_p|c> written by the projection kernels
+enum ProjScale { PROJ_E = 0, PROJ_Q = 1, PROJ_ONE = 2 };
+// proj[b][p] = scale_p <beta_p|c_b>; projq (optional) [b][p] = q_p <beta_p|c_b>
 mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld,
-                            int prec, hipStream_t s);
+                            int prec, hipStream_t s, int scale = PROJ_E, void* projq = nullptr);
 // plane kernel (one output row per Gauss plane); MB_ERR_INVALID_ARG = no variant for this grid
 bool plane_kernel_grid(const Problem* p);
 mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,
@@ -188,20 +201,38 @@ mb_status refresh_vt(Problem* p, hipStream_t s);
 bool local_uses_planes(const Problem* p, int ik, int lp);
 // matrix-core projections: mode 1 FP32 MFMA, mode 2 BF16x3 MFMA; vin64 = complex128 vectors
 mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int mode,
-                                 bool vin64, hipStream_t s, void* nlpart = nullptr);
+                                 bool vin64, hipStream_t s, void* nlpart = nullptr, int scale = PROJ_E,
+                                 void* projq = nullptr);
+// the projection path of apply_h (vector kernel or matrix cores, by projector count,
+// tuning and precision); prec as apply_h; nlpart: caller's matrix-core partials or null
+mb_status project(Problem* p, int ik, const void* c, void* proj, int nbands, int ld, int prec, hipStream_t s,
+                  void* nlpart, int scale = PROJ_E, void* projq = nullptr);
 // bytes of the matrix-core partial projections; mode 0 FP64, else FP32 partials
 size_t nl_mfma_part_bytes(const Problem* p, int nbands, int mode);
 // y = T c + local partials + nonlocal; sy = S c if sy != nullptr; part/proj may be null;
-// planes: part holds one row per Gauss plane (plane kernel) instead of kappa rows per interval
+// planes: part holds one row per Gauss plane (plane kernel) instead of kappa rows per interval;
+// projq: q-scaled projections, sy gains sum_p |beta_p> projq_p (ultrasoft overlap);
+// sband: band of the sy product (null: S_z)
 mb_status launch_combine(Problem* p, int ik, const void* c, const void* part, const void* proj,
-                         void* y, void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes = false);
+                         void* y, void* sy, int nbands, int ld, int prec, hipStream_t s, bool planes = false,
+                         const void* projq = nullptr, const double* sband = nullptr);
 // the combine pass of the plane layout with the z contractions on the matrix cores
 mb_status launch_zcombine(Problem* p, int ik, const void* c, const void* u, const void* proj, void* y, void* sy,
-                          int nbands, int ld, int prec, hipStream_t s);
+                          int nbands, int ld, int prec, hipStream_t s, const void* projq = nullptr);
+// y = S c and x = S^{-1} r, with the ultrasoft terms when the problem has augmentation charges
 mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
                       hipStream_t s);
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
                         hipStream_t s);
+// the banded parts alone: y = S_0 c, x = S_0^{-1} r (S_0 = I_G (x) S_z)
+mb_status launch_spsi_banded(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
+                             hipStream_t s);
+mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
+                               hipStream_t s);
+// host: per k-point Woodbury matrices of the ultrasoft overlap (after the projector tables)
+mb_status build_augmentation(Problem* p);
+// bytes of s_solve's in-place copy of r (0 without augmentation charges)
+size_t aux_bytes(const Problem* p, int ik, int nbands, int ld, int prec);
 mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s);
 // x[j] = K (h[j] - theta[j] s[j]), K = (T + sigma S)^{-1}; theta on device (nvec doubles),
 // sel: optional device index list mapping output j to input vector sel[j]

@@ -232,6 +232,7 @@ mb_status build_tables(const mb_desc* d, Problem* p) {
         if (p->species[a.species].nonlocal) p->np += 4;
     p->Zp.assign((size_t)p->np * p->nb, 0.0);
     p->Ep.assign(p->np, 0.0);
+    p->Qp.assign(p->np, 0.0);
     p->zwin.assign((size_t)p->np * 2, 0);
     {
         int pidx = 0;
@@ -241,6 +242,9 @@ mb_status build_tables(const mb_desc* d, Problem* p) {
             for (int t = 0; t < 4; ++t, ++pidx) {
                 double al = t == 0 ? sp.alpha_s : sp.alpha_p;
                 p->Ep[pidx] = t == 0 ? sp.E_s : sp.E_p;
+                p->Qp[pidx] = t == 0 ? sp.q_s : sp.q_p;
+                if (!std::isfinite(p->Qp[pidx]) || p->Qp[pidx] < 0.0)
+                    return set_error(MB_ERR_INVALID_ARG, "augmentation charges q_s, q_p must be finite and >= 0");
                 double* Zrow = &p->Zp[(size_t)pidx * p->nb];
                 for (int s = 0; s < p->nint; ++s)
                     for (int j = 0; j < p->nq; ++j) {
@@ -353,6 +357,86 @@ mb_status build_tables(const mb_desc* d, Problem* p) {
                 }
             }
         }
+    }
+    return build_augmentation(p);
+}
+
+// Ultrasoft overlap S = S_0 + B Q B^H (S_0 = I_G (x) S_z, columns of B the projectors
+// beta_p = F_p (x) Z_p, Q = diag(q_p); Sec. II.B.2).  The Woodbury identity
+//   S^{-1} = S_0^{-1} - S_0^{-1} B W B^H S_0^{-1},  W = Q (I + C Q)^{-1},  C = B^H S_0^{-1} B,
+// needs only the N_p x N_p matrix W per k-point: C[a][b] = (sum_G conj(F_a(G)) F_b(G)) *
+// (sum_i Z_a(i) (S_z^{-1} Z_b)(i)), since S_0^{-1} acts on the z factor alone.  I + C Q is
+// inverted by Gauss-Jordan elimination with partial pivoting (it is nonsingular: C is
+// positive semidefinite and Q >= 0, so C Q has no negative eigenvalue).
+mb_status build_augmentation(Problem* p) {
+    p->uspp = false;
+    for (double q : p->Qp)
+        if (q != 0.0) p->uspp = true;
+    for (auto& kp : p->kp) kp.W.clear();
+    if (!p->uspp) return MB_OK;
+    const int np = p->np, nb = p->nb, K = p->order;
+    // Z'_b = S_z^{-1} Z_b by forward and back substitution with lband[i][d] = L[i][i-d]
+    std::vector<double> Zs(p->Zp);
+    for (int b = 0; b < np; ++b) {
+        double* x = &Zs[(size_t)b * nb];
+        for (int i = 0; i < nb; ++i) {
+            double v = x[i];
+            for (int d = 1; d < K && d <= i; ++d) v -= p->lband[(size_t)i * K + d] * x[i - d];
+            x[i] = v / p->lband[(size_t)i * K];
+        }
+        for (int i = nb - 1; i >= 0; --i) {
+            double v = x[i];
+            for (int d = 1; d < K && i + d < nb; ++d) v -= p->lband[(size_t)(i + d) * K + d] * x[i + d];
+            x[i] = v / p->lband[(size_t)i * K];
+        }
+    }
+    std::vector<double> Cz((size_t)np * np, 0.0);
+    for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) {
+            double acc = 0.0;
+            for (int i = 0; i < nb; ++i) acc += p->Zp[(size_t)a * nb + i] * Zs[(size_t)b * nb + i];
+            Cz[(size_t)a * np + b] = acc;
+        }
+    std::vector<zd> A((size_t)np * np), Ai((size_t)np * np);
+    for (auto& kp : p->kp) {
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) {
+                zd cf(0.0, 0.0);
+                const zd* Fa = &kp.F[(size_t)a * kp.ld];
+                const zd* Fb = &kp.F[(size_t)b * kp.ld];
+                for (int g = 0; g < kp.ng; ++g) cf += std::conj(Fa[g]) * Fb[g];
+                A[(size_t)a * np + b] = (a == b ? zd(1.0, 0.0) : zd(0.0, 0.0)) + cf * Cz[(size_t)a * np + b] * p->Qp[b];
+                Ai[(size_t)a * np + b] = a == b ? zd(1.0, 0.0) : zd(0.0, 0.0);
+            }
+        for (int col = 0; col < np; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < np; ++r)
+                if (std::abs(A[(size_t)r * np + col]) > std::abs(A[(size_t)piv * np + col])) piv = r;
+            if (!(std::abs(A[(size_t)piv * np + col]) > 0.0))
+                return set_error(MB_ERR_NOT_SPD, "ultrasoft overlap: I + C Q is singular");
+            if (piv != col)
+                for (int j = 0; j < np; ++j) {
+                    std::swap(A[(size_t)piv * np + j], A[(size_t)col * np + j]);
+                    std::swap(Ai[(size_t)piv * np + j], Ai[(size_t)col * np + j]);
+                }
+            const zd inv = 1.0 / A[(size_t)col * np + col];
+            for (int j = 0; j < np; ++j) {
+                A[(size_t)col * np + j] *= inv;
+                Ai[(size_t)col * np + j] *= inv;
+            }
+            for (int r = 0; r < np; ++r) {
+                if (r == col) continue;
+                const zd f = A[(size_t)r * np + col];
+                if (f == zd(0.0, 0.0)) continue;
+                for (int j = 0; j < np; ++j) {
+                    A[(size_t)r * np + j] -= f * A[(size_t)col * np + j];
+                    Ai[(size_t)r * np + j] -= f * Ai[(size_t)col * np + j];
+                }
+            }
+        }
+        kp.W.assign((size_t)np * np, zd(0.0, 0.0));
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) kp.W[(size_t)a * np + b] = p->Qp[a] * Ai[(size_t)a * np + b];
     }
     return MB_OK;
 }

@@ -24,7 +24,8 @@ MB_MAX_GAUSS = 4
 
 # every symbol the C header declares
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
-           "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_set_potential",
+           "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_augmentation",
+           "mb_problem_set_potential",
            "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
            "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
@@ -39,7 +40,7 @@ class MbError(RuntimeError):
 class MbSpecies(ctypes.Structure):
     _fields_ = [("ngauss", c_int32), ("gauss_A", c_double * MB_MAX_GAUSS), ("gauss_w", c_double * MB_MAX_GAUSS),
                 ("nonlocal_", c_int32), ("alpha_s", c_double), ("alpha_p", c_double), ("E_s", c_double),
-                ("E_p", c_double)]
+                ("E_p", c_double), ("q_s", c_double), ("q_p", c_double)]
 
 
 class MbAtom(ctypes.Structure):
@@ -204,6 +205,8 @@ class Problem:
                 sp_arr[n].alpha_p = sp["alpha_p"]
                 sp_arr[n].E_s = sp["E_s"]
                 sp_arr[n].E_p = sp["E_p"]
+                sp_arr[n].q_s = sp.get("q_s", 0.0)
+                sp_arr[n].q_p = sp.get("q_p", 0.0)
         at_arr = (MbAtom * max(1, len(desc["atoms"])))()
         for n, at in enumerate(desc["atoms"]):
             at_arr[n].species = at["species"]
@@ -290,6 +293,12 @@ class Problem:
         _check(load().mb_problem_projectors(self.h, ik, c_void_p(F.ctypes.data), c_void_p(Z.ctypes.data),
                                             c_void_p(E.ctypes.data)))
         return F, Z, E
+
+    def augmentation(self):
+        """Augmentation charge q_p of every projector (zeros: norm-conserving)."""
+        q = np.zeros(self.dims(0)["np"])
+        _check(load().mb_problem_augmentation(self.h, c_void_p(q.ctypes.data)))
+        return q
 
     def set_potential(self, v: np.ndarray):
         v = np.ascontiguousarray(v, dtype=np.float64)

@@ -1,6 +1,7 @@
 """Write stored oracle eigenvalues for the full-size parity tests.
 
     python tests/golden/make_golden.py graphene       # -> tests/golden/graphene_eigs.json
+    python tests/golden/make_golden.py graphene_uspp  # the same slab with augmentation charges
     python tests/golden/make_golden.py graphene_2x2   # 2x2 supercell, k-point 0, 64 lowest
     python tests/golden/make_golden.py surface        # 128x64 surface slab, k-point 0, 32 lowest
     python tests/golden/make_golden.py member12       # batch member 12 (60x60 grid), every k-point
@@ -27,6 +28,7 @@ from paper_1406_4960_amd import workloads  # noqa: E402
 # name -> (description maker, k-points (None = all), eigenvalues per k-point (None = nbands), local mode)
 SETS = {
     "graphene": (workloads.graphene, None, None, "dense"),
+    "graphene_uspp": (workloads.graphene_uspp, None, None, "dense"),
     "graphene_2x2": (workloads.graphene_2x2, [0], 64, "fft"),
     "surface": (workloads.surface, [0], 32, "fft"),
     "member12": (lambda: workloads.batched_member(12), None, None, "fft"),

@@ -3,7 +3,8 @@
 oracle's matrix-free FP64 operator and a library eigensolver only).
 
 These are the lowest roots of H c = eps S c (Sec. II.C) at sizes the dense
-oracle cannot diagonalise: the 2x2 supercell (k-point 0, 64 lowest), the 128x64
+oracle cannot diagonalise: the graphene-like slab with augmentation charges (the
+ultrasoft overlap of Sec. II.B.2; every k-point, 32 lowest), the 2x2 supercell (k-point 0, 64 lowest), the 128x64
 surface slab (k-point 0, 32 lowest) and two members of the 48-problem uneven
 batch (every k-point, all their bands).  Bars: FP64 form within 1e-8 Ha, mixed
 forms within 1e-6 Ha, residual ||H x - eps S x||_2 < 1e-6 with x^H S x = 1
@@ -42,7 +43,8 @@ def _residuals(p, ik, x, eig):
     return np.max(np.abs(gram - np.eye(n))), res
 
 
-@pytest.mark.parametrize("cfg,prec,tol", [("graphene_2x2", "fp64", 1e-8), ("graphene_2x2", "fp32", 1e-6),
+@pytest.mark.parametrize("cfg,prec,tol", [("graphene_uspp", "fp64", 1e-8), ("graphene_uspp", "fp32", 1e-6),
+                                          ("graphene_2x2", "fp64", 1e-8), ("graphene_2x2", "fp32", 1e-6),
                                           ("graphene_2x2", "bf16x3", 1e-6), ("surface", "fp64", 1e-8),
                                           ("surface", "fp32", 1e-6)])
 def test_lowest_eigenvalues_match_stored_oracle(cfg, prec, tol):

@@ -80,6 +80,25 @@ def test_invalid_descriptions_rejected():
         mbks.Problem(dict(d, nq=0), device=None)
 
 
+def test_augmentation_charges_reach_the_library():
+    # ultrasoft overlap (Sec. II.B.2): the charges of the seeded description, per
+    # projector in the library's projector order, equal the oracle's; a description
+    # without charges gives zeros; negative or non-finite charges are refused
+    d = workloads.graphene_uspp()
+    p = mbks.Problem(d, device=None)
+    assert np.array_equal(p.augmentation(), operators.projector_augmentation(d))
+    assert np.all(p.augmentation() > 0)
+    p.close()
+    p = mbks.Problem(workloads.graphene(), device=None)
+    assert np.all(p.augmentation() == 0)
+    p.close()
+    for bad in (-0.1, float("nan")):
+        sp = dict(d["species"][0], q_p=bad)
+        with pytest.raises(mbks.MbError) as e:
+            mbks.Problem(dict(d, species=[sp]), device=None)
+        assert e.value.status == -1
+
+
 def test_gpu_calls_on_host_only_handle_fail():
     p = mbks.Problem(workloads.tiny(), device=None)
     lib = mbks.load()
