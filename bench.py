@@ -267,6 +267,64 @@ def graphene_leg(torch, mbks, workloads, steps=2):
     return res
 
 
+def uspp_leg(torch, mbks, workloads, steps=2):
+    """The graphene-like slab with augmentation charges (ultrasoft overlap): spsi_apply
+    and s_solve per call of 32 bands (FP64; the norm-conserving banded S beside it),
+    and the time to all 4 x 32 eigenpairs, mixed vs FP64, with errors against the
+    stored oracle eigenvalues."""
+    d = workloads.graphene_uspp()
+    p = mbks.Problem(d, device=0)
+    p_nc = mbks.Problem(workloads.graphene(), device=0)
+    nk, M = len(d["kpts"]), d["nbands"]
+    res = {"workload": d["name"], "kpoints": nk, "bands": M}
+    dm = p.dims(0)
+    xt = torch.zeros((M, dm["nb"], dm["ld"]), dtype=torch.complex128, device="cuda:0")
+    xt[:, :, :dm["ng"]] = torch.from_numpy(workloads.random_block(7, M, dm["nb"], dm["ng"])).to("cuda:0")
+    yt = torch.empty_like(xt)
+    for name, fn in (("spsi_fp64", lambda: p.spsi(0, xt, yt)), ("s_solve_fp64", lambda: p.s_solve(0, xt, yt)),
+                     ("spsi_fp64_norm_conserving", lambda: p_nc.spsi(0, xt, yt)),
+                     ("s_solve_fp64_norm_conserving", lambda: p_nc.s_solve(0, xt, yt))):
+        fn()
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"band_vectors_per_s": round(M / (ms * 1e-3), 1), "ms_per_call": round(ms, 4)}
+    del xt, yt
+    p_nc.close()
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "graphene_uspp_eigs.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath))
+    kb = mbks.Batch([(p, ik) for ik in range(nk)])
+    kb.lanczos_lowest([M] * nk, "fp32")  # workspaces, factors
+    for prec in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            eigs, xs, infos, st = kb.lanczos_lowest([M] * nk, prec)
+            del xs
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        err = None
+        if golden:
+            err = max(float(np.max(np.abs(eigs[ik] - np.array(golden["kpoints"][str(ik)]["eps"]))))
+                      for ik in range(nk) if str(ik) in golden["kpoints"])
+        res[prec] = {"ms_to_eigenpairs": round(ms, 2), "max_eig_err_vs_oracle": err,
+                     "max_resid": max(i["max_resid"] for i in infos),
+                     "h_applies": sum(i["h_applies"] for i in infos)}
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms_to_eigenpairs"] / res["fp32"]["ms_to_eigenpairs"], 3)
+    log("uspp", res)
+    kb.close()
+    p.close()
+    return res
+
+
 def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
     """FP64 hpsi_apply on k-point 0 (320 vectors), and the time to the 320 lowest
     eigenpairs of k-point 0 (the share of one GPU in a k-point split over 8) in the
@@ -366,6 +424,8 @@ def main(argv=None):
     ap.add_argument("--no-graphene", action="store_true", help="skip the graphene-like slab leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
+    ap.add_argument("--no-uspp", action="store_true",
+                    help="skip the graphene-like slab with augmentation charges (ultrasoft overlap)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
                     help="problems of the uneven batch whose eigenpairs are timed (all their k-points)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -481,6 +541,7 @@ def main(argv=None):
     graphene = None if args.no_graphene else graphene_leg(torch, mbks, workloads)
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
     c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
+    uspp = None if args.no_uspp else uspp_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -510,6 +571,7 @@ def main(argv=None):
         "graphene": graphene,
         "batched_48": batched,
         "supercell_2x2": c3,
+        "ultrasoft_graphene": uspp,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
