@@ -325,6 +325,46 @@ def uspp_leg(torch, mbks, workloads, steps=2):
     return res
 
 
+def density_leg(torch, mbks, workloads, d, reps=3):
+    """Electron density of 320 band-vectors (k-point 0 of the surface slab, FP64 vectors,
+    weight 2/8 each) at all 1,146 Gauss planes, and the Hartree potential of that density
+    in the (z, g) form."""
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    M = d["nbands"]
+    N1, N2 = d["grid"]
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(14064966)
+    x = torch.randn((M, dm["nb"], dm["ld"]), dtype=torch.complex128, device="cuda:0", generator=gen)
+    x[:, :, dm["ng"]:] = 0
+    w = torch.full((M,), 2.0 / len(d["kpts"]), dtype=torch.float64, device="cuda:0")
+    rho = torch.zeros((dm["nzq"], N1, N2), dtype=torch.float64, device="cuda:0")
+    vh = torch.empty_like(rho)
+    p.density(0, x, w, rho)
+    p.hartree(rho, vh)
+    torch.cuda.synchronize()
+    res = {"workload": d["name"], "bands": M, "planes": dm["nzq"], "grid": [N1, N2]}
+    for name, fn in (("density_fp64", lambda: p.density(0, x, w, rho)), ("hartree", lambda: p.hartree(rho, vh))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = {"ms_per_call": round(e0.elapsed_time(e1) / reps, 3)}
+    res["density_fp64"]["band_vectors_per_s"] = round(M / (res["density_fp64"]["ms_per_call"] * 1e-3), 1)
+    # flop model of the density kernel per band and plane: one inverse 2D FFT (5 N log2 N),
+    # evaluate (8 N_G), |psi|^2 accumulate (3 N)
+    n = N1 * N2
+    fl = dm["nzq"] * (5 * n * np.log2(n) + 8 * dm["ng"] + 3 * n) * M
+    res["density_fp64"]["tflops"] = round(float(fl) / (res["density_fp64"]["ms_per_call"] * 1e-3) / 1e12, 2)
+    log("density", res)
+    del x, rho, vh
+    torch.cuda.empty_cache()
+    p.close()
+    return res
+
+
 def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
     """FP64 hpsi_apply on k-point 0 (320 vectors), and the time to the 320 lowest
     eigenpairs of k-point 0 (the share of one GPU in a k-point split over 8) in the
@@ -424,6 +464,7 @@ def main(argv=None):
     ap.add_argument("--no-graphene", action="store_true", help="skip the graphene-like slab leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
+    ap.add_argument("--no-density", action="store_true", help="skip the density / Hartree leg")
     ap.add_argument("--no-uspp", action="store_true",
                     help="skip the graphene-like slab with augmentation charges (ultrasoft overlap)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
@@ -542,6 +583,7 @@ def main(argv=None):
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
     c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
     uspp = None if args.no_uspp else uspp_leg(torch, mbks, workloads)
+    dens = None if args.no_density else density_leg(torch, mbks, workloads, d)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -572,6 +614,7 @@ def main(argv=None):
         "batched_48": batched,
         "supercell_2x2": c3,
         "ultrasoft_graphene": uspp,
+        "density_hartree": dens,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

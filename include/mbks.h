@@ -188,6 +188,37 @@ mb_status hpsi_apply_noalloc(mb_problem* p, int ik, const void* c, void* y, int6
 mb_status spsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
+/* Electron density of nbands vectors of k-point ik at the Gauss planes (the charge
+ * density of Sec. II.B.1, rho_e = sum of |phi|^2 over occupied states):
+ *   rho[q][j1][j2] += sum_b w[b] |phi_b(rho_j, z_q)|^2,
+ *   phi_b(rho, z) = A^{-1/2} sum_{G,i} c_b(G, i) e^{i(k+G).rho} B_i(z),
+ *   rho_j = (j1/N1) a1 + (j2/N2) a2.
+ * rho: device, N_q x N1 x N2 doubles, accumulated into (zero it first; sum k-points and
+ * band blocks over several calls on one stream).  w: device, nbands doubles (occupation
+ * times k-point weight).  c: as hpsi_apply (complex128 for MB_FP64, complex64 otherwise);
+ * the transforms and sums run in FP64 in every precision.  One workgroup per Gauss plane
+ * sums the bands in a fixed order (deterministic, no atomics); the plane must fit in LDS
+ * (N1 (N2 + 1) complex doubles <= ~158 KB) and N1 N2 <= 16 x the plane kernel's threads.
+ * rho must not overlap c. */
+mb_status density_accumulate(mb_problem* p, int ik, const void* c, int64_t nbands, int64_t ld, const double* w,
+                             double* rho, mb_precision prec, void* stream);
+
+/* Hartree (Coulomb) potential of a charge density given on the grid at every Gauss plane,
+ * in the (z, g) form of Sec. II.B.1 (eq. Coul, from the 2D transform of 1/r):
+ *   rho(z_q, g) = 1/(N1 N2) sum_j rho[q][j] e^{i g.rho_j},
+ *   V(z_q, g)   = sum_q' w_q' rho(z_q', g) (2 pi/|g|) e^{-|g| |z_q - z_q'|}   (g != 0),
+ *   V(z_q, 0)   = -2 pi sum_q' w_q' rho(z_q', 0) |z_q - z_q'|   (the finite part; the
+ *                 divergent constant multiplies the cell's net charge, zero if neutral),
+ *   vh[q][j]    = sum_g V(z_q, g) e^{-i g.rho_j}   (real).
+ * The z integral is the Gauss rule of the knot intervals; each grid frequency is taken at
+ * its shortest alias |(m1 + n1 N1) b1 + (m2 + n2 N2) b2|, n in {-1,0,1}^2, which keeps
+ * the potential real.  The z sums run as recursions over the ordered Gauss points, O(N_q)
+ * per frequency.  rho, vh: device, N_q x N1 x N2 doubles (vh may equal rho).  vzg: NULL or
+ * device N_q x N1 x N2 complex128 receiving V(z_q, g) by grid frequency (j1, j2).  Work
+ * planes (N_q x N1 x N2 complex128, twice without vzg) are allocated on first use and kept
+ * by the problem; the call then enqueues kernels only.  FP64. */
+mb_status hartree_potential(mb_problem* p, const double* rho, double* vh, void* vzg, void* stream);
+
 /* Reserve the H work buffers of k-point ik (local partial rows, projections, matrix-core
  * partial projections; with augmentation charges also s_solve's in-place copy of r) for
  * calls of up to max_bands vectors with row stride ld (0: the
@@ -351,7 +382,7 @@ mb_status mb_small_geneig(const double* H, const double* S, int N, int nz, doubl
  * number of launches.  Stages: MB_STAGE_LOCAL (fused evaluate / FFT / V / FFT /
  * project, FP64 arithmetic), MB_STAGE_NL_PROJECT, MB_STAGE_COMBINE, MB_STAGE_SPSI, MB_STAGE_SSOLVE,
  * MB_STAGE_PRECOND, MB_STAGE_GRAM, MB_STAGE_COMBO, MB_STAGE_SMALLEIG, MB_STAGE_OTHER,
- * MB_STAGE_LOCAL32.
+ * MB_STAGE_LOCAL32, MB_STAGE_DENSITY, MB_STAGE_HARTREE.
  * Not thread safe; enable only in single-threaded measurement code. */
 #define MB_STAGE_LOCAL 0
 #define MB_STAGE_NL_PROJECT 1
@@ -364,7 +395,9 @@ mb_status mb_small_geneig(const double* H, const double* S, int N, int nz, doubl
 #define MB_STAGE_SMALLEIG 8
 #define MB_STAGE_OTHER 9
 #define MB_STAGE_LOCAL32 10  /* the local-potential kernel with FP32 arithmetic */
-#define MB_NSTAGE 11
+#define MB_STAGE_DENSITY 11
+#define MB_STAGE_HARTREE 12
+#define MB_NSTAGE 13
 mb_status mb_timer_enable(int on);
 /* total_ms: summed kernel time; count: launches; units (may be NULL): summed band
  * count of the launches (vectors processed) */

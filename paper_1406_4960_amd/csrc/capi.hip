@@ -60,7 +60,8 @@ void free_all(Problem* p) {
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
                     p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin,
-                    p->d_Q, p->d_Qf, p->d_one, p->d_onef, p->d_iband};
+                    p->d_Q, p->d_Qf, p->d_one, p->d_onef, p->d_iband, p->d_zq, p->d_wq, p->d_gnorm,
+                    p->ws_hartree.ptr};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto& kp : p->kp) {
@@ -747,6 +748,38 @@ mb_status s_solve(mb_problem* h, int ik, const void* r, void* x, int64_t nbands,
         return set_error(MB_ERR_INVALID_ARG, "s_solve: r and x partially overlap");
     if (nbands == 0) return MB_OK;
     return mb::launch_ssolve(&h->p, ik, r, x, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
+}
+
+mb_status density_accumulate(mb_problem* h, int ik, const void* c, int64_t nbands, int64_t ld, const double* w,
+                             double* rho, mb_precision prec, void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, c, rho, nbands, ld, "density_accumulate");
+    if (st != MB_OK) return st;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "density_accumulate: unknown precision");
+    if (nbands > 0 && !w) return set_error(MB_ERR_INVALID_ARG, "density_accumulate: NULL weights");
+    const mb::Problem& p = h->p;
+    const size_t vbytes = (size_t)nbands * p.nb * ld * (prec == MB_FP64 ? 16 : 8);
+    const size_t rbytes = (size_t)p.nzq * p.N1 * p.N2 * sizeof(double);
+    if (nbands > 0 && mb::ranges_overlap(c, vbytes, rho, rbytes))
+        return set_error(MB_ERR_INVALID_ARG, "density_accumulate: c and rho overlap");
+    if (nbands == 0) return MB_OK;
+    return mb::launch_density(&h->p, ik, c, (int)nbands, (int)ld, w, rho, prec == MB_FP64 ? 0 : 1,
+                              (hipStream_t)stream);
+}
+
+mb_status hartree_potential(mb_problem* h, const double* rho, double* vh, void* vzg, void* stream) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "hartree_potential: problem is NULL");
+    mb::Problem& p = h->p;
+    if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, "hartree_potential: host-only problem");
+    if (!rho || !vh) return set_error(MB_ERR_INVALID_ARG, "hartree_potential: NULL density or potential");
+    const size_t rbytes = (size_t)p.nzq * p.N1 * p.N2 * sizeof(double);
+    if (vzg && (mb::ranges_overlap(vzg, 2 * rbytes, rho, rbytes) || mb::ranges_overlap(vzg, 2 * rbytes, vh, rbytes)))
+        return set_error(MB_ERR_INVALID_ARG, "hartree_potential: vzg overlaps the density or the potential");
+    if (rho != vh && mb::ranges_overlap(rho, rbytes, vh, rbytes))
+        return set_error(MB_ERR_INVALID_ARG, "hartree_potential: rho and vh partially overlap");
+    mb_status st = mb::ensure_ws(p.ws_hartree, mb::hartree_work_bytes(&p, vzg != nullptr));
+    if (st != MB_OK) return st;
+    return mb::launch_hartree(&p, rho, vh, vzg, p.ws_hartree.ptr, (hipStream_t)stream);
 }
 
 }  // extern "C"

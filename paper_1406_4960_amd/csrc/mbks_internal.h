@@ -125,6 +125,10 @@ struct Problem {
     double* d_Vt = nullptr;    float* d_Vtf = nullptr;  // nzq x N2 x N1 (plane kernel grids only)
     void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)
     void* d_tw2 = nullptr; void* d_tw2f = nullptr;
+    // Hartree step: z_q, w_q, shortest-alias |g| per grid frequency (first use), and its
+    // work planes rho(z_q, g) (+ V(z_q, g) when the caller does not take them)
+    double* d_zq = nullptr; double* d_wq = nullptr; double* d_gnorm = nullptr;
+    Workspace ws_hartree;
 
 };
 
@@ -229,6 +233,12 @@ mb_status launch_spsi_banded(Problem* p, int ik, const void* c, void* y, int nba
                              hipStream_t s);
 mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
                                hipStream_t s);
+// electron density at the Gauss planes (accumulated into rho) and the Hartree potential
+// of a density in the (z, g) form; prec 0 complex128 vectors, else complex64
+mb_status launch_density(Problem* p, int ik, const void* c, int nbands, int ld, const double* w, double* rho,
+                         int prec, hipStream_t s);
+size_t hartree_work_bytes(const Problem* p, bool with_vzg);
+mb_status launch_hartree(Problem* p, const double* rho, double* vh, void* vzg, void* work, hipStream_t s);
 // host: per k-point Woodbury matrices of the ultrasoft overlap (after the projector tables)
 mb_status build_augmentation(Problem* p);
 // bytes of s_solve's in-place copy of r (0 without augmentation charges)

@@ -27,7 +27,7 @@ EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dim
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_augmentation",
            "mb_problem_set_potential",
            "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
-           "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
+           "density_accumulate", "hartree_potential", "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
@@ -147,7 +147,7 @@ def _ptr(t):
 
 
 STAGES = ("local", "nl_project", "combine", "spsi", "ssolve", "precond", "gram", "combo", "smalleig", "other",
-          "local32")
+          "local32", "density", "hartree")
 
 
 def timer_enable(on: bool = True):
@@ -324,6 +324,18 @@ class Problem:
     def s_solve(self, ik, r, x, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, r, x, prec)
         _check(load().s_solve(self.h, ik, _ptr(r), _ptr(x), nbands, ld, _prec(prec), _stream(stream)))
+
+    def density(self, ik, c, w, rho, prec="fp64", stream=None):
+        """rho += sum_b w[b] |phi_b|^2 at the Gauss planes: c [nbands][N_b][ld] (device),
+        w [nbands] float64 (device), rho [N_q][N1][N2] float64 (device)."""
+        nbands, nb, ld = c.shape
+        _check(load().density_accumulate(self.h, ik, _ptr(c), ctypes.c_int64(nbands), ctypes.c_int64(ld), _ptr(w),
+                                         _ptr(rho), _prec(prec), _stream(stream)))
+
+    def hartree(self, rho, vh, vzg=None, stream=None):
+        """vh = Hartree potential of rho on the grid at the Gauss planes ([N_q][N1][N2] float64,
+        device); vzg (optional, [N_q][N1][N2] complex128): V(z_q, g) by grid frequency."""
+        _check(load().hartree_potential(self.h, _ptr(rho), _ptr(vh), _ptr(vzg), _stream(stream)))
 
     def reserve(self, ik, max_bands, ld=0, lock=True):
         """Size the k-point's H work buffers for max_bands vectors and (lock) keep them fixed."""
