@@ -247,10 +247,11 @@ mb_status mb_problem_reserve(mb_problem* p, int ik, int64_t max_bands, int64_t l
  * allocates and frees scratch memory and synchronises `stream`; it must not overlap
  * other calls on the same k-point.  info may be NULL. */
 typedef struct {
-    int32_t local_kernel;     /* 0 line-per-thread, 1 two-step line, 2 generic, 3 plane */
-    int32_t lds_budget_kb;    /* line-per-thread kernel: LDS budget per workgroup */
+    int32_t local_kernel;     /* 0 line-per-thread, 1 two-step line, 2 generic, 3 plane; -1 untuned rule */
+    int32_t lds_budget_kb;    /* line-per-thread kernel: LDS budget per workgroup (22..160) */
     int32_t plane_variant;    /* plane kernel: 0 8 points per lane, 1 16 points per lane */
     int32_t nl_matrix_cores;  /* FP32 projectors: 1 matrix cores, 0 vector kernel, -1 not tuned */
+    int32_t combine_bands;    /* partial-row combine pass: bands per thread 1 or 4, 0 = by projector count */
     int32_t candidates;       /* configurations timed */
     double local_ms;          /* chosen local kernel + combine pass, per call of nbands vectors */
     double local_default_ms;  /* the untuned choice (local kernel + combine pass), per call */
@@ -258,6 +259,26 @@ typedef struct {
 } mb_tune_info;
 mb_status mb_autotune(mb_problem* p, int ik, int64_t nbands, mb_precision prec, void* stream,
                       mb_tune_info* info);
+
+/* Kernel choices of k-point ik for one precision class (MB_FP64; MB_FP32 and MB_BF16X3
+ * share one class), as mb_autotune left them or as set here; timing fields are zero.
+ * mb_tune_set applies choices without timing (MB_ERR_INVALID_ARG for a value outside the
+ * ranges above, or the plane kernel on a grid it does not support); local_kernel = -1
+ * restores the untuned rules.  Host-side; no GPU needed. */
+mb_status mb_tune_get(const mb_problem* p, int ik, mb_precision prec, mb_tune_info* info);
+mb_status mb_tune_set(mb_problem* p, int ik, mb_precision prec, const mb_tune_info* info);
+
+/* Persisted autotuner cache.  mb_tune_save merges the tuned choices of every k-point and
+ * precision class of the problem into the JSON file at `path` (created if missing; entries
+ * of other problems in it are kept).  Each entry is keyed by what the choice depends on:
+ * grid N1 x N2, spline order, N_b, knot intervals, Gauss points per interval, N_G,
+ * projector count, recommended ld and the GPU architecture ("host" for host-only
+ * handles).  mb_tune_load applies every entry whose key matches a k-point and class of
+ * the problem and reports how many it applied (applied may be NULL); a missing file
+ * applies nothing and is not an error; MB_ERR_INVALID_ARG for a malformed file.  Host
+ * file I/O only. */
+mb_status mb_tune_save(const mb_problem* p, const char* path);
+mb_status mb_tune_load(mb_problem* p, const char* path, int* applied);
 
 /* x = S^{-1} r by forward and back substitution with the banded Cholesky factor
  * of S_z, shared by every G and band.  With augmentation charges (ultrasoft overlap
@@ -346,9 +367,26 @@ mb_status mb_batch_destroy(mb_batch* b);
  * Stream-ordered: the small descriptor tables of the launches are staged through
  * pinned host memory owned by the batch, so successive calls on one batch must
  * be issued on one stream (or be synchronised in between).  Not capturable into
- * a graph (it copies from host memory that later calls reuse). */
+ * a graph (it copies from host memory that later calls reuse): mb_batch_bind +
+ * hpsi_apply_batched_bound are the capturable form. */
 mb_status hpsi_apply_batched(mb_batch* b, const void* const* c, void* const* y, const int64_t* nbands,
                              const int64_t* ld, mb_precision prec, void* stream);
+
+/* Bind vector blocks to the batch for repeated, capturable applications: the arguments
+ * of hpsi_apply_batched (validated here), work buffers of their own sized for exactly
+ * these blocks, and a staging slot of their own.  Allocates and synchronises the device;
+ * a later bind replaces the earlier one (a graph that captured the earlier bound call
+ * must not be replayed after it).  The bound device blocks must stay allocated while
+ * bound calls may run. */
+mb_status mb_batch_bind(mb_batch* b, const void* const* c, void* const* y, const int64_t* nbands,
+                        const int64_t* ld, mb_precision prec);
+
+/* y_t = H_t c_t for the bound blocks, as hpsi_apply_batched.  Enqueues kernels and copies
+ * of launch descriptors from the bound staging slot only: no allocation, no host
+ * synchronisation, and the slot's contents are the same on every call, so the call can
+ * be captured into a HIP graph and replayed (the replays read the current contents of the
+ * bound c blocks).  Bound calls on one batch must not overlap each other. */
+mb_status hpsi_apply_batched_bound(mb_batch* b, void* stream);
 
 /* lanczos_lowest for every item t (nev[t] eigenpairs, eig[t] host nev[t] doubles,
  * x[t] device complex128 [nev[t]][N_b][ld_t] with the item's recommended ld_t,

@@ -41,6 +41,18 @@ struct mb_batch {
         bool pending = false;
     } slot[2];
     int next = 0;
+    // bound vector blocks (mb_batch_bind): the arguments of every bound call, their own work
+    // buffers and a staging slot of their own whose contents are the same on every call, so
+    // that a captured graph's descriptor copies replay correctly
+    struct Bound {
+        bool on = false;
+        std::vector<const void*> c;
+        std::vector<void*> y;
+        std::vector<int64_t> nbands, ld;
+        mb_precision prec = MB_FP64;
+        mb::Workspace part, proj, nlpart;
+        Slot slot;
+    } bound;
 };
 
 namespace mb {
@@ -61,17 +73,18 @@ void free_batch(mb_batch* b) {
     }
     if (b->part.ptr) (void)hipFree(b->part.ptr);
     if (b->proj.ptr) (void)hipFree(b->proj.ptr);
+    if (b->bound.on || b->bound.slot.host) (void)hipDeviceSynchronize();
+    if (b->bound.slot.host) (void)hipHostFree(b->bound.slot.host);
+    if (b->bound.slot.dev) (void)hipFree(b->bound.slot.dev);
+    for (mb::Workspace* w : {&b->bound.part, &b->bound.proj, &b->bound.nlpart})
+        if (w->ptr) (void)hipFree(w->ptr);
     delete b;
 }
 
-// records the slot's event on every exit path once copies may have been enqueued
-struct SlotGuard {
-    mb_batch::Slot& sl;
-    hipStream_t s;
-    ~SlotGuard() {
-        if (hipEventRecord(sl.done, s) == hipSuccess) sl.pending = true;
-    }
-};
+// the projection path of an item inside a batch: matrix cores for BF16x3 and for FP32 /
+// FP64 with at least 64 projectors, the vector kernel otherwise
+bool item_uses_mfma(const mb::Problem* p, int prec) { return prec == 3 || p->np >= 64; }
+
 
 mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUploader& up, hipStream_t s) {
     // projections <beta_p|c> per item (a8, a9)
@@ -82,11 +95,11 @@ mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUplo
         }
         // as in the single-item operator: matrix cores for BF16x3 and for FP32 / FP64
         // with at least 64 projectors, the vector kernel otherwise
-        if (prec != 3 && it.p->np < 64)
+        if (!item_uses_mfma(it.p, prec))
             BT_TRY(launch_nl_project(it.p, it.ik, it.c, it.proj, it.nbands, it.ld, lp, s));
         else
             BT_TRY(launch_nl_project_mfma(it.p, it.ik, it.c, it.proj, it.nbands, it.ld,
-                                          prec == 3 ? 2 : lp == 0 ? 0 : 1, false, s));
+                                          prec == 3 ? 2 : lp == 0 ? 0 : 1, false, s, it.nlpart));
     }
     // local potential, grouped by grid
     std::map<std::pair<int, int>, std::vector<BatchItem>> by_grid;
@@ -108,14 +121,21 @@ mb_status apply_chunk(std::vector<BatchItem>& chunk, int prec, int lp, TableUplo
     return launch_combine_batch(live, lp, up, s);
 }
 
+// bytes of the bound work buffers for the bound arguments (proj, partial rows, matrix-core
+// partials); the same arithmetic as apply_batched's
+struct BatchSizes {
+    size_t proj = 0, part = 0, nlpart = 0;
+};
+
 mb_status apply_batched(mb_batch* b, const void* const* c, void* const* y, const int64_t* nbands,
-                        const int64_t* ld, mb_precision prec, hipStream_t s) {
+                        const int64_t* ld, mb_precision prec, hipStream_t s, bool bound = false,
+                        BatchSizes* sizes_only = nullptr) {
     const int n = (int)b->items.size();
     const int lp = prec == MB_FP64 ? 0 : 1;               // local / combine precision
     const int kprec = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3;
     const size_t csz = lp == 0 ? 16 : 8;
     std::vector<BatchItem> all(n);
-    size_t proj_total = 0, part_max = 0, part_total = 0;
+    size_t proj_total = 0, part_max = 0, part_total = 0, nl_total = 0;
     for (int t = 0; t < n; ++t) {
         Problem* p = b->items[t].p;
         const int ik = b->items[t].ik;
@@ -134,29 +154,63 @@ mb_status apply_batched(mb_batch* b, const void* const* c, void* const* y, const
         part_max = std::max(part_max, pb);
         part_total += pb;
         proj_total += ((size_t)nbt * p->np * csz + 255) / 256 * 256;
+        if (bound && p->np > 0 && nbt > 0 && item_uses_mfma(p, kprec))
+            nl_total += (nl_mfma_part_bytes(p, (int)nbt, kprec == 3 ? 2 : lp == 0 ? 0 : 1) + 255) / 256 * 256;
     }
-    BT_TRY(ensure_ws(b->proj, std::max<size_t>(proj_total, 256)));
-    // partial rows of as many consecutive items as fit the budget (at least the largest item)
-    BT_TRY(ensure_ws(b->part, std::max<size_t>(std::min(PART_BUDGET, part_total), 256)));
-    const size_t part_cap = b->part.bytes;
+    const size_t proj_need = std::max<size_t>(proj_total, 256);
+    const size_t part_need = std::max<size_t>(std::min(PART_BUDGET, part_total), 256);
+    if (sizes_only) {
+        sizes_only->proj = proj_need;
+        sizes_only->part = part_need;
+        sizes_only->nlpart = std::max<size_t>(nl_total, 256);
+        return MB_OK;
+    }
+    mb::Workspace& wproj = bound ? b->bound.proj : b->proj;
+    mb::Workspace& wpart = bound ? b->bound.part : b->part;
+    if (bound) {
+        // the bound call allocates nothing: its buffers were sized by mb_batch_bind
+        if (wproj.bytes < proj_need || wpart.bytes < part_need || b->bound.nlpart.bytes < nl_total)
+            return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_batched_bound: bound work buffers too small");
+    } else {
+        BT_TRY(ensure_ws(wproj, proj_need));
+        // partial rows of as many consecutive items as fit the budget (at least the largest item)
+        BT_TRY(ensure_ws(wpart, part_need));
+    }
+    const size_t part_cap = wpart.bytes;
     {
-        size_t off = 0;
+        size_t off = 0, noff = 0;
         for (auto& it : all) {
-            it.proj = (char*)b->proj.ptr + off;
+            it.proj = (char*)wproj.ptr + off;
             off += ((size_t)it.nbands * it.p->np * csz + 255) / 256 * 256;
+            if (bound && it.p->np > 0 && it.nbands > 0 && item_uses_mfma(it.p, kprec)) {
+                it.nlpart = (char*)b->bound.nlpart.ptr + noff;
+                noff += (nl_mfma_part_bytes(it.p, it.nbands, kprec == 3 ? 2 : lp == 0 ? 0 : 1) + 255) / 256 * 256;
+            }
         }
     }
-    mb_batch::Slot& sl = b->slot[b->next];
-    b->next ^= 1;
-    if (sl.pending) {
-        MB_HIP_TRY(hipEventSynchronize(sl.done));
-        sl.pending = false;
-    }
     TableUploader up;
-    up.host = sl.host;
-    up.dev = sl.dev;
     up.cap = STAGE_BYTES;
-    SlotGuard guard{sl, s};
+    mb_batch::Slot* slp = nullptr;
+    if (bound) {
+        up.host = b->bound.slot.host;
+        up.dev = b->bound.slot.dev;
+    } else {
+        slp = &b->slot[b->next];
+        b->next ^= 1;
+        if (slp->pending) {
+            MB_HIP_TRY(hipEventSynchronize(slp->done));
+            slp->pending = false;
+        }
+        up.host = slp->host;
+        up.dev = slp->dev;
+    }
+    struct MaybeGuard {
+        mb_batch::Slot* sl;
+        hipStream_t s;
+        ~MaybeGuard() {
+            if (sl && hipEventRecord(sl->done, s) == hipSuccess) sl->pending = true;
+        }
+    } guard{slp, s};
     // chunks of consecutive items whose partial rows fit the workspace together
     std::vector<BatchItem> chunk;
     size_t used = 0;
@@ -167,7 +221,7 @@ mb_status apply_batched(mb_batch* b, const void* const* c, void* const* y, const
             chunk.clear();
             used = 0;
         }
-        it.part = (char*)b->part.ptr + used;
+        it.part = (char*)wpart.ptr + used;
         used += pb;
         chunk.push_back(it);
     }
@@ -242,6 +296,52 @@ mb_status hpsi_apply_batched(mb_batch* b, const void* const* c, void* const* y, 
     if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_batched: unknown precision");
     return mb::apply_batched(b, c, y, nbands, ld, prec, (hipStream_t)stream);
+}
+
+mb_status mb_batch_bind(mb_batch* b, const void* const* c, void* const* y, const int64_t* nbands,
+                        const int64_t* ld, mb_precision prec) {
+    if (!b || !c || !y || !nbands) return set_error(MB_ERR_INVALID_ARG, "mb_batch_bind: NULL argument");
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "mb_batch_bind: unknown precision");
+    const int n = (int)b->items.size();
+    mb::BatchSizes sz;
+    mb_status st = mb::apply_batched(b, c, y, nbands, ld, prec, nullptr, true, &sz);  // validates
+    if (st != MB_OK) return st;
+    if (hipSetDevice(b->device) != hipSuccess) return set_error(MB_ERR_HIP, "mb_batch_bind: hipSetDevice failed");
+    auto& bd = b->bound;
+    bd.on = false;
+    MB_HIP_TRY(hipDeviceSynchronize());  // no bound call may still read the old buffers
+    for (mb::Workspace* w : {&bd.part, &bd.proj, &bd.nlpart}) {
+        if (w->ptr) MB_HIP_TRY(hipFree(w->ptr));
+        w->ptr = nullptr;
+        w->bytes = 0;
+    }
+    if (mb::ensure_ws(bd.proj, sz.proj) != MB_OK || mb::ensure_ws(bd.part, sz.part) != MB_OK ||
+        mb::ensure_ws(bd.nlpart, sz.nlpart) != MB_OK)
+        return set_error(MB_ERR_OOM, "mb_batch_bind: work buffer allocation failed");
+    if (!bd.slot.host) {
+        if (hipHostMalloc((void**)&bd.slot.host, STAGE_BYTES, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&bd.slot.dev, STAGE_BYTES) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(MB_ERR_OOM, "mb_batch_bind: staging allocation failed");
+        }
+    }
+    bd.c.assign(c, c + n);
+    bd.y.assign(y, y + n);
+    bd.nbands.assign(nbands, nbands + n);
+    bd.ld.resize(n);
+    for (int t = 0; t < n; ++t) bd.ld[t] = ld ? ld[t] : mb::recommended_ld(b->items[t].p->kp[b->items[t].ik].ng);
+    bd.prec = prec;
+    bd.on = true;
+    return MB_OK;
+}
+
+mb_status hpsi_apply_batched_bound(mb_batch* b, void* stream) {
+    if (!b) return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_batched_bound: NULL batch");
+    if (!b->bound.on) return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_batched_bound: no blocks bound (mb_batch_bind)");
+    auto& bd = b->bound;
+    return mb::apply_batched(b, bd.c.data(), bd.y.data(), bd.nbands.data(), bd.ld.data(), bd.prec,
+                             (hipStream_t)stream, true);
 }
 
 mb_status lanczos_lowest_batched(mb_batch* b, const int* nev, mb_precision prec, const mb_lanczos_opts* opts,

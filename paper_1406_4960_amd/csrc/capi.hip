@@ -635,6 +635,7 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         return set_error(MB_ERR_OOM, "mb_autotune: scratch allocation failed");
     }
     (void)hipMemsetAsync(c, 0, vbytes, s);
+    (void)hipMemsetAsync(proj, 0, std::max<size_t>(16, (size_t)nb * p->np * csz), s);
     // average time of 3 calls after one warm-up; < 0 when the configuration is unsupported
     auto timeit = [&](auto&& call) -> double {
         mb_status r = call();
@@ -692,6 +693,20 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         const double t = timeit([&]() { return candidate(3, 110, var); });
         if (t >= 0) { ++ncand; if (t < best) { best = t; best_kind = 3; best_budget = 110; best_var = var; } }
     }
+    // bands per thread of the partial-row combine pass with the projector expansion
+    int combine_bb = 0;
+    if (st == MB_OK && best_kind >= 0 && best_kind != 3 && p->np > 0) {
+        double tb[2] = {-1.0, -1.0};
+        const int bbs[2] = {1, 4};
+        for (int v = 0; v < 2 && st == MB_OK; ++v) {
+            kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, -1, best_var, bbs[v]};
+            tb[v] = timeit([&]() { return mb::launch_combine(p, ik, c, part, proj, y, nullptr, nb, ld, cls, s); });
+        }
+        if (st == MB_OK && tb[0] >= 0 && tb[1] >= 0) {
+            combine_bb = tb[1] < tb[0] ? 4 : 1;
+            ncand += 2;
+        }
+    }
     int nl_mfma = -1;
     double nl_best = 0.0;
     if (st == MB_OK && p->np > 0 && cls == 1) {
@@ -708,7 +723,7 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         cleanup();
         return st != MB_OK ? st : set_error(MB_ERR_INVALID_ARG, "mb_autotune: no local kernel ran");
     }
-    kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, nl_mfma, best_var};
+    kp.tune[cls] = mb::KPoint::Tune{1, best_kind, best_budget, nl_mfma, best_var, combine_bb};
     if (cls == 1) kp.tune[2] = kp.tune[1];  // complex128 vectors with FP32 arithmetic (mixed solver)
     cleanup();
     if (info) {
@@ -716,12 +731,48 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
         info->lds_budget_kb = best_budget;
         info->plane_variant = best_var;
         info->nl_matrix_cores = nl_mfma;
+        info->combine_bands = combine_bb;
         info->candidates = ncand;
         info->local_ms = best;
         info->local_default_ms = t_default;
         info->nl_ms = nl_best;
     }
     return MB_OK;
+}
+
+mb_status mb_tune_get(const mb_problem* h, int ik, mb_precision prec, mb_tune_info* info) {
+    if (!h || !info) return set_error(MB_ERR_INVALID_ARG, "mb_tune_get: NULL argument");
+    if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_tune_get: ik out of range");
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "mb_tune_get: unknown precision");
+    const mb::KPoint::Tune& t = h->p.kp[ik].tune[prec == MB_FP64 ? 0 : 1];
+    *info = mb_tune_info{};
+    info->local_kernel = t.set ? t.kind : -1;
+    info->lds_budget_kb = t.budget_kb;
+    info->plane_variant = t.plane_var;
+    info->nl_matrix_cores = t.nl_mfma;
+    info->combine_bands = t.combine_bb;
+    return MB_OK;
+}
+
+mb_status mb_tune_set(mb_problem* h, int ik, mb_precision prec, const mb_tune_info* info) {
+    if (!h || !info) return set_error(MB_ERR_INVALID_ARG, "mb_tune_set: NULL argument");
+    mb::Problem& p = h->p;
+    if (ik < 0 || ik >= (int)p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_tune_set: ik out of range");
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "mb_tune_set: unknown precision");
+    return mb::apply_tune(&p, ik, prec == MB_FP64 ? 0 : 1, info->local_kernel, info->lds_budget_kb,
+                          info->plane_variant, info->nl_matrix_cores, info->combine_bands);
+}
+
+mb_status mb_tune_save(const mb_problem* h, const char* path) {
+    if (!h || !path) return set_error(MB_ERR_INVALID_ARG, "mb_tune_save: NULL argument");
+    return mb::tune_save(&h->p, path);
+}
+
+mb_status mb_tune_load(mb_problem* h, const char* path, int* applied) {
+    if (!h || !path) return set_error(MB_ERR_INVALID_ARG, "mb_tune_load: NULL argument");
+    return mb::tune_load(&h->p, path, applied);
 }
 
 mb_status spsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld, mb_precision prec,

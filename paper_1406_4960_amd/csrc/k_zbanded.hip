@@ -435,7 +435,10 @@ mb_status combine_impl(Problem* p, int ik, const void* c, const void* part, cons
                        const double* sband = nullptr) {
     CombineArgs<TI, T> a = make_combine_args<TI, T>(p, ik, c, part, proj, y, sy, nbands, ld, planes, projq, sband);
     const bool aug = sy && a.projq;
-    bool wide = ((y && a.proj) || aug) && p->np >= COMBINE_BB_NP;
+    const int cls = sizeof(T) == 8 ? 0 : sizeof(TI) == 8 ? 2 : 1;
+    const KPoint::Tune& tn = p->kp[ik].tune[cls];
+    bool wide = ((y && a.proj) || aug) &&
+                (tn.set && tn.combine_bb ? tn.combine_bb == 4 : p->np >= COMBINE_BB_NP);
     if (wide) {
         const char* e = getenv("MBKS_COMBINE_BB");  // "1": one band per thread (cross-checks)
         if (e && e[0] == '1' && e[1] == 0) wide = false;

@@ -70,6 +70,7 @@ struct KPoint {
         int budget_kb = 110;  // LDS budget of the line-per-thread kernel (planes per group)
         int nl_mfma = -1;     // FP32 projector path: 1 matrix cores, 0 vector kernel, -1 default
         int plane_var = 0;    // plane kernel lane split: 0 8 points per lane, 1 16 points per lane
+        int combine_bb = 0;   // partial-row combine pass: bands per thread (1, 4), 0 = by projector count
     } tune[3];
 };
 
@@ -239,6 +240,13 @@ mb_status launch_density(Problem* p, int ik, const void* c, int nbands, int ld, 
                          int prec, hipStream_t s);
 size_t hartree_work_bytes(const Problem* p, bool with_vzg);
 mb_status launch_hartree(Problem* p, const double* rho, double* vh, void* vzg, void* work, hipStream_t s);
+// kernel choices of (k-point, class 0 FP64 / 1 FP32): validated and applied (class 1 also
+// sets class 2, complex128 vectors with FP32 arithmetic); kind -1 restores the defaults
+mb_status apply_tune(Problem* p, int ik, int cls, int kind, int budget_kb, int plane_var, int nl_mfma,
+                     int combine_bb);
+// persisted choices (JSON file, merged on save, matched by size key on load)
+mb_status tune_save(const Problem* p, const char* path);
+mb_status tune_load(Problem* p, const char* path, int* applied);
 // host: per k-point Woodbury matrices of the ultrasoft overlap (after the projector tables)
 mb_status build_augmentation(Problem* p);
 // bytes of s_solve's in-place copy of r (0 without augmentation charges)
@@ -259,6 +267,7 @@ struct BatchItem {
     void* proj;        // projections of this item
     int nbands;
     int ld;
+    void* nlpart = nullptr;  // matrix-core partial projections (null: the k-point's own buffer)
 };
 
 // Copies small descriptor tables to the device in stream order through a pinned

@@ -27,7 +27,8 @@ EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dim
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_augmentation",
            "mb_problem_set_potential",
            "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
-           "density_accumulate", "hartree_potential", "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
+           "density_accumulate", "hartree_potential", "mb_tune_get", "mb_tune_set", "mb_tune_save",
+           "mb_tune_load", "mb_batch_bind", "hpsi_apply_batched_bound", "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
 
 
@@ -63,7 +64,7 @@ class LanczosOpts(ctypes.Structure):
 
 class TuneInfo(ctypes.Structure):
     _fields_ = [("local_kernel", c_int32), ("lds_budget_kb", c_int32), ("plane_variant", c_int32),
-                ("nl_matrix_cores", c_int32), ("candidates", c_int32), ("local_ms", c_double),
+                ("nl_matrix_cores", c_int32), ("combine_bands", c_int32), ("candidates", c_int32), ("local_ms", c_double),
                 ("local_default_ms", c_double), ("nl_ms", c_double)]
 
 
@@ -347,6 +348,31 @@ class Problem:
         _check(load().mb_autotune(self.h, ik, int(nbands), _prec(prec), _stream(stream), ctypes.byref(info)))
         return {f: getattr(info, f) for f, _ in TuneInfo._fields_}
 
+    def tune_get(self, ik, prec="fp32"):
+        """The kernel choices of k-point ik for a precision class (timing fields zero)."""
+        info = TuneInfo()
+        _check(load().mb_tune_get(self.h, ik, _prec(prec), ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in TuneInfo._fields_}
+
+    def tune_set(self, ik, prec="fp32", **choices):
+        """Apply kernel choices (keys of TuneInfo) to k-point ik without timing."""
+        info = TuneInfo()
+        cur = self.tune_get(ik, prec)
+        cur.update(choices)
+        for f, _ in TuneInfo._fields_:
+            setattr(info, f, cur[f])
+        _check(load().mb_tune_set(self.h, ik, _prec(prec), ctypes.byref(info)))
+
+    def tune_save(self, path):
+        """Merge this problem's tuned choices into the JSON cache file at path."""
+        _check(load().mb_tune_save(self.h, os.fsencode(path)))
+
+    def tune_load(self, path) -> int:
+        """Apply the matching entries of the JSON cache file; returns how many applied."""
+        n = ctypes.c_int(0)
+        _check(load().mb_tune_load(self.h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
     @staticmethod
     def default_opts() -> LanczosOpts:
         o = LanczosOpts()
@@ -414,6 +440,24 @@ class Batch:
         _check(load().hpsi_apply_batched(self.h, ctypes.cast(cp, c_void_p), ctypes.cast(yp, c_void_p),
                                          ctypes.cast(nb, c_void_p), ctypes.cast(ld, c_void_p), _prec(prec),
                                          _stream(stream)))
+
+    def bind(self, cs, ys, prec="fp64"):
+        """Bind the blocks cs -> ys for hpsi_bound (repeatable and capturable)."""
+        n = len(self.items)
+        if len(cs) != n or len(ys) != n:
+            raise ValueError("one input and one output block per item")
+        cp = (c_void_p * n)(*[c.data_ptr() if c is not None else 0 for c in cs])
+        yp = (c_void_p * n)(*[y.data_ptr() if y is not None else 0 for y in ys])
+        nb = (c_int64 * n)(*[c.shape[0] if c is not None else 0 for c in cs])
+        ld = (c_int64 * n)(*[c.shape[2] if c is not None else self.items[t][0].dims(self.items[t][1])["ld"]
+                             for t, c in enumerate(cs)])
+        _check(load().mb_batch_bind(self.h, ctypes.cast(cp, c_void_p), ctypes.cast(yp, c_void_p),
+                                    ctypes.cast(nb, c_void_p), ctypes.cast(ld, c_void_p), _prec(prec)))
+        self._bound = (cs, ys)  # keep the tensors alive while bound
+
+    def hpsi_bound(self, stream=None):
+        """H applied to the bound blocks (no allocation, no host synchronisation)."""
+        _check(load().hpsi_apply_batched_bound(self.h, _stream(stream)))
 
     def lanczos_lowest(self, nev, prec="fp64", opts=None, stream=None, raise_not_converged=True):
         """nev: list of eigenpair counts per item.  Returns (eigs list, xs list of torch tensors,

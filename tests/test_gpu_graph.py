@@ -96,3 +96,47 @@ def test_reserved_locked_buffers_keep_a_captured_graph_valid():
     p.hpsi(0, big, torch.empty_like(big))
     torch.cuda.synchronize()
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_bound_batch_graph_replays_match_eager(prec):
+    # hpsi_apply_batched_bound captured once: every replay (with eager work on the inputs
+    # in between) equals an eager hpsi_apply_batched call on the same inputs; the list mixes
+    # grids, k-points and projector counts (BF16x3 takes the matrix-core projections with
+    # the bound partial buffers)
+    print(f"[case] graph bound batch {prec}", flush=True)
+    probs = [mbks.Problem(workloads.graphene(), device=0), mbks.Problem(workloads.tiny(), device=0),
+             mbks.Problem(workloads.batched_member(12), device=0)]
+    items = [(probs[0], 0), (probs[0], 1), (probs[1], 0), (probs[2], 0)]
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    xs, ys = [], []
+    for t, (pr, ik) in enumerate(items):
+        dm = pr.dims(ik)
+        xs.append(torch.from_numpy(random_lib_block(80 + t, 3 + t, dm["nb"], dm["ng"], dm["ld"])).to(DEV).to(ct))
+        ys.append(torch.empty_like(xs[-1]))
+    b = mbks.Batch(items)
+    b.bind(xs, ys, prec)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.hpsi_bound()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.hpsi_bound()
+    for rep in range(3):
+        for x in xs:
+            x.mul_(complex(0.5, 0.2 * (rep + 1)))
+        g.replay()
+        torch.cuda.synchronize()
+        ye = [torch.empty_like(x) for x in xs]
+        b.hpsi(xs, ye, prec)
+        torch.cuda.synchronize()
+        for t in range(len(items)):
+            assert torch.equal(ys[t], ye[t]), (rep, t)
+            assert float(torch.max(torch.abs(ye[t]))) > 0
+    del g
+    b.close()
+    for pr in probs:
+        pr.close()

@@ -121,3 +121,49 @@ def test_bench_runs_on_one_gpu_only():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_tune_choices_persist_through_the_cache_file(tmp_path):
+    # choices set on one handle are saved, merged with another problem's, and applied
+    # to fresh handles of the same sizes only
+    path = str(tmp_path / "tune.json")
+    g = mbks.Problem(workloads.graphene(), device=None)
+    for ik in range(4):
+        g.tune_set(ik, "fp32", local_kernel=0, lds_budget_kb=66, nl_matrix_cores=0, combine_bands=4)
+    g.tune_set(0, "fp64", local_kernel=2, combine_bands=1)
+    g.tune_save(path)
+    s = mbks.Problem(workloads.surface(), device=None)
+    s.tune_set(0, "fp32", local_kernel=3, plane_variant=1, nl_matrix_cores=1)
+    s.tune_save(path)
+    text = open(path).read()
+    assert '"format": "mbks-tune-1"' in text and text.count('"key"') >= 3
+    g2 = mbks.Problem(workloads.graphene(), device=None)
+    assert g2.tune_get(0, "fp32")["local_kernel"] == -1
+    n = g2.tune_load(path)
+    assert n >= 5  # four FP32 k-points (identical sizes share one entry) and the FP64 one
+    for ik in range(4):
+        t = g2.tune_get(ik, "fp32")
+        assert (t["local_kernel"], t["lds_budget_kb"], t["nl_matrix_cores"], t["combine_bands"]) == (0, 66, 0, 4)
+    assert g2.tune_get(0, "fp64")["local_kernel"] == 2 and g2.tune_get(0, "fp64")["combine_bands"] == 1
+    s2 = mbks.Problem(workloads.surface(), device=None)
+    assert s2.tune_load(path) >= 1
+    t = s2.tune_get(0, "bf16x3")  # BF16x3 shares the FP32 class
+    assert (t["local_kernel"], t["plane_variant"], t["nl_matrix_cores"]) == (3, 1, 1)
+    # a problem of other sizes takes nothing; a missing file applies nothing
+    t2 = mbks.Problem(workloads.graphene_2x2(), device=None)
+    assert t2.tune_load(path) == 0
+    assert t2.tune_load(str(tmp_path / "missing.json")) == 0
+    # invalid choices and malformed files are refused
+    for bad in (dict(local_kernel=7), dict(local_kernel=0, lds_budget_kb=10), dict(local_kernel=3),
+                dict(local_kernel=0, combine_bands=3)):
+        with pytest.raises(mbks.MbError) as e:
+            g2.tune_set(0, "fp32", **bad)  # kind 3 on the 36x36 grid has no plane kernel
+        assert e.value.status == -1
+    open(str(tmp_path / "bad.json"), "w").write('{\n "format": "mbks-tune-1",\n "entries": [\n  {"key": 3}\n ]\n}\n')
+    with pytest.raises(mbks.MbError):
+        g2.tune_load(str(tmp_path / "bad.json"))
+    # -1 restores the untuned rules
+    g2.tune_set(1, "fp32", local_kernel=-1)
+    assert g2.tune_get(1, "fp32")["local_kernel"] == -1
+    for pr in (g, s, g2, s2, t2):
+        pr.close()
