@@ -305,6 +305,12 @@ typedef struct {
     uint64_t seed;        /* seed of the random start when x0 is NULL */
     int32_t extra;        /* buffer vectors iterated above the nev wanted ones (not required to
                              converge); < 0: min(16, max(4, nev / 4)) */
+    int32_t dense_low;    /* MB_FP32/MB_BF16X3: 1 (default) = during the reduced-precision cycles the
+                             vector combinations of 128 or more vectors (rotations, Gram-Schmidt
+                             updates) use FP32 matrix-core arithmetic on the FP64 vectors; 0 = FP64
+                             throughout.  Gram products stay FP64 (the projected problems need their
+                             overlap matrices to FP64 accuracy); the FP64 cycles that finish the
+                             solve are unaffected. */
 } mb_lanczos_opts;
 
 typedef struct {

@@ -1,4 +1,4 @@
-// Launchers of the FP64 dense kernels used by the eigensolver.
+// Launchers of the dense kernels used by the eigensolver (FP64 vectors).
 #pragma once
 
 #include "mbks_internal.h"
@@ -9,8 +9,10 @@ namespace mb {
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
                      void* scratch, size_t scratch_bytes, hipStream_t s);
 // Y_{z,n} = alpha sum_m W_z[m][n] X_{z,m} + beta Y_{z,n}; W_z is MI x NO row-major.
+// low: the wide combinations may run with FP32 matrix-core arithmetic (reduced-precision
+// cycles of the eigensolver)
 mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
-                      double alpha, double beta, hipStream_t s);
+                      double alpha, double beta, hipStream_t s, bool low = false);
 // scratch: at least 64 * nvec complex doubles
 mb_status dense_dots(const void* const* ta, const void* const* tb, int nvec, int64_t K, void* out, void* scratch,
                      hipStream_t s);

@@ -285,6 +285,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const zc* const* ta, const zc
             }
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
 // narrow products (MA <= 16): block (chunk, n, z) streams its k range once, each
 // thread accumulating conj(A_m[k]) B_n[k] for every m in registers; wave shuffles
 // and one LDS pass reduce the block's MA sums into part[z][chunk][m][n]
@@ -453,6 +455,232 @@ __global__ __launch_bounds__(256) void k_combo_w(const zc* const* __restrict__ t
             if (beta != 0.0) o = cadd(o, cscale(*yp, beta));
             *yp = o;
         }
+    }
+}
+
+// The wide combinations on the FP64 matrix cores (v_mfma_f64_16x16x4_f64): Y = X W as a
+// product of a K x MI block of vectors with the MI x NO coefficients.  A workgroup owns
+// 64 consecutive k (16 per wave) and 64 outputs (the output groups of one k range are
+// consecutive blocks on one XCD, so the later groups re-read X from L2); the
+// coefficients of each chunk of 16 inputs are staged in LDS once for the four waves
+// (two buffers: the next chunk's operands load while the current chunk's products issue),
+// and each lane loads one element of X per 4 inputs (lane l: input m0 + l/16,
+// k = k0 + l%16, so 16 lanes read 256 contiguous bytes of one vector).  Complex
+// products as four real ones per tile:
+//   Re += Xr Wr + (-Xi) Wi,  Im += Xr Wi + Xi Wr.
+// Output of tile t in lane l: rows (k) 4r + l/16, column (output) 16t + l%16; the tiles
+// go through LDS so that every output vector is written (and, with beta, read) as 64
+// consecutive k, 1 KB per instruction, instead of 64-byte pieces of 16 vectors.
+constexpr int CM_K = 64, CM_N = 64, CM_M = 16, CM_H = 32;  // CM_H: outputs per epilogue pass
+constexpr size_t CM_LDS = sizeof(zc) * (CM_K * (CM_H + 1) > 2 * CM_M * (CM_N + 1) ? CM_K * (CM_H + 1)
+                                                                                    : 2 * CM_M * (CM_N + 1));
+
+__global__ __launch_bounds__(256) void k_combo_mfma(const zc* const* __restrict__ tx, zc* const* __restrict__ ty,
+                                                    const zc* __restrict__ W, int MI, int NO, int64_t K,
+                                                    double alpha, double beta, int nng, int64_t nkb) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[CM_LDS];
+    zc (*Ws)[CM_N + 1] = reinterpret_cast<zc (*)[CM_N + 1]>(smem);
+    zc (*Os)[CM_H + 1] = reinterpret_cast<zc (*)[CM_H + 1]>(smem);
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int z = blockIdx.y;
+    const int ng = (int)(L % (unsigned)nng);
+    const int64_t kb = (int64_t)(L / (unsigned)nng);
+    if (kb >= nkb) return;
+    const int n0 = ng * CM_N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t k0 = kb * CM_K;
+    const int64_t ka = k0 + wave * 16 + li;  // row of this lane's A operand
+    const bool kok = ka < K;
+    const zc* const* xt = tx + (size_t)z * MI;
+    const zc* Wz = W + (size_t)z * MI * NO;
+    mfma_d4 cr[CM_N / 16], ci[CM_N / 16];
+#pragma unroll
+    for (int t = 0; t < CM_N / 16; ++t) {
+        cr[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+        ci[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    }
+    // operands of one chunk of CM_M inputs: this lane's X elements for the chunk's four
+    // steps and this thread's share of the chunk's coefficients; the next chunk's are
+    // loaded while the current chunk's products issue (two coefficient buffers in LDS)
+    constexpr int WPT = CM_M * CM_N / 256;
+    zc av[CM_M / 4], wv[WPT];
+    auto load = [&](int m0) {
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) {
+            const int m = m0 + 4 * st + lg;
+            av[st] = (kok && m < MI) ? xt[m][ka] : mk<double>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            const int m = m0 + e / CM_N, n = n0 + e % CM_N;
+            wv[u] = (m < MI && n < NO) ? Wz[(size_t)m * NO + n] : mk<double>(0, 0);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            Ws[buf * CM_M + e / CM_N][e % CM_N] = wv[u];
+        }
+    };
+    load(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int m0 = 0; m0 < MI; m0 += CM_M) {
+        zc a[CM_M / 4];
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) a[st] = av[st];
+        const bool more = m0 + CM_M < MI;
+        if (more) load(m0 + CM_M);
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) {
+            const double xr = a[st].x, xi = a[st].y;
+#pragma unroll
+            for (int t = 0; t < CM_N / 16; ++t) {
+                const zc w = Ws[buf * CM_M + 4 * st + lg][16 * t + li];
+                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, w.x, cr[t], 0, 0, 0);
+                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, w.y, cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, w.y, ci[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, w.x, ci[t], 0, 0, 0);
+            }
+        }
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // epilogue in two passes of CM_H outputs: tiles to LDS as [k][n], then each wave
+    // writes CM_H / 4 outputs, lane l taking row k0 + l
+#pragma unroll
+    for (int h = 0; h < CM_N / CM_H; ++h) {
+#pragma unroll
+        for (int tt = 0; tt < CM_H / 16; ++tt) {
+            const int t = h * (CM_H / 16) + tt;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Os[wave * 16 + 4 * r + lg][16 * tt + li] = mk<double>(cr[t][r], ci[t][r]);
+        }
+        __syncthreads();
+        const int64_t k = k0 + lane;
+#pragma unroll
+        for (int j = 0; j < CM_H / 4; ++j) {
+            const int nn = wave * (CM_H / 4) + j;
+            const int n = n0 + h * CM_H + nn;
+            if (n < NO && k < K) {
+                zc* yv = ty[(size_t)z * NO + n];
+                const zc v = Os[lane][nn];
+                zc o = mk<double>(alpha * v.x, alpha * v.y);
+                if (beta != 0.0) o = cadd(o, cscale(yv[k], beta));
+                yv[k] = o;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The combination with FP32 matrix-core arithmetic on FP64 vectors (reduced-precision
+// cycles of the eigensolver): the same tiles and staging as k_combo_mfma, operands
+// converted to FP32 on load, products accumulated in FP32, outputs (and beta Y) in FP64.
+__global__ __launch_bounds__(256) void k_combo_mfma32(const zc* const* __restrict__ tx, zc* const* __restrict__ ty,
+                                                      const zc* __restrict__ W, int MI, int NO, int64_t K,
+                                                      double alpha, double beta, int nng, int64_t nkb) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[CM_LDS];
+    cx<float> (*Ws)[CM_N + 1] = reinterpret_cast<cx<float> (*)[CM_N + 1]>(smem);
+    zc (*Os)[CM_H + 1] = reinterpret_cast<zc (*)[CM_H + 1]>(smem);
+    const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
+    const int z = blockIdx.y;
+    const int ng = (int)(L % (unsigned)nng);
+    const int64_t kb = (int64_t)(L / (unsigned)nng);
+    if (kb >= nkb) return;
+    const int n0 = ng * CM_N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t k0 = kb * CM_K;
+    const int64_t ka = k0 + wave * 16 + li;
+    const bool kok = ka < K;
+    const zc* const* xt = tx + (size_t)z * MI;
+    const zc* Wz = W + (size_t)z * MI * NO;
+    mfma_f4 cr[CM_N / 16], ci[CM_N / 16];
+#pragma unroll
+    for (int t = 0; t < CM_N / 16; ++t) {
+        cr[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+        ci[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    }
+    constexpr int WPT = CM_M * CM_N / 256;
+    cx<float> av[CM_M / 4], wv[WPT];
+    auto load = [&](int m0) {
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) {
+            const int m = m0 + 4 * st + lg;
+            const zc v = (kok && m < MI) ? xt[m][ka] : mk<double>(0, 0);
+            av[st] = mk<float>((float)v.x, (float)v.y);
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            const int m = m0 + e / CM_N, n = n0 + e % CM_N;
+            const zc v = (m < MI && n < NO) ? Wz[(size_t)m * NO + n] : mk<double>(0, 0);
+            wv[u] = mk<float>((float)v.x, (float)v.y);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            Ws[buf * CM_M + e / CM_N][e % CM_N] = wv[u];
+        }
+    };
+    load(0);
+    stage(0);
+    __syncthreads();
+    int buf = 0;
+    for (int m0 = 0; m0 < MI; m0 += CM_M) {
+        cx<float> a[CM_M / 4];
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) a[st] = av[st];
+        const bool more = m0 + CM_M < MI;
+        if (more) load(m0 + CM_M);
+#pragma unroll
+        for (int st = 0; st < CM_M / 4; ++st) {
+            const float xr = a[st].x, xi = a[st].y;
+#pragma unroll
+            for (int t = 0; t < CM_N / 16; ++t) {
+                const cx<float> w = Ws[buf * CM_M + 4 * st + lg][16 * t + li];
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, w.x, cr[t], 0, 0, 0);
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xi, w.y, cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, w.y, ci[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, w.x, ci[t], 0, 0, 0);
+            }
+        }
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int h = 0; h < CM_N / CM_H; ++h) {
+#pragma unroll
+        for (int tt = 0; tt < CM_H / 16; ++tt) {
+            const int t = h * (CM_H / 16) + tt;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                Os[wave * 16 + 4 * lg + r][16 * tt + li] = mk<double>((double)cr[t][r], (double)ci[t][r]);
+        }
+        __syncthreads();
+        const int64_t k = k0 + lane;
+#pragma unroll
+        for (int j = 0; j < CM_H / 4; ++j) {
+            const int nn = wave * (CM_H / 4) + j;
+            const int n = n0 + h * CM_H + nn;
+            if (n < NO && k < K) {
+                zc* yv = ty[(size_t)z * NO + n];
+                const zc v = Os[lane][nn];
+                zc o = mk<double>(alpha * v.x, alpha * v.y);
+                if (beta != 0.0) o = cadd(o, cscale(yv[k], beta));
+                yv[k] = o;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1200,7 +1428,7 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
 }
 
 mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int MI, int NO, int nz, int64_t K,
-                      double alpha, double beta, hipStream_t s) {
+                      double alpha, double beta, hipStream_t s, bool low) {
     if (MI <= 0 || NO <= 0 || nz <= 0) return MB_OK;
     StageScope ts_(MB_STAGE_COMBO, s);
     static const int cw_env = [] {
@@ -1210,6 +1438,25 @@ mb_status dense_combo(const void* const* tx, void* const* ty, const void* W, int
     // 16 outputs per thread for the wide combinations (measured 1.8x faster than 8 on
     // MI, NO ~ 300-1000), 8 for the narrow ones, whose grids would otherwise be small
     const int cw = (cw_env == 8 || cw_env == 16 || cw_env == 32) ? cw_env : (MI >= 64 && NO >= 64) ? 16 : 8;
+    // wide combinations (both sides >= 128, e.g. the rotations and Gram-Schmidt updates of
+    // hundreds of trial vectors) on the matrix cores; MBKS_COMBO_MFMA=0 keeps them on the
+    // vector units (cross-checks)
+    const char* me = getenv("MBKS_COMBO_MFMA");
+    const bool mfma_on = !(me && me[0] == '0');
+    if (mfma_on && cw_env < 0 && MI >= 128 && NO >= 128 && K >= 4096) {
+        const int nng = (NO + CM_N - 1) / CM_N;
+        const int64_t nkb = (K + CM_K - 1) / CM_K;
+        if ((int64_t)nng * nkb < ((int64_t)1 << 31)) {
+            if (low)
+                hipLaunchKernelGGL(k_combo_mfma32, dim3((unsigned)(nng * nkb), nz), dim3(256), 0, s,
+                                   (const zc* const*)tx, (zc* const*)ty, (const zc*)W, MI, NO, K, alpha, beta, nng, nkb);
+            else
+                hipLaunchKernelGGL(k_combo_mfma, dim3((unsigned)(nng * nkb), nz), dim3(256), 0, s,
+                                   (const zc* const*)tx, (zc* const*)ty, (const zc*)W, MI, NO, K, alpha, beta, nng, nkb);
+            MB_HIP_TRY(hipGetLastError());
+            return MB_OK;
+        }
+    }
     if (cw == 8) launch_combo_w<8>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);
     else if (cw == 16) launch_combo_w<16>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);
     else launch_combo_w<32>(tx, ty, W, MI, NO, nz, K, alpha, beta, s);

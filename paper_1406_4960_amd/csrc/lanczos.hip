@@ -94,6 +94,9 @@ struct Solver {
     // host mirrors
     std::vector<double> h_theta, h_resid;
     int64_t applies = 0, applies_low = 0;
+    // combinations of the current cycle may use FP32 matrix cores (Gram products stay in
+    // FP64: the projected problems need their overlap to FP64 accuracy)
+    bool low = false;
 
     char* vec(char* base, int i) const { return base + (size_t)i * vbytes; }
 
@@ -118,9 +121,9 @@ struct Solver {
         LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tSX, n, n, 1, K, Sp, gscratch, gscratch_bytes, s));
         LZ_TRY(dense_geneig(Hp, Sp, n, 1, evals, Y, gwork, status, s));
         LZ_TRY(dense_copy_cols(Y, n, M, n, W, s));
-        LZ_TRY(dense_combo((const void* const*)tX, tXn, W, n, M, 1, K, 1.0, 0.0, s));
-        LZ_TRY(dense_combo((const void* const*)tHX, tHXn, W, n, M, 1, K, 1.0, 0.0, s));
-        LZ_TRY(dense_combo((const void* const*)tSX, tSXn, W, n, M, 1, K, 1.0, 0.0, s));
+        LZ_TRY(dense_combo((const void* const*)tX, tXn, W, n, M, 1, K, 1.0, 0.0, s, low));
+        LZ_TRY(dense_combo((const void* const*)tHX, tHXn, W, n, M, 1, K, 1.0, 0.0, s, low));
+        LZ_TRY(dense_combo((const void* const*)tSX, tSXn, W, n, M, 1, K, 1.0, 0.0, s, low));
         MB_HIP_TRY(hipMemcpyAsync(X, Xn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
         MB_HIP_TRY(hipMemcpyAsync(HX, HXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
         MB_HIP_TRY(hipMemcpyAsync(SX, SXn, (size_t)M * vbytes, hipMemcpyDeviceToDevice, s));
@@ -150,7 +153,7 @@ struct Solver {
             // against all trial vectors: C = (S X)^H K_j, K_j -= X C
             LZ_TRY(dense_gram((const void* const*)tSX, (const void* const*)tKj, M, nbl, 1, K, coef, gscratch,
                               gscratch_bytes, s));
-            LZ_TRY(dense_combo((const void* const*)tX, tKj, coef, M, nbl, 1, K, -1.0, 1.0, s));
+            LZ_TRY(dense_combo((const void* const*)tX, tKj, coef, M, nbl, 1, K, -1.0, 1.0, s, low));
             if (j > 0) {
                 // d[z*j + i] = <K_i^z|S|K_j^z>, then K_j^z -= sum_i d[z*j + i] K_i^z
                 LZ_TRY(dense_dots((const void* const*)tGA[j], (const void* const*)tGB[j], nbl * j, K, dots,
@@ -418,6 +421,8 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
         LZ_TRY(dense_random(S.X, S.M, p->nb, S.ld, kp.ng, o.seed, s));
     }
     int cur = prec == MB_FP64 ? 0 : prec == MB_FP32 ? 2 : 4;
+    const bool low_dense = o.dense_low != 0;
+    S.low = cur != 0 && low_dense;
     LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, cur));
     LZ_TRY(S.global_rr(S.M));
 
@@ -433,6 +438,7 @@ mb_status lanczos_impl(Problem* p, int ik, int nev, mb_precision prec, const mb_
             if (mx <= o.switch_tol || stall >= 4) {
                 // continue in FP64: refresh H X at full precision
                 cur = 0;
+                S.low = false;
                 LZ_TRY(S.hop(S.X, S.HX, S.SX, S.M, 0));
                 LZ_TRY(S.global_rr(S.M));
                 LZ_TRY(S.residuals());
@@ -491,6 +497,7 @@ extern "C" void mb_lanczos_default_opts(mb_lanczos_opts* o) {
     o->switch_tol = 1e-4;
     o->seed = 14064960ull;
     o->extra = -1;
+    o->dense_low = 1;
 }
 
 extern "C" mb_status lanczos_lowest(mb_problem* h, int ik, int nev, mb_precision prec, const mb_lanczos_opts* opts,

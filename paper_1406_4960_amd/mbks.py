@@ -59,7 +59,7 @@ class MbDesc(ctypes.Structure):
 class LanczosOpts(ctypes.Structure):
     _fields_ = [("block", c_int32), ("krylov", c_int32), ("krylov_global", c_int32), ("max_iter", c_int32),
                 ("tol", c_double), ("sigma", c_double), ("switch_tol", c_double), ("seed", c_uint64),
-                ("extra", c_int32)]
+                ("extra", c_int32), ("dense_low", c_int32)]
 
 
 class TuneInfo(ctypes.Structure):

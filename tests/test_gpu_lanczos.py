@@ -218,3 +218,52 @@ def test_large_solve_releases_its_workspace():
     print("held after the solve (GiB):", (free0 - free1) / 2**30, flush=True)
     assert free0 - free1 < 2 * 2**30
     p.close()
+
+
+def test_wide_combinations_on_matrix_cores_match_vector_units(monkeypatch):
+    # 128 eigenpairs (144 iterated vectors): the rotations and Gram-Schmidt updates of
+    # >= 128 vectors run on the FP64 matrix cores; the same solve with them on the vector
+    # units gives the same eigenvalues.  The graphene-like slab's lowest 32 match the stored
+    # oracle eigenvalues; batch member 3 has a vector length (73 x 240) that is not a
+    # multiple of the kernel's 64-row tile and 144 outputs, not a multiple of 64
+    print("[case] lanczos wide combinations mfma vs vector", flush=True)
+    for name, d in (("graphene", workloads.graphene()), ("member3", workloads.batched_member(3))):
+        eigs = {}
+        for mode in ("1", "0"):
+            monkeypatch.setenv("MBKS_COMBO_MFMA", mode)
+            p = mbks.Problem(d, device=0)
+            e, x, info, st = p.lanczos_lowest(0, 128, "fp64")
+            print(name, mode, info, flush=True)
+            assert st == 0
+            eigs[mode] = e
+            p.close()
+        assert np.max(np.abs(eigs["1"] - eigs["0"])) < 1e-9, name
+        if name == "graphene":
+            g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "graphene_eigs.json")))
+            ref = np.array(g["kpoints"]["0"]["eps"])
+            assert np.max(np.abs(eigs["1"][:len(ref)] - ref)) < 1e-8
+
+
+@pytest.mark.parametrize("cfg,nev", [("graphene", 240), ("surface", 128)])
+def test_reduced_precision_dense_products_reach_the_same_eigenpairs(cfg, nev):
+    # nev eigenpairs in the mixed form (graphene-like slab: 256 iterated vectors; surface
+    # slab: 144): with the reduced-precision cycles' vector combinations on the FP32 matrix
+    # cores (default) and with them in FP64, the FP64 cycles that finish the solve reach the
+    # same eigenvalues, and the lowest 32 match the stored oracle eigenvalues
+    print(f"[case] lanczos mixed form, FP32 combinations, {cfg} nev={nev}", flush=True)
+    d = workloads.CONFIGS[cfg]()
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{cfg}_eigs.json")))
+    ref = np.array(g["kpoints"]["0"]["eps"])
+    eigs = {}
+    for low in (1, 0):
+        p = mbks.Problem(d, device=0)
+        o = p.default_opts()
+        assert o.dense_low == 1
+        o.dense_low = low
+        e, x, info, st = p.lanczos_lowest(0, nev, "fp32", opts=o)
+        print(low, info, flush=True)
+        assert st == 0 and info["iters_low"] >= 1
+        assert np.max(np.abs(e[:len(ref)] - ref)) < 1e-8
+        eigs[low] = e
+        p.close()
+    assert np.max(np.abs(eigs[1] - eigs[0])) < 1e-9
