@@ -16,6 +16,8 @@
 //             e^{-i g.rho_j} (real part).  |g| is the grid frequency's shortest alias.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "cplx.h"
@@ -325,6 +327,12 @@ mb_status launch_density(Problem* p, int ik, const void* c, int nbands, int ld, 
                          int prec, hipStream_t s) {
     if (nbands == 0) return MB_OK;
     if (p->order != KORD) return set_error(MB_ERR_INVALID_ARG, "GPU kernels support order 4 only");
+    // the 128 x 64 grid: lane-split transforms (MBKS_DENSITY_KERNEL=generic: LDS transforms)
+    const char* sel = getenv("MBKS_DENSITY_KERNEL");
+    if (!(sel && std::string(sel) == "generic")) {
+        mb_status st = launch_density_plane(p, ik, c, nbands, ld, w, rho, prec, s);
+        if (st != MB_ERR_INVALID_ARG) return st;
+    }
     if (prec == 0) return density_impl<double>(p, ik, c, nbands, ld, w, rho, s);
     return density_impl<float>(p, ik, c, nbands, ld, w, rho, s);
 }

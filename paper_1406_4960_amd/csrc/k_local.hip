@@ -347,7 +347,9 @@ bool local_uses_planes(const Problem* p, int ik, int lp) {
     const char* sel = getenv("MBKS_LOCAL_KERNEL");
     if (sel && (std::string(sel) == "generic" || std::string(sel) == "split")) return false;
     const KPoint::Tune& tn = p->kp[ik].tune[lp];
-    return !(tn.set && tn.kind != 3);
+    if (tn.set) return tn.kind == 3;
+    // untuned: the plane kernel on the 128 x 64 grid; elsewhere when mb_autotune picks it
+    return p->N1 == 128 && p->N2 == 64;
 }
 
 mb_status launch_vgrid(Problem* p, hipStream_t s) {

@@ -1,5 +1,6 @@
 // Local-potential part of H c, one Gauss plane at a time, for in-plane grids whose FFT
-// lines are split over a few lanes (the 128 x 64 grid of the large surface slab):
+// lines are split over a few lanes (the 128 x 64 grid of the large surface slab, and the
+// 36 x 36 grid of the graphene-like slab):
 //   evaluate psi(G, z_q) = sum_t B_{s-1+t}(z_q) c(G, s-1+t), scatter on the sphere rows,
 //   inverse 2D FFT, multiply by V(rho, z_q), forward 2D FFT, gather, and write
 //   u_q(G) = (V psi_q)(G) / (N1 N2) for every Gauss plane q (local-potential matrix
@@ -403,12 +404,200 @@ mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, 
         if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1>(p, ik, c, u, nbands, ld, s);
         return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
     }
+    // 36 x 36 (the graphene-like slab): lines of 36 = 4 x 9 points over 4 lanes (144 line
+    // tasks per pass, 192 threads) or 2 x 18 over 2 lanes (72 tasks, 128 threads); the
+    // planes are small enough for several workgroups per CU
+    if (p->N1 == 36 && p->N2 == 36) {
+        if (var == 1) return plane_launch<TI, T, 36, 36, 2, 2, 128, 1>(p, ik, c, u, nbands, ld, s);
+        return plane_launch<TI, T, 36, 36, 4, 4, 192, 1>(p, ik, c, u, nbands, ld, s);
+    }
     return MB_ERR_INVALID_ARG;
+}
+
+// Electron density at the Gauss planes with the same lane-split transforms (the charge
+// density of Sec. II.B.1): one workgroup per Gauss plane runs over the bands; per band
+// the row pass evaluates and transforms the sphere rows into LDS and the column pass
+// finishes the inverse transform, after which lane l of column j2 holds the points
+// j1 = k + L1 bitrev(l) and adds w_b |psi|^2 / A to its accumulators.  Every thread owns
+// the same grid points for all bands, so the sum over bands needs no atomics and runs in
+// a fixed order.  FP64 arithmetic.
+template <typename TI>
+struct DensPlaneArgs {
+    const cx<TI>* c;
+    const double* w;
+    double* rho;           // [q][j1][j2]
+    const double* bval;
+    const int32_t* gtab;
+    const int32_t* rows;
+    const cx<double>* tw1;
+    const cx<double>* tw2;
+    int nbands, ld, nq, nb, nrows, nzq;
+    double inv_area;
+};
+
+template <typename TI, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+__global__ __launch_bounds__(NT) void k_density_plane(DensPlaneArgs<TI> a) {
+    using T = double;
+    constexpr int L1 = N1 / Q1, L2 = N2 / Q2;
+    constexpr int P = plane_pitch<N2, Q2, PADB>();
+    constexpr int CT = N2 * Q1 / NT;  // column tasks per thread
+    static_assert(N2 * Q1 % NT == 0, "column tasks fill the workgroup");
+    extern __shared__ unsigned char smem_raw[];
+    cx<T>* tw1 = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* tw2 = tw1 + N1;
+    uint32_t* rmask = reinterpret_cast<uint32_t*>(tw2 + N2);
+    cx<T>* grid = reinterpret_cast<cx<T>*>(smem_raw + plane_hdr<T, N1, N2>());
+    const int q = (int)xcd_logical(blockIdx.x, gridDim.x);
+    if (q >= a.nzq) return;
+    const int s = q / a.nq;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < N1; e += NT) tw1[e] = a.tw1[e];
+    for (int e = tid; e < N2; e += NT) tw2[e] = a.tw2[e];
+    for (int e = tid; e < (N1 + 31) / 32; e += NT) rmask[e] = 0u;
+    __syncthreads();
+    for (int e = tid; e < a.nrows; e += NT) {
+        const int j1 = a.rows[e];
+        atomicOr(&rmask[j1 >> 5], 1u << (j1 & 31));
+    }
+    __syncthreads();
+    T bv[KORD];
+#pragma unroll
+    for (int t = 0; t < KORD; ++t) bv[t] = a.bval[(size_t)q * KORD + t];
+    T acc[CT][L1];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int k = 0; k < L1; ++k) acc[c][k] = 0.0;
+    const int nrt = (a.nrows * Q2 + 15) / 16 * 16;
+    for (int b = 0; b < a.nbands; ++b) {
+        const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
+        // rows: evaluate on the sphere row, inverse transform along j2
+        for (int task = tid; task < nrt; task += NT) {
+            const int rc = (task >> 4) * (16 / Q2) + LaneMap<Q2>::line(task & 15);
+            const int l = LaneMap<Q2>::lane(task & 15);
+            if (rc >= a.nrows) continue;
+            const int j1 = a.rows[rc];
+            const int32_t* gr = a.gtab + (size_t)rc * N2;
+            cx<T> x[L2];
+            int gi[L2];
+#pragma unroll
+            for (int m = 0; m < L2; ++m) {
+                gi[m] = gr[l + Q2 * m];
+                x[m] = mk<T>(0, 0);
+            }
+#pragma unroll 1
+            for (int t = 0; t < KORD; ++t) {
+                const int row = s - 1 + t;
+                if (row < 0 || row >= a.nb) continue;
+                const cx<TI>* cr = cb + (size_t)row * a.ld;
+#pragma unroll
+                for (int m = 0; m < L2; ++m) {
+                    const cx<TI> v = cr[gi[m] >= 0 ? gi[m] : 0];
+                    const T w = gi[m] >= 0 ? bv[t] : (T)0;
+                    x[m].x = fma(w, (T)v.x, x[m].x);
+                    x[m].y = fma(w, (T)v.y, x[m].y);
+                }
+            }
+            line_fft<T, L2, +1>(x);
+#pragma unroll
+            for (int k = 1; k < L2; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw2, l * k));
+            dif_lanes<T, L2, Q2, N2, +1>(x, l, tw2);
+            cx<T>* dst = grid + (size_t)j1 * P + colpos<N2, Q2, PADB>(L2 * bitrev_lane<Q2>(l));
+#pragma unroll
+            for (int k = 0; k < L2; ++k) dst[k] = x[k];
+        }
+        __syncthreads();
+        // columns: inverse transform along j1, then |psi|^2 into the accumulators
+        const T wb = a.w[b] * a.inv_area;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int task = tid + c * NT;
+            const int j2 = (task >> 4) * (16 / Q1) + LaneMap<Q1>::line(task & 15);
+            const int l = LaneMap<Q1>::lane(task & 15);
+            const int cp = colpos<N2, Q2, PADB>(j2);
+            uint32_t live = 0u;
+#pragma unroll
+            for (int m = 0; m < L1; ++m) {
+                const int j1 = l + Q1 * m;
+                if ((rmask[j1 >> 5] >> (j1 & 31)) & 1u) live |= 1u << m;
+            }
+            cx<T> x[L1];
+#pragma unroll
+            for (int m = 0; m < L1; ++m) {
+                const cx<T> v = grid[(size_t)(l + Q1 * m) * P + cp];
+                x[m] = ((live >> m) & 1u) ? v : mk<T>(0, 0);
+            }
+            line_fft<T, L1, +1>(x);
+#pragma unroll
+            for (int k = 1; k < L1; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw1, l * k));
+            dif_lanes<T, L1, Q1, N1, +1>(x, l, tw1);
+#pragma unroll
+            for (int k = 0; k < L1; ++k) acc[c][k] = fma(wb, x[k].x * x[k].x + x[k].y * x[k].y, acc[c][k]);
+        }
+        __syncthreads();  // the next band's row pass overwrites the plane
+    }
+    double* rq = a.rho + (size_t)q * N1 * N2;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const int task = tid + c * NT;
+        const int j2 = (task >> 4) * (16 / Q1) + LaneMap<Q1>::line(task & 15);
+        const int l = LaneMap<Q1>::lane(task & 15);
+#pragma unroll
+        for (int k = 0; k < L1; ++k) {
+            const int j1 = k + L1 * bitrev_lane<Q1>(l);
+            rq[(size_t)j1 * N2 + j2] += acc[c][k];
+        }
+    }
+}
+
+template <typename TI, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+mb_status density_plane_launch(Problem* p, int ik, const void* c, int nbands, int ld, const double* w, double* rho,
+                               hipStream_t s) {
+    const KPoint& kp = p->kp[ik];
+    if (!kp.d_gtab) return set_error(MB_ERR_INVALID_ARG, "plane kernel tables missing");
+    if (kp.ng > 0 && (int)kp.rows.size() > N1) return set_error(MB_ERR_INVALID_ARG, "plane kernel: rows");
+    DensPlaneArgs<TI> a;
+    a.c = (const cx<TI>*)c;
+    a.w = w;
+    a.rho = rho;
+    a.bval = p->d_bval;
+    a.gtab = kp.d_gtab;
+    a.rows = kp.d_rows;
+    a.tw1 = (const cx<double>*)p->d_tw1;
+    a.tw2 = (const cx<double>*)p->d_tw2;
+    a.nbands = nbands;
+    a.ld = ld;
+    a.nq = p->nq;
+    a.nb = p->nb;
+    a.nrows = (int)kp.rows.size();
+    a.nzq = p->nzq;
+    a.inv_area = 1.0 / p->area;
+    constexpr size_t lds = plane_lds<double, N1, N2, Q2, PADB>();
+    static_assert(lds <= 163840, "plane does not fit in LDS");
+    auto kern = k_density_plane<TI, N1, N2, Q1, Q2, NT, PADB>;
+    if (lds > 65536)
+        MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    StageScope ts_(MB_STAGE_DENSITY, s, nbands);
+    hipLaunchKernelGGL(kern, dim3((unsigned)p->nzq), dim3(NT), lds, s, a);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
 }
 
 }  // namespace
 
-bool plane_kernel_grid(const Problem* p) { return p->order == KORD && p->N1 == 128 && p->N2 == 64; }
+bool plane_kernel_grid(const Problem* p) {
+    return p->order == KORD && ((p->N1 == 128 && p->N2 == 64) || (p->N1 == 36 && p->N2 == 36));
+}
+
+// Returns MB_ERR_INVALID_ARG (no message) if the grid has no plane kernel.  FP64 planes
+// with 16 points per lane (8 lanes per 128-point column, 4 per 64-point row).
+mb_status launch_density_plane(Problem* p, int ik, const void* c, int nbands, int ld, const double* w, double* rho,
+                               int prec, hipStream_t s) {
+    if (p->order != KORD || p->N1 != 128 || p->N2 != 64) return MB_ERR_INVALID_ARG;
+    if (nbands == 0) return MB_OK;
+    if (prec == 0) return density_plane_launch<double, 128, 64, 8, 4, 512, 1>(p, ik, c, nbands, ld, w, rho, s);
+    return density_plane_launch<float, 128, 64, 8, 4, 512, 1>(p, ik, c, nbands, ld, w, rho, s);
+}
 
 // Returns MB_ERR_INVALID_ARG (no message) if the grid has no plane kernel.
 mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,

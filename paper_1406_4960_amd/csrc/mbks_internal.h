@@ -238,6 +238,9 @@ mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int n
 // of a density in the (z, g) form; prec 0 complex128 vectors, else complex64
 mb_status launch_density(Problem* p, int ik, const void* c, int nbands, int ld, const double* w, double* rho,
                          int prec, hipStream_t s);
+// the density with the plane kernel's lane-split transforms; MB_ERR_INVALID_ARG = no variant
+mb_status launch_density_plane(Problem* p, int ik, const void* c, int nbands, int ld, const double* w, double* rho,
+                               int prec, hipStream_t s);
 size_t hartree_work_bytes(const Problem* p, bool with_vzg);
 mb_status launch_hartree(Problem* p, const double* rho, double* vh, void* vzg, void* work, hipStream_t s);
 // kernel choices of (k-point, class 0 FP64 / 1 FP32): validated and applied (class 1 also

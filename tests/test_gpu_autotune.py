@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-@pytest.mark.parametrize("cfg,prec,kinds", [("graphene", "fp64", {0, 2}), ("graphene", "fp32", {0, 2}),
+@pytest.mark.parametrize("cfg,prec,kinds", [("graphene", "fp64", {0, 2, 3}), ("graphene", "fp32", {0, 2, 3}),
                                             ("graphene_2x2", "fp32", {1, 2}), ("graphene_2x2", "fp64", {1, 2}),
                                             ("surface", "fp32", {2, 3}), ("surface", "fp64", {1, 2, 3})])
 def test_autotune_keeps_operator(cfg, prec, kinds):

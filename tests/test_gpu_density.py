@@ -4,7 +4,8 @@ density and the Coulomb potential in the (z, g) form) against the oracle:
 * density_accumulate against the oracle's explicit sums on a small cell (every plane,
   FP64 and FP32 vectors, accumulation over two calls), on the graphene-like slab and the
   128x64 surface slab at sampled Gauss planes, and the total charge against
-  sum_b w_b c_b^H S c_b with the library's own S;
+  sum_b w_b c_b^H S c_b with the library's own S; on the 128x64 grid the lane-split
+  kernel against the LDS-transform kernel on every plane;
 * hartree_potential against the oracle's direct double sums over Gauss points (every
   plane and grid frequency on a small cell and on the graphene-like slab's 36x36 grid);
   on the 128x64 grid V(z, g) at sampled frequencies against the oracle's z sums, and the
@@ -165,3 +166,29 @@ def test_hartree_surface_grid_sampled_frequencies():
     for q in (0, 600, nzq - 1):
         inv = np.fft.fft2(vz[q]).real  # sum_g V e^{-i g.rho}
         assert rel_err(v[q], inv) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_density_plane_kernel_matches_generic_kernel(monkeypatch, prec):
+    # the 128x64 grid's lane-split density kernel against the LDS-transform kernel on
+    # every Gauss plane of the surface slab (6 bands), accumulating into a non-zero density
+    d = workloads.surface()
+    print(f"[case] density plane vs generic {prec}", flush=True)
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    x = random_lib_block(84, 6, dm["nb"], dm["ng"], dm["ld"])
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    xt = torch.from_numpy(x).to(DEV).to(ct)
+    w = torch.tensor([2.0, 1.5, 1.0, 0.5, 0.25, 0.125], dtype=torch.float64, device=DEV)
+    N1, N2 = d["grid"]
+    base = torch.from_numpy(np.random.default_rng(85).uniform(0.0, 1.0, (dm["nzq"], N1, N2))).to(DEV)
+    out = {}
+    for kern in ("default", "generic"):
+        if kern == "generic":
+            monkeypatch.setenv("MBKS_DENSITY_KERNEL", "generic")
+        rho = base.clone()
+        p.density(0, xt, w, rho, prec)
+        torch.cuda.synchronize()
+        out[kern] = rho.cpu().numpy()
+    p.close()
+    assert rel_err(out["default"], out["generic"]) < 1e-13

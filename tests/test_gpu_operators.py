@@ -310,18 +310,26 @@ def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
                                                     ("surface", "fp64", 2, "split"),
                                                     ("member-00", "fp64", 3, "default"),
                                                     ("member-19", "fp64", 3, "default"),
-                                                    ("member-33", "fp32", 3, "default")])
+                                                    ("member-33", "fp32", 3, "default"),
+                                                    ("graphene", "fp64", 5, "plane0"),
+                                                    ("graphene", "fp64", 4, "plane1"),
+                                                    ("graphene", "fp32", 5, "plane0"),
+                                                    ("graphene", "fp32", 3, "plane1"),
+                                                    ("graphene", "bf16x3", 3, "plane0")])
 def test_local_kernels_match_generic_kernel(cfg, prec, nbands, kernel, monkeypatch):
     # the two-step line kernel of the larger grids (72^2, 45^2, 75^2, 80^2; and the
     # 128x64 grid in FP64 with MBKS_LOCAL_KERNEL=split) and the plane kernel of the
     # 128x64 grid (default there, one output row per Gauss plane, projected by the
-    # combine pass) against the generic LDS-stage kernel; all compute the same
-    # operator, and each is also checked against the oracle through the sampled rows
+    # combine pass) and of the 36x36 grid in both lane splits (chosen through
+    # mb_tune_set) against the generic LDS-stage kernel; all compute the same operator,
+    # and each is also checked against the oracle through the sampled rows
     d = workloads.batched_member(int(cfg[-2:])) if cfg.startswith("member") else workloads.CONFIGS[cfg]()
     print(f"[case] {kernel} local kernel vs generic {cfg} {prec}", flush=True)
     p, dm, _ = _setup(d, 0)
     x = random_lib_block(33, nbands, dm["nb"], dm["ng"], dm["ld"])
-    if kernel != "default":
+    if kernel.startswith("plane"):
+        p.tune_set(0, prec, local_kernel=3, plane_variant=int(kernel[-1]))
+    elif kernel != "default":
         monkeypatch.setenv("MBKS_LOCAL_KERNEL", kernel)
     y_k = _run(p, "hpsi", 0, x, prec)
     monkeypatch.setenv("MBKS_LOCAL_KERNEL", "generic")

@@ -154,10 +154,10 @@ def test_tune_choices_persist_through_the_cache_file(tmp_path):
     assert t2.tune_load(path) == 0
     assert t2.tune_load(str(tmp_path / "missing.json")) == 0
     # invalid choices and malformed files are refused
-    for bad in (dict(local_kernel=7), dict(local_kernel=0, lds_budget_kb=10), dict(local_kernel=3),
-                dict(local_kernel=0, combine_bands=3)):
+    for target, bad in ((g2, dict(local_kernel=7)), (g2, dict(local_kernel=0, lds_budget_kb=10)),
+                        (t2, dict(local_kernel=3)), (g2, dict(local_kernel=0, combine_bands=3))):
         with pytest.raises(mbks.MbError) as e:
-            g2.tune_set(0, "fp32", **bad)  # kind 3 on the 36x36 grid has no plane kernel
+            target.tune_set(0, "fp32", **bad)  # kind 3: the 72x72 grid has no plane kernel
         assert e.value.status == -1
     open(str(tmp_path / "bad.json"), "w").write('{\n "format": "mbks-tune-1",\n "entries": [\n  {"key": 3}\n ]\n}\n')
     with pytest.raises(mbks.MbError):
