@@ -313,12 +313,99 @@ def micro(seed: int = 7, nonlocal_: bool = True, nint: int = 7, mmax: int = 1,
     }
 
 
+def mp_line(n: int) -> list:
+    """Monkhorst-Pack fractions of 2 pi / L along the periodic axis."""
+    return [(2 * r - n - 1) / (2.0 * n) for r in range(1, n + 1)]
+
+
+def armchair_ribbon_atoms(na: int, a: float = 4.65) -> tuple:
+    """Carbon-like sites of an armchair ribbon with na dimer lines across x, periodic
+    along y with period sqrt(3) a (bond length d = a / sqrt(3)): line n sits at
+    x = (n - (na - 1)/2) a/2 and holds the two atoms y = 0, d (n even) or 1.5 d, 2.5 d
+    (n odd), so neighbouring lines bond at distance d.  Returns (period, [(x, y)])."""
+    d = a / math.sqrt(3.0)
+    out = []
+    for n in range(na):
+        x = (n - 0.5 * (na - 1)) * 0.5 * a
+        ys = (0.0, d) if n % 2 == 0 else (1.5 * d, 2.5 * d)
+        out += [(float(x), float(y)) for y in ys]
+    return 3.0 * d, out
+
+
+def _wire(name, na, x_half, nint_x, z_half, nint_z, ecut, ny, nk, nbands, offset):
+    rng = _rng(offset)
+    sp = _graphene_species(rng)
+    period, sites = armchair_ribbon_atoms(na)
+    return {
+        "kind": "wire",
+        "name": name,
+        "period": period,
+        "order": 4,
+        "breakpoints_x": uniform_breakpoints(-x_half, x_half, nint_x),
+        "breakpoints_z": graded_breakpoints(-z_half, z_half, nint_z),
+        "nq": 5,
+        "ny": ny,
+        "ecut": ecut,
+        "kpts": mp_line(nk),
+        "species": [sp],
+        "atoms": [{"species": 0, "pos": [x, y, 0.0]} for x, y in sites],
+        "nbands": nbands,
+    }
+
+
+def ribbon() -> dict:
+    """1D-periodic armchair ribbon (19 dimer lines, 38 atoms per period 8.05 bohr)
+    in the basis of two B-spline directions x 1D plane waves: 112 uniform intervals
+    on x in [-28, 28] (113 splines), 48 graded intervals on z in [-16, 16] (49
+    splines), the graphene-like cutoff 1/2 (k+G)^2 <= 161.9 (47 plane waves), a
+    64-point y grid, 4 k-points, 96 bands (n ~ 260,000 per k)."""
+    return _wire("armchair-ribbon-19", 19, 28.0, 112, 16.0, 48, 161.9, 64, 4, 96, 30)
+
+
+def ribbon_narrow() -> dict:
+    """A 3-line ribbon small enough for dense eigenvalues: 16 x 16 intervals on
+    [-8, 8]^2, 1/2 (k+G)^2 <= 15 (15 plane waves), 16-point y grid, 2 k-points,
+    16 bands (n ~ 4,300)."""
+    return _wire("armchair-ribbon-3", 3, 8.0, 16, 8.0, 16, 15.0, 16, 2, 16, 31)
+
+
+def wire_micro(seed: int = 0, nint: int = 6, ecut: float = 6.0, ny: int = 8, kfrac: float = 0.17,
+               natoms: int = 2, nonlocal_: bool = True, period: float = 4.0) -> dict:
+    """A very small 1D-periodic cell for brute-force checks: seeded wells on
+    [-5, 5]^2 with nint intervals per direction."""
+    rng = _rng(200 + seed)
+    species, atoms = [], []
+    for _ in range(natoms):
+        gauss = [[-float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.8, 1.5))]]
+        species.append(_kb_species(rng, gauss) if nonlocal_ else {"gauss": gauss, "nonlocal": False})
+        atoms.append({"species": len(species) - 1,
+                      "pos": [float(rng.uniform(-1.5, 1.5)), float(rng.uniform(0.0, period)),
+                              float(rng.uniform(-1.0, 1.0))]})
+    return {
+        "kind": "wire",
+        "name": f"wire-micro-{seed}",
+        "period": period,
+        "order": 4,
+        "breakpoints_x": uniform_breakpoints(-5.0, 5.0, nint),
+        "breakpoints_z": graded_breakpoints(-5.0, 5.0, nint),
+        "nq": 5,
+        "ny": ny,
+        "ecut": ecut,
+        "kpts": [kfrac],
+        "species": species,
+        "atoms": atoms,
+        "nbands": 4,
+    }
+
+
 CONFIGS = {
     "tiny": tiny,
     "graphene": graphene,
     "graphene_uspp": graphene_uspp,
     "graphene_2x2": graphene_2x2,
     "surface": surface,
+    "ribbon": ribbon,
+    "ribbon_narrow": ribbon_narrow,
 }
 
 
