@@ -131,6 +131,52 @@ mb_status mb_init(int* ndevices);
 mb_status mb_problem_create(const mb_desc* desc, int device, mb_problem** out);
 mb_status mb_problem_destroy(mb_problem* p);
 
+/* ---- the 1D-periodic form --------------------------------------------------
+ * Two B-spline directions and plane waves along the periodic one (the extension named
+ * at the end of Sec. II.B.2, for wires and ribbons without a vacuum supercell):
+ *   chi_{G,i,j}(x, y, z) = L^{-1/2} e^{i(k+G) y} B_i(x) B_j(z),  G = 2 pi m / L,
+ *   1/2 (k+G)^2 <= ecut,  k = kfrac 2 pi / L,
+ * with hard-wall spline sets along x and z (same order and Gauss points per interval).
+ *   S = I_G (x) S_x (x) S_z
+ *   T = 1/2 [D_x (x) S_z + S_x (x) D_z + (k+G)^2 S_x (x) S_z]   per G
+ *   V_loc: the Gaussian wells of the species (summed over the images along y) sampled at
+ *          (x_q, y_n, z_p), y_n = n L / ny, and applied through ny-point transforms along y
+ *   V_NL = sum_p E_p |beta_p><beta_p| with the s, p_x, p_y, p_z projectors of mb_species,
+ *          <G,i,j|beta_p> = F_p(G) X_p(i) Z_p(j)  (three one-dimensional integrals)
+ * Vectors: x[band][i][j][G], rows i * N_bz + j, row stride ld >= N_G (the slab layout with
+ * N_b = N_bx N_bz rows).  Handles from mb_wire_create work with mb_problem_destroy,
+ * mb_problem_dims (N_b = N_bx N_bz, nzq = z Gauss points), mb_problem_gvectors (m as
+ * (m, 0) pairs, |k+G|^2), hpsi_apply, spsi_apply, s_solve and lanczos_lowest (FP64;
+ * MB_FP32 and MB_BF16X3 run the local and nonlocal parts in FP32, the projections on the
+ * vector units).  Every other call returns MB_ERR_INVALID_ARG for them.  Augmentation
+ * charges are not supported in this form (MB_ERR_INVALID_ARG). */
+typedef struct {
+    double period;                /* L along y, bohr (> 0) */
+    int32_t order;                /* spline order (4: the GPU kernels are cubic) */
+    int32_t nbreak_x;             /* breakpoints along x, strictly increasing (>= 2) */
+    const double* breakpoints_x;
+    int32_t nbreak_z;             /* breakpoints along z */
+    const double* breakpoints_z;
+    int32_t nq;                   /* Gauss points per interval in both directions, 1..8 */
+    int32_t ny;                   /* transform length along y: 8, 12, 16, 24, 32, 48, 64 or 128;
+                                     2 m_max + 1 <= ny */
+    double ecut;                  /* plane waves with 1/2 (k+G)^2 <= ecut (Ha) */
+    int32_t nk;
+    const double* kfrac;          /* nk fractions of 2 pi / L */
+    int32_t nspecies;
+    const mb_species* species;
+    int32_t natoms;
+    const mb_atom* atoms;         /* positions (x, y, z), bohr */
+} mb_wire_desc;
+
+/* Build the tables of a 1D-periodic problem (as mb_problem_create: host tables, then
+ * upload to `device`, device < 0 host-only).  MB_ERR_INVALID_ARG for an inconsistent
+ * description, MB_ERR_NOT_SPD if S_x or S_z is singular. */
+mb_status mb_wire_create(const mb_wire_desc* desc, int device, mb_problem** out);
+/* Sizes of a 1D-periodic problem: splines along x and z, Gauss points along x and z,
+ * transform length along y.  MB_ERR_INVALID_ARG for a slab problem. */
+mb_status mb_wire_dims(const mb_problem* p, int64_t* nbx, int64_t* nbz, int64_t* nxq, int64_t* nzq, int64_t* ny);
+
 /* Sizes for k-point ik: N_G, N_b, recommended ld, number of projectors, number
  * of Gauss points N_q = nq * N_int. Any output pointer may be NULL. */
 mb_status mb_problem_dims(const mb_problem* p, int ik, int64_t* ng, int64_t* nb, int64_t* ld,

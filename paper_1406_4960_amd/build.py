@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmbks.so")
 SOURCES = ["setup.cpp", "capi.hip", "k_local.hip", "k_local_lines.hip", "k_local_split.hip", "k_local_plane.hip", "k_zbanded.hip", "k_zcombine.hip", "k_nonlocal.hip", "k_nonlocal_mfma.hip", "k_uspp.hip", "k_density.hip", "tune_cache.cpp", "k_dense.hip",
-           "lanczos.hip", "batch.hip"]
+           "lanczos.hip", "batch.hip", "wire.cpp", "k_wire.hip"]
 ARCH = "gfx950"
 
 

@@ -252,6 +252,8 @@ mb_status mb_batch_create(mb_problem* const* probs, const int* iks, int nitems, 
         mb_status st = MB_OK;
         if (!p)
             st = set_error(MB_ERR_INVALID_ARG, what + ": problem is NULL");
+        else if (p->wire)
+            st = set_error(MB_ERR_INVALID_ARG, what + ": not available for the 1D-periodic form");
         else if (p->device < 0)
             st = set_error(MB_ERR_NO_DEVICE, what + ": host-only problem");
         else if (iks[t] < 0 || iks[t] >= (int)p->kp.size())

@@ -36,12 +36,6 @@ mb_status upload_f32(float** dst, const std::vector<T>& src) {
     return upload_vec(dst, f);
 }
 
-#define MB_TRY(call)                       \
-    do {                                   \
-        mb_status s_ = (call);             \
-        if (s_ != MB_OK) return s_;        \
-    } while (0)
-
 mb_status upload_twiddles(int n, void** d64, void** d32) {
     std::vector<cx<double>> t(n);
     std::vector<cx<float>> tf(n);
@@ -140,6 +134,12 @@ mb_status check_vec_args(const mb_problem* h, int ik, const void* in, const void
     if (ld < p.kp[ik].ng || ld > (1 << 24)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": ld < N_G");
     if (nbands > 0 && (!in || !out)) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": NULL vector");
     if (p.order != 4) return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": GPU kernels support order 4 only");
+    return MB_OK;
+}
+
+mb_status refuse_wire(const mb_problem* h, const char* what) {
+    if (h && h->p.wire)
+        return set_error(MB_ERR_INVALID_ARG, std::string(what) + ": not available for the 1D-periodic form");
     return MB_OK;
 }
 
@@ -268,6 +268,10 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
                   const HWork* ext) {
     if (nbands == 0) return MB_OK;
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;  // local / combine precision
+    if (p->wire) {
+        if (ext) return set_error(MB_ERR_INVALID_ARG, "apply_h: caller work buffers are not used by the 1D-periodic form");
+        return wire_apply_h(p, ik, c, y, sy, nbands, ld, lp, s);
+    }
     KPoint& kp = p->kp[ik];
     void* part = ext ? ext->part : nullptr;
     if (!ext) {
@@ -433,12 +437,60 @@ mb_status mb_problem_create(const mb_desc* desc, int device, mb_problem** out) {
     return MB_OK;
 }
 
+mb_status mb_wire_create(const mb_wire_desc* desc, int device, mb_problem** out) {
+    if (!out) return set_error(MB_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    auto* h = new mb_problem;
+    mb_status st = mb::build_wire(desc, &h->p);
+    if (st != MB_OK) {
+        mb::free_wire(&h->p);
+        delete h;
+        return st;
+    }
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+            mb::free_wire(&h->p);
+            delete h;
+            return set_error(MB_ERR_NO_DEVICE, "no such GPU");
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            mb::free_wire(&h->p);
+            delete h;
+            return set_error(MB_ERR_HIP, "hipSetDevice failed");
+        }
+        h->p.device = device;
+        st = mb::upload_wire(&h->p);
+        if (st != MB_OK) {
+            mb::free_all(&h->p);
+            mb::free_wire(&h->p);
+            delete h;
+            return st;
+        }
+    }
+    *out = h;
+    return MB_OK;
+}
+
+mb_status mb_wire_dims(const mb_problem* h, int64_t* nbx, int64_t* nbz, int64_t* nxq, int64_t* nzq, int64_t* ny) {
+    if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
+    const mb::WireTables* w = h->p.wire;
+    if (!w) return set_error(MB_ERR_INVALID_ARG, "mb_wire_dims: not a 1D-periodic problem");
+    if (nbx) *nbx = w->x.nb;
+    if (nbz) *nbz = w->z.nb;
+    if (nxq) *nxq = w->x.nzq;
+    if (nzq) *nzq = w->z.nzq;
+    if (ny) *ny = w->ny;
+    return MB_OK;
+}
+
 mb_status mb_problem_destroy(mb_problem* h) {
     if (!h) return MB_OK;
     if (h->p.device >= 0) {
         (void)hipDeviceSynchronize();
         mb::free_all(&h->p);
     }
+    mb::free_wire(&h->p);
     delete h;
     return MB_OK;
 }
@@ -465,6 +517,7 @@ mb_status mb_problem_gvectors(const mb_problem* h, int ik, int32_t* m, double* k
 }
 
 mb_status mb_problem_zrule(const mb_problem* h, double* zq, double* wq) {
+    if (mb::refuse_wire(h, "mb_problem_zrule") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
     if (zq) std::memcpy(zq, h->p.zq.data(), h->p.zq.size() * sizeof(double));
     if (wq) std::memcpy(wq, h->p.wq.data(), h->p.wq.size() * sizeof(double));
@@ -472,6 +525,7 @@ mb_status mb_problem_zrule(const mb_problem* h, double* zq, double* wq) {
 }
 
 mb_status mb_problem_zbands(const mb_problem* h, double* sband, double* dband) {
+    if (mb::refuse_wire(h, "mb_problem_zbands") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
     if (sband) std::memcpy(sband, h->p.sband.data(), h->p.sband.size() * sizeof(double));
     if (dband) std::memcpy(dband, h->p.dband.data(), h->p.dband.size() * sizeof(double));
@@ -479,6 +533,7 @@ mb_status mb_problem_zbands(const mb_problem* h, double* sband, double* dband) {
 }
 
 mb_status mb_problem_projectors(const mb_problem* h, int ik, double* F, double* Z, double* E) {
+    if (mb::refuse_wire(h, "mb_problem_projectors") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h) return set_error(MB_ERR_INVALID_ARG, "problem is NULL");
     if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "ik out of range");
     const auto& p = h->p;
@@ -495,12 +550,14 @@ mb_status mb_problem_projectors(const mb_problem* h, int ik, double* F, double* 
 }
 
 mb_status mb_problem_augmentation(const mb_problem* h, double* q) {
+    if (mb::refuse_wire(h, "mb_problem_augmentation") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !q) return set_error(MB_ERR_INVALID_ARG, "NULL argument");
     std::memcpy(q, h->p.Qp.data(), h->p.Qp.size() * sizeof(double));
     return MB_OK;
 }
 
 mb_status mb_problem_set_potential(mb_problem* h, const double* v) {
+    if (mb::refuse_wire(h, "mb_problem_set_potential") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !v) return set_error(MB_ERR_INVALID_ARG, "NULL argument");
     auto& p = h->p;
     if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, "host-only problem");
@@ -531,6 +588,7 @@ mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int6
                              mb_precision prec, void* stream) {
     mb_status st = mb::check_vec_args(h, ik, c, y, nbands, ld, "hpsi_apply_noalloc");
     if (st != MB_OK) return st;
+    if (mb::refuse_wire(h, "hpsi_apply_noalloc") != MB_OK) return MB_ERR_INVALID_ARG;
     if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
         return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_noalloc: unknown precision");
     mb::Problem* p = &h->p;
@@ -575,6 +633,7 @@ mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int6
 }
 
 mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t ld, int lock) {
+    if (mb::refuse_wire(h, "mb_problem_reserve") != MB_OK) return MB_ERR_INVALID_ARG;
     mb::Problem* p = mb::problem_of(h);
     if (!p) return set_error(MB_ERR_INVALID_ARG, "mb_problem_reserve: problem is NULL");
     if (p->device < 0) return set_error(MB_ERR_NO_DEVICE, "mb_problem_reserve: host-only problem");
@@ -599,6 +658,7 @@ mb_status mb_problem_reserve(mb_problem* h, int ik, int64_t max_bands, int64_t l
 }
 
 mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, void* stream, mb_tune_info* info) {
+    if (mb::refuse_wire(h, "mb_autotune") != MB_OK) return MB_ERR_INVALID_ARG;
     mb::Problem* p = mb::problem_of(h);
     if (!p) return set_error(MB_ERR_INVALID_ARG, "mb_autotune: problem is NULL");
     if (p->device < 0) return set_error(MB_ERR_NO_DEVICE, "mb_autotune: host-only problem");
@@ -741,6 +801,7 @@ mb_status mb_autotune(mb_problem* h, int ik, int64_t nbands, mb_precision prec, 
 }
 
 mb_status mb_tune_get(const mb_problem* h, int ik, mb_precision prec, mb_tune_info* info) {
+    if (mb::refuse_wire(h, "mb_tune_get") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !info) return set_error(MB_ERR_INVALID_ARG, "mb_tune_get: NULL argument");
     if (ik < 0 || ik >= (int)h->p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_tune_get: ik out of range");
     if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
@@ -756,6 +817,7 @@ mb_status mb_tune_get(const mb_problem* h, int ik, mb_precision prec, mb_tune_in
 }
 
 mb_status mb_tune_set(mb_problem* h, int ik, mb_precision prec, const mb_tune_info* info) {
+    if (mb::refuse_wire(h, "mb_tune_set") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !info) return set_error(MB_ERR_INVALID_ARG, "mb_tune_set: NULL argument");
     mb::Problem& p = h->p;
     if (ik < 0 || ik >= (int)p.kp.size()) return set_error(MB_ERR_INVALID_ARG, "mb_tune_set: ik out of range");
@@ -766,11 +828,13 @@ mb_status mb_tune_set(mb_problem* h, int ik, mb_precision prec, const mb_tune_in
 }
 
 mb_status mb_tune_save(const mb_problem* h, const char* path) {
+    if (mb::refuse_wire(h, "mb_tune_save") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !path) return set_error(MB_ERR_INVALID_ARG, "mb_tune_save: NULL argument");
     return mb::tune_save(&h->p, path);
 }
 
 mb_status mb_tune_load(mb_problem* h, const char* path, int* applied) {
+    if (mb::refuse_wire(h, "mb_tune_load") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h || !path) return set_error(MB_ERR_INVALID_ARG, "mb_tune_load: NULL argument");
     return mb::tune_load(&h->p, path, applied);
 }
@@ -785,6 +849,8 @@ mb_status spsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
     if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
         return set_error(MB_ERR_INVALID_ARG, "spsi_apply: c and y overlap");
     if (nbands == 0) return MB_OK;
+    if (h->p.wire)
+        return mb::wire_spsi(&h->p, ik, c, y, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
     return mb::launch_spsi(&h->p, ik, c, y, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
 }
 
@@ -798,6 +864,8 @@ mb_status s_solve(mb_problem* h, int ik, const void* r, void* x, int64_t nbands,
     if (nbands > 0 && r != x && mb::ranges_overlap(r, bytes, x, bytes))
         return set_error(MB_ERR_INVALID_ARG, "s_solve: r and x partially overlap");
     if (nbands == 0) return MB_OK;
+    if (h->p.wire)
+        return mb::wire_ssolve(&h->p, ik, r, x, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
     return mb::launch_ssolve(&h->p, ik, r, x, (int)nbands, (int)ld, prec == MB_FP64 ? 0 : 1, (hipStream_t)stream);
 }
 
@@ -805,6 +873,7 @@ mb_status density_accumulate(mb_problem* h, int ik, const void* c, int64_t nband
                              double* rho, mb_precision prec, void* stream) {
     mb_status st = mb::check_vec_args(h, ik, c, rho, nbands, ld, "density_accumulate");
     if (st != MB_OK) return st;
+    if (mb::refuse_wire(h, "density_accumulate") != MB_OK) return MB_ERR_INVALID_ARG;
     if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
         return set_error(MB_ERR_INVALID_ARG, "density_accumulate: unknown precision");
     if (nbands > 0 && !w) return set_error(MB_ERR_INVALID_ARG, "density_accumulate: NULL weights");
@@ -819,6 +888,7 @@ mb_status density_accumulate(mb_problem* h, int ik, const void* c, int64_t nband
 }
 
 mb_status hartree_potential(mb_problem* h, const double* rho, double* vh, void* vzg, void* stream) {
+    if (mb::refuse_wire(h, "hartree_potential") != MB_OK) return MB_ERR_INVALID_ARG;
     if (!h) return set_error(MB_ERR_INVALID_ARG, "hartree_potential: problem is NULL");
     mb::Problem& p = h->p;
     if (p.device < 0) return set_error(MB_ERR_NO_DEVICE, "hartree_potential: host-only problem");

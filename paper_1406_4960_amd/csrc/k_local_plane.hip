@@ -21,6 +21,7 @@
 
 #include "cplx.h"
 #include "fft_line.h"
+#include "lane_fft.h"
 #include "mbks_internal.h"
 
 namespace mb {
@@ -49,130 +50,6 @@ struct PlaneArgs {
     int nbands, ld, nint, nq, nb, nrows, nzq;
     T inv_n;
 };
-
-template <int Q>
-__device__ __forceinline__ int bitrev_lane(int l) {
-    int r = 0;
-#pragma unroll
-    for (int b = 1; b < Q; b <<= 1) r = (r << 1) | ((l & b) ? 1 : 0);
-    return r;
-}
-
-// Lane exchange v <- v of physical lane (p xor M) with DPP moves (VALU, no LDS
-// traffic): xor 1 and 2 are quad permutations, xor 8 the half-row rotation of a
-// 16-lane row, xor 4 two masked row shifts (lanes 0-3 and 8-11 of a row take
-// p + 4, lanes 4-7 and 12-15 take p - 4).
-template <int M>
-__device__ __forceinline__ int lane_xor_i32(int v) {
-    if constexpr (M == 1) {
-        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
-    } else if constexpr (M == 2) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
-    } else if constexpr (M == 4) {
-        const int t = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);  // row_shl:4, banks 0, 2
-        return __builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false);         // row_shr:4, banks 1, 3
-    } else if constexpr (M == 8) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true);  // row_ror:8
-    } else {
-        return __shfl_xor(v, M);
-    }
-}
-
-// Lanes of a line of Q <= 16 points within a 16-lane row: logical lane bits 0, 1, 2,
-// 3 sit on physical bits 0, 1, 3, 2, so lines of up to 8 lanes exchange only through
-// single DPP moves (xor 1, 2, 8).
-template <int Q>
-struct LaneMap {
-    static_assert(Q == 2 || Q == 4 || Q == 8 || Q == 16, "lanes per line");
-    // logical lane of physical position p (0..15) in its line
-    __device__ static int lane(int p) {
-        if constexpr (Q <= 4) return p & (Q - 1);
-        else if constexpr (Q == 8) return (p & 3) | (((p >> 3) & 1) << 2);
-        else return (p & 3) | (((p >> 3) & 1) << 2) | (((p >> 2) & 1) << 3);
-    }
-    // line of physical position p within its 16-lane row
-    __device__ static int line(int p) {
-        if constexpr (Q <= 4) return p / Q;
-        else if constexpr (Q == 8) return (p >> 2) & 1;
-        else return 0;
-    }
-    // physical xor mask of logical mask m
-    static constexpr int phys(int m) { return m == 4 ? 8 : m == 8 ? 4 : m; }
-};
-
-template <int M>
-__device__ __forceinline__ float lane_xor(float v) {
-    return __int_as_float(lane_xor_i32<M>(__float_as_int(v)));
-}
-
-template <int M>
-__device__ __forceinline__ double lane_xor(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = lane_xor_i32<M>((int)(b & 0xffffffffll));
-    const int hi = lane_xor_i32<M>((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// exchange with the lane of logical index (l xor M) of the same line
-template <int M, int Q, typename T>
-__device__ __forceinline__ cx<T> lane_xor_cx(cx<T> v) {
-    constexpr int P = LaneMap<Q>::phys(M);
-    return mk<T>(lane_xor<P>(v.x), lane_xor<P>(v.y));
-}
-
-// w_N^{sign e} from the table exp(+2 pi i k / N)
-template <typename T, int SIGN>
-__device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, int e) {
-    const cx<T> w = tw[e];
-    return SIGN > 0 ? w : mk<T>(w.x, -w.y);
-}
-
-// Radix-2 decimation-in-frequency network over the Q lanes of a line (lane l of the
-// line = l): natural lane order in, lane l ends with the outputs of index bitrev(l).
-// Each stage of both networks is one fused form for every lane: y = u + s x with
-// s = -1 on the upper lane of a pair (bit m of l set) and +1 on the lower, and the
-// stage twiddle on the upper lane only (w = 1 on the lower lanes and in the last
-// stage of the DIF network / the first of the DIT network, which have none).
-template <typename T, int L, int Q, int N, int SIGN, int QS = Q>
-__device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
-    if constexpr (QS >= 2) {
-        constexpr int m = QS >> 1;
-        const bool h = (l & m) != 0;
-        const T sg = h ? (T)-1 : (T)1;
-#pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
-            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
-        }
-        if constexpr (QS > 2) {
-            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
-#pragma unroll
-            for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
-        }
-        dif_lanes<T, L, Q, N, SIGN, QS / 2>(x, l, tw);
-    }
-}
-
-// The mirrored decimation-in-time network: bit-reversed lanes in, natural order out.
-template <typename T, int L, int Q, int N, int SIGN, int QS = 2>
-__device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw) {
-    if constexpr (QS <= Q) {
-        constexpr int m = QS >> 1;
-        const bool h = (l & m) != 0;
-        const T sg = h ? (T)-1 : (T)1;
-        if constexpr (QS > 2) {
-            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
-#pragma unroll
-            for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
-        }
-#pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
-            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
-        }
-        dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw);
-    }
-}
 
 // LDS row pitch and column position: columns are stored in blocks of L2 with PADB
 // elements after each block, so the Q2 lanes of a row write their blocks to different banks

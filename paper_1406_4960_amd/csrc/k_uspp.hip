@@ -39,6 +39,7 @@ size_t proj_elem(int prec) { return prec == 1 ? sizeof(cx<float>) : sizeof(cx<do
 }  // namespace
 
 mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec, hipStream_t s) {
+    if (p->wire) return wire_spsi(p, ik, c, y, nbands, ld, prec, s);
     if (!p->uspp) return launch_spsi_banded(p, ik, c, y, nbands, ld, prec, s);
     if (nbands == 0) return MB_OK;
     KPoint& kp = p->kp[ik];
@@ -51,6 +52,7 @@ mb_status launch_spsi(Problem* p, int ik, const void* c, void* y, int nbands, in
 }
 
 mb_status launch_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s) {
+    if (p->wire) return wire_ssolve(p, ik, r, x, nbands, ld, prec, s);
     if (!p->uspp) return launch_ssolve_banded(p, ik, r, x, nbands, ld, prec, s);
     if (nbands == 0) return MB_OK;
     KPoint& kp = p->kp[ik];

@@ -508,12 +508,14 @@ mb_status launch_combine_batch(const std::vector<BatchItem>& items, int prec, Ta
 
 mb_status launch_spsi_banded(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec,
                              hipStream_t s) {
+    if (p->wire) return wire_spsi(p, ik, c, y, nbands, ld, prec, s);
     if (prec == 1) return combine_impl<float, float>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
     return combine_impl<double, double>(p, ik, c, nullptr, nullptr, nullptr, y, nbands, ld, s);
 }
 
 mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec,
                                hipStream_t s) {
+    if (p->wire) return wire_ssolve(p, ik, r, x, nbands, ld, prec, s);
     const KPoint& kp = p->kp[ik];
     dim3 grid((ld + 63) / 64, nbands);
     StageScope ts_(MB_STAGE_SSOLVE, s, nbands);
@@ -532,6 +534,7 @@ mb_status launch_ssolve_banded(Problem* p, int ik, const void* r, void* x, int n
 }
 
 mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s) {
+    if (p->wire) return wire_prec_factor(p, ik, sigma, s);
     KPoint& kp = p->kp[ik];
     if (kp.d_pfac && kp.pfac_sigma == sigma) return MB_OK;
     if (!kp.d_pfac) MB_HIP_TRY(hipMalloc(&kp.d_pfac, (size_t)p->nb * KORD * kp.ld * sizeof(double)));
@@ -554,6 +557,7 @@ mb_status launch_prec_factor(Problem* p, int ik, double sigma, hipStream_t s) {
 
 mb_status launch_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta,
                             const int32_t* sel, void* x, int nvec, int ld, hipStream_t s) {
+    if (p->wire) return wire_prec_apply(p, ik, h, sv, theta, sel, x, nvec, ld, s);
     const KPoint& kp = p->kp[ik];
     if (!kp.d_pfac || ld != kp.ld) return set_error(MB_ERR_INVALID_ARG, "preconditioner not built for this ld");
     dim3 grid((ld + 63) / 64, nvec);

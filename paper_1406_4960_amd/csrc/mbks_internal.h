@@ -26,6 +26,39 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Tables of one B-spline direction (hard-wall set of order kappa on clamped knots):
+// Gauss points and weights, kept-spline values bval[q][t] = B_{s-1+t}(z_q) on the
+// interval s of point q (zero for dropped splines), w_q bval, derivatives, and the
+// banded overlap, derivative overlap and Cholesky factor, band[i][d].
+struct SplineDir {
+    int nint = 0, nb = 0, nq = 0, nzq = 0;
+    std::vector<double> bp, zq, wq, bval, wbval, dval, sband, dband, lband;
+};
+
+// The 1D-periodic form: B-splines along x and z, plane waves along the period L in y.
+// Vector rows are (i, j) = i * nbz + j (x spline i, z spline j), G fastest.
+struct WireTables {
+    double period = 0.0;
+    int ny = 0;              // FFT length along y
+    SplineDir x, z;
+    std::vector<double> Xp, Zp;             // np x nbx, np x nbz projector factors
+    std::vector<int32_t> xwin, zwin;        // np x 2: first, last non-negligible row
+    std::vector<int32_t> ploff, plist;      // per x row i: projectors whose x window holds i
+    std::vector<double> Uz, lamz;           // D_z u = lambda S_z u, Uz[j][j'] S_z-orthonormal columns
+    // device copies (T: double and float)
+    double *d_bx = nullptr, *d_wbx = nullptr, *d_bz = nullptr, *d_wbz = nullptr;
+    float *d_bxf = nullptr, *d_wbxf = nullptr, *d_bzf = nullptr, *d_wbzf = nullptr;
+    double *d_sx = nullptr, *d_dx = nullptr, *d_lx = nullptr;
+    double *d_sz = nullptr, *d_dz = nullptr, *d_lz = nullptr;
+    double *d_X = nullptr, *d_Z = nullptr;
+    float *d_Xf = nullptr, *d_Zf = nullptr;
+    int32_t *d_xwin = nullptr, *d_zwin = nullptr, *d_ploff = nullptr, *d_plist = nullptr;
+    double *d_Uz = nullptr, *d_lamz = nullptr;
+    double* d_V = nullptr;   // [p][q][n] = V(x_q, y_n, z_p) / ny
+    float* d_Vf = nullptr;
+    void *d_tw = nullptr, *d_twf = nullptr;  // exp(+2 pi i k / ny)
+};
+
 // Per-k-point tables and the device workspaces of calls on this k-point (calls on
 // different k-points of one problem may run concurrently on different streams).
 struct KPoint {
@@ -131,6 +164,9 @@ struct Problem {
     double* d_zq = nullptr; double* d_wq = nullptr; double* d_gnorm = nullptr;
     Workspace ws_hartree;
 
+    // the 1D-periodic form (null for the slab): then nb = nbx * nbz rows, N1 = ny, and
+    // nzq, nq refer to the z direction
+    WireTables* wire = nullptr;
 };
 
 // stage timer: brackets one kernel launch with events when enabled
@@ -152,10 +188,34 @@ mb_status set_error(mb_status s, const std::string& msg);
             return ::mb::set_error(MB_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define MB_TRY(call)                \
+    do {                            \
+        mb_status s_ = (call);      \
+        if (s_ != MB_OK) return s_; \
+    } while (0)
+
 // host set-up (setup.cpp)
 mb_status build_tables(const mb_desc* d, Problem* p);
+// one B-spline direction: knots, Gauss rule, spline tables, banded overlap / derivative
+// overlap and the Cholesky factor of the overlap (name: for the error message)
+mb_status build_spline_dir(const std::vector<double>& bp, int order, int nq, SplineDir* out, const char* name);
 bool fft_plan(int n, FftPlan* plan);
 int recommended_ld(int ng);
+
+// the 1D-periodic form (wire.cpp: host tables; k_wire.hip: upload and kernels)
+mb_status build_wire(const mb_wire_desc* d, Problem* p);
+mb_status upload_wire(Problem* p);
+void free_wire(Problem* p);  // device tables (when on a device) and the host tables
+// y = H c (sy = S c if non-null); lp 0 FP64, 1 FP32 complex64, 2 FP32 arithmetic on complex128
+mb_status wire_apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int lp,
+                       hipStream_t s);
+mb_status wire_spsi(Problem* p, int ik, const void* c, void* y, int nbands, int ld, int prec, hipStream_t s);
+mb_status wire_ssolve(Problem* p, int ik, const void* r, void* x, int nbands, int ld, int prec, hipStream_t s);
+mb_status wire_prec_factor(Problem* p, int ik, double sigma, hipStream_t s);
+mb_status wire_prec_apply(Problem* p, int ik, const void* h, const void* sv, const double* theta, const int32_t* sel,
+                          void* x, int nvec, int ld, hipStream_t s);
+// MB_ERR_INVALID_ARG with a message when h is a 1D-periodic problem (calls of the slab only)
+mb_status refuse_wire(const mb_problem* h, const char* what);
 
 // device upload (capi.hip)
 bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb);

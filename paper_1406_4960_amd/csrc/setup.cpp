@@ -103,6 +103,97 @@ bool fft_plan(int n, FftPlan* plan) {
 
 int recommended_ld(int ng) { return (ng + 15) / 16 * 16; }
 
+mb_status build_spline_dir(const std::vector<double>& bp, int K, int nq, SplineDir* out, const char* name) {
+    SplineDir& d = *out;
+    d.bp = bp;
+    d.nint = (int)bp.size() - 1;
+    d.nb = d.nint + K - 3;
+    d.nq = nq;
+    d.nzq = nq * d.nint;
+    if (d.nint < 1 || d.nb < 1) return set_error(MB_ERR_INVALID_ARG, "no basis spline left after the hard walls");
+    // clamped knot sequence
+    std::vector<double> tau;
+    for (int j = 0; j < K - 1; ++j) tau.push_back(bp.front());
+    for (double v : bp) tau.push_back(v);
+    for (int j = 0; j < K - 1; ++j) tau.push_back(bp.back());
+
+    // Gauss rule and spline tables per interval
+    std::vector<double> gx, gw;
+    gauss_legendre(nq, gx, gw);
+    d.zq.resize(d.nzq);
+    d.wq.resize(d.nzq);
+    d.bval.assign((size_t)d.nzq * K, 0.0);
+    d.wbval.assign((size_t)d.nzq * K, 0.0);
+    d.dval.assign((size_t)d.nzq * K, 0.0);
+    for (int s = 0; s < d.nint; ++s) {
+        double a = bp[s], b = bp[s + 1];
+        double h = 0.5 * (b - a), mid = 0.5 * (a + b);
+        int l = K - 1 + s;
+        for (int j = 0; j < nq; ++j) {
+            int q = s * nq + j;
+            double z = mid + h * gx[j];
+            d.zq[q] = z;
+            d.wq[q] = h * gw[j];
+            double v[8], vl[8];
+            nonzero_splines(tau, l, K, z, v);       // full indices s .. s+K-1
+            nonzero_splines(tau, l, K - 1, z, vl);  // order K-1: full indices s+1 .. s+K-1
+            for (int r = 0; r < K; ++r) {
+                int full = s + r;
+                int kept = full - 1;
+                double val = v[r];
+                // derivative, eq. 3
+                double dv = 0.0;
+                double d1 = tau[full + K - 1] - tau[full];
+                double d2 = tau[full + K] - tau[full + 1];
+                if (r >= 1 && d1 > 0) dv += (K - 1) / d1 * vl[r - 1];
+                if (r <= K - 2 && d2 > 0) dv -= (K - 1) / d2 * vl[r];
+                if (kept < 0 || kept >= d.nb) { val = 0.0; dv = 0.0; }
+                d.bval[(size_t)q * K + r] = val;
+                d.wbval[(size_t)q * K + r] = d.wq[q] * val;
+                d.dval[(size_t)q * K + r] = dv;
+            }
+        }
+    }
+
+    // banded overlap and derivative-overlap matrices, band[i][dd] = M[i][i + dd]
+    d.sband.assign((size_t)d.nb * K, 0.0);
+    d.dband.assign((size_t)d.nb * K, 0.0);
+    for (int s = 0; s < d.nint; ++s)
+        for (int j = 0; j < nq; ++j) {
+            int q = s * nq + j;
+            for (int r1 = 0; r1 < K; ++r1)
+                for (int r2 = r1; r2 < K; ++r2) {
+                    int i = s - 1 + r1, i2 = s - 1 + r2;
+                    if (i < 0 || i2 >= d.nb) continue;
+                    int dd = r2 - r1;
+                    d.sband[(size_t)i * K + dd] += d.wq[q] * d.bval[(size_t)q * K + r1] * d.bval[(size_t)q * K + r2];
+                    d.dband[(size_t)i * K + dd] += d.wq[q] * d.dval[(size_t)q * K + r1] * d.dval[(size_t)q * K + r2];
+                }
+        }
+
+    // banded Cholesky of the overlap, lband[i][dd] = L[i][i - dd]
+    d.lband.assign((size_t)d.nb * K, 0.0);
+    auto S = [&](int i, int j) -> double {  // symmetric access, |i-j| < K
+        if (i > j) std::swap(i, j);
+        return d.sband[(size_t)i * K + (j - i)];
+    };
+    auto L = [&](int i, int j) -> double& { return d.lband[(size_t)i * K + (i - j)]; };
+    for (int i = 0; i < d.nb; ++i) {
+        int j0 = std::max(0, i - (K - 1));
+        for (int j = j0; j <= i; ++j) {
+            double sum = S(i, j);
+            for (int k = std::max(j0, j - (K - 1)); k < j; ++k) sum -= L(i, k) * L(j, k);
+            if (j == i) {
+                if (!(sum > 0)) return set_error(MB_ERR_NOT_SPD, std::string(name) + " is not positive definite");
+                L(i, i) = std::sqrt(sum);
+            } else {
+                L(i, j) = sum / L(j, j);
+            }
+        }
+    }
+    return MB_OK;
+}
+
 mb_status build_tables(const mb_desc* d, Problem* p) {
     if (!d) return set_error(MB_ERR_INVALID_ARG, "desc is NULL");
     if (d->order < 2 || d->order > 6) return set_error(MB_ERR_INVALID_ARG, "order must be 2..6");
@@ -145,86 +236,15 @@ mb_status build_tables(const mb_desc* d, Problem* p) {
     }
 
     const int K = p->order;
-    // clamped knot sequence
-    std::vector<double> tau;
-    for (int j = 0; j < K - 1; ++j) tau.push_back(p->bp.front());
-    for (double v : p->bp) tau.push_back(v);
-    for (int j = 0; j < K - 1; ++j) tau.push_back(p->bp.back());
-
-    // Gauss rule and spline tables per interval
-    std::vector<double> gx, gw;
-    gauss_legendre(p->nq, gx, gw);
-    p->zq.resize(p->nzq);
-    p->wq.resize(p->nzq);
-    p->bval.assign((size_t)p->nzq * K, 0.0);
-    p->wbval.assign((size_t)p->nzq * K, 0.0);
-    std::vector<double> dval((size_t)p->nzq * K, 0.0);
-    for (int s = 0; s < p->nint; ++s) {
-        double a = p->bp[s], b = p->bp[s + 1];
-        double h = 0.5 * (b - a), mid = 0.5 * (a + b);
-        int l = K - 1 + s;
-        for (int j = 0; j < p->nq; ++j) {
-            int q = s * p->nq + j;
-            double z = mid + h * gx[j];
-            p->zq[q] = z;
-            p->wq[q] = h * gw[j];
-            double v[8], vl[8];
-            nonzero_splines(tau, l, K, z, v);       // full indices s .. s+K-1
-            nonzero_splines(tau, l, K - 1, z, vl);  // order K-1: full indices s+1 .. s+K-1
-            for (int r = 0; r < K; ++r) {
-                int full = s + r;
-                int kept = full - 1;
-                double val = v[r];
-                // derivative, eq. 3
-                double dv = 0.0;
-                double d1 = tau[full + K - 1] - tau[full];
-                double d2 = tau[full + K] - tau[full + 1];
-                if (r >= 1 && d1 > 0) dv += (K - 1) / d1 * vl[r - 1];
-                if (r <= K - 2 && d2 > 0) dv -= (K - 1) / d2 * vl[r];
-                if (kept < 0 || kept >= p->nb) { val = 0.0; dv = 0.0; }
-                p->bval[(size_t)q * K + r] = val;
-                p->wbval[(size_t)q * K + r] = p->wq[q] * val;
-                dval[(size_t)q * K + r] = dv;
-            }
-        }
-    }
-
-    // banded S_z and D_z
-    p->sband.assign((size_t)p->nb * K, 0.0);
-    p->dband.assign((size_t)p->nb * K, 0.0);
-    for (int s = 0; s < p->nint; ++s)
-        for (int j = 0; j < p->nq; ++j) {
-            int q = s * p->nq + j;
-            for (int r1 = 0; r1 < K; ++r1)
-                for (int r2 = r1; r2 < K; ++r2) {
-                    int i = s - 1 + r1, i2 = s - 1 + r2;
-                    if (i < 0 || i2 >= p->nb) continue;
-                    int dd = r2 - r1;
-                    p->sband[(size_t)i * K + dd] += p->wq[q] * p->bval[(size_t)q * K + r1] * p->bval[(size_t)q * K + r2];
-                    p->dband[(size_t)i * K + dd] += p->wq[q] * dval[(size_t)q * K + r1] * dval[(size_t)q * K + r2];
-                }
-        }
-
-    // banded Cholesky S_z = L L^T, lband[i][d] = L[i][i-d]
-    p->lband.assign((size_t)p->nb * K, 0.0);
-    auto S = [&](int i, int j) -> double {  // symmetric access, |i-j| < K
-        if (i > j) std::swap(i, j);
-        return p->sband[(size_t)i * K + (j - i)];
-    };
-    auto L = [&](int i, int j) -> double& { return p->lband[(size_t)i * K + (i - j)]; };
-    for (int i = 0; i < p->nb; ++i) {
-        int j0 = std::max(0, i - (K - 1));
-        for (int j = j0; j <= i; ++j) {
-            double sum = S(i, j);
-            for (int k = std::max(j0, j - (K - 1)); k < j; ++k) sum -= L(i, k) * L(j, k);
-            if (j == i) {
-                if (!(sum > 0)) return set_error(MB_ERR_NOT_SPD, "overlap S_z is not positive definite");
-                L(i, i) = std::sqrt(sum);
-            } else {
-                L(i, j) = sum / L(j, j);
-            }
-        }
-    }
+    SplineDir zdir;
+    MB_TRY(build_spline_dir(p->bp, K, p->nq, &zdir, "overlap S_z"));
+    p->zq = std::move(zdir.zq);
+    p->wq = std::move(zdir.wq);
+    p->bval = std::move(zdir.bval);
+    p->wbval = std::move(zdir.wbval);
+    p->sband = std::move(zdir.sband);
+    p->dband = std::move(zdir.dband);
+    p->lband = std::move(zdir.lband);
 
     // projectors: z factors (same for every k) and energies
     p->np = 0;

@@ -29,7 +29,8 @@ EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dim
            "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
            "density_accumulate", "hartree_potential", "mb_tune_get", "mb_tune_set", "mb_tune_save",
            "mb_tune_load", "mb_batch_bind", "hpsi_apply_batched_bound", "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
-           "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error")
+           "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error", "mb_wire_create",
+           "mb_wire_dims")
 
 
 class MbError(RuntimeError):
@@ -54,6 +55,13 @@ class MbDesc(ctypes.Structure):
                 ("gset_kind", c_int32), ("mmax", c_int32 * 2), ("ecut", c_double), ("nk", c_int32),
                 ("kfrac", POINTER(c_double)), ("nspecies", c_int32), ("species", POINTER(MbSpecies)),
                 ("natoms", c_int32), ("atoms", POINTER(MbAtom))]
+
+
+class MbWireDesc(ctypes.Structure):
+    _fields_ = [("period", c_double), ("order", c_int32), ("nbreak_x", c_int32), ("breakpoints_x", POINTER(c_double)),
+                ("nbreak_z", c_int32), ("breakpoints_z", POINTER(c_double)), ("nq", c_int32), ("ny", c_int32),
+                ("ecut", c_double), ("nk", c_int32), ("kfrac", POINTER(c_double)), ("nspecies", c_int32),
+                ("species", POINTER(MbSpecies)), ("natoms", c_int32), ("atoms", POINTER(MbAtom))]
 
 
 class LanczosOpts(ctypes.Structure):
@@ -180,39 +188,72 @@ def small_geneig(H: np.ndarray, S: np.ndarray, stream=None):
     return ev, Y, sw
 
 
+def _species_atoms(desc):
+    sp_arr = (MbSpecies * max(1, len(desc["species"])))()
+    for n, sp in enumerate(desc["species"]):
+        g = sp.get("gauss", [])
+        if len(g) > MB_MAX_GAUSS:
+            raise ValueError("too many Gaussian terms")
+        sp_arr[n].ngauss = len(g)
+        for t, (A, w) in enumerate(g):
+            sp_arr[n].gauss_A[t] = A
+            sp_arr[n].gauss_w[t] = w
+        nl = bool(sp.get("nonlocal", False))
+        sp_arr[n].nonlocal_ = int(nl)
+        if nl:
+            sp_arr[n].alpha_s = sp["alpha_s"]
+            sp_arr[n].alpha_p = sp["alpha_p"]
+            sp_arr[n].E_s = sp["E_s"]
+            sp_arr[n].E_p = sp["E_p"]
+            sp_arr[n].q_s = sp.get("q_s", 0.0)
+            sp_arr[n].q_p = sp.get("q_p", 0.0)
+    at_arr = (MbAtom * max(1, len(desc["atoms"])))()
+    for n, at in enumerate(desc["atoms"]):
+        at_arr[n].species = at["species"]
+        for c in range(3):
+            at_arr[n].pos[c] = at["pos"][c]
+    return sp_arr, at_arr
+
+
 class Problem:
     """Handle of one problem description; device=None builds host tables only."""
 
     def __init__(self, desc: dict, device: int | None = 0):
+        """desc: a slab description, or a 1D-periodic one (desc["kind"] == "wire": keys
+        period, order, breakpoints_x, breakpoints_z, nq, ny, ecut, kpts (fractions of
+        2 pi / L), species, atoms)."""
         lib = load()
         self.desc = desc
-        keep = []
+        self.wire = desc.get("kind") == "wire"
+        sp_arr, at_arr = _species_atoms(desc)
+        if self.wire:
+            bx = np.ascontiguousarray(desc["breakpoints_x"], dtype=np.float64)
+            bz = np.ascontiguousarray(desc["breakpoints_z"], dtype=np.float64)
+            kf = np.ascontiguousarray(np.array(desc["kpts"], dtype=np.float64).reshape(-1))
+            w = MbWireDesc()
+            w.period = desc["period"]
+            w.order = desc["order"]
+            w.nbreak_x = len(bx)
+            w.breakpoints_x = bx.ctypes.data_as(POINTER(c_double))
+            w.nbreak_z = len(bz)
+            w.breakpoints_z = bz.ctypes.data_as(POINTER(c_double))
+            w.nq = desc["nq"]
+            w.ny = desc["ny"]
+            w.ecut = desc["ecut"]
+            w.nk = len(kf)
+            w.kfrac = kf.ctypes.data_as(POINTER(c_double))
+            w.nspecies = len(desc["species"])
+            w.species = sp_arr
+            w.natoms = len(desc["atoms"])
+            w.atoms = at_arr
+            h = c_void_p()
+            _check(lib.mb_wire_create(ctypes.byref(w), -1 if device is None else int(device), ctypes.byref(h)))
+            self.h = h
+            self.device = device
+            self.nk = len(kf)
+            return
         bp = np.ascontiguousarray(desc["breakpoints"], dtype=np.float64)
         kf = np.ascontiguousarray(np.array(desc["kpts"], dtype=np.float64).reshape(-1, 2))
-        keep += [bp, kf]
-        sp_arr = (MbSpecies * max(1, len(desc["species"])))()
-        for n, sp in enumerate(desc["species"]):
-            g = sp.get("gauss", [])
-            if len(g) > MB_MAX_GAUSS:
-                raise ValueError("too many Gaussian terms")
-            sp_arr[n].ngauss = len(g)
-            for t, (A, w) in enumerate(g):
-                sp_arr[n].gauss_A[t] = A
-                sp_arr[n].gauss_w[t] = w
-            nl = bool(sp.get("nonlocal", False))
-            sp_arr[n].nonlocal_ = int(nl)
-            if nl:
-                sp_arr[n].alpha_s = sp["alpha_s"]
-                sp_arr[n].alpha_p = sp["alpha_p"]
-                sp_arr[n].E_s = sp["E_s"]
-                sp_arr[n].E_p = sp["E_p"]
-                sp_arr[n].q_s = sp.get("q_s", 0.0)
-                sp_arr[n].q_p = sp.get("q_p", 0.0)
-        at_arr = (MbAtom * max(1, len(desc["atoms"])))()
-        for n, at in enumerate(desc["atoms"]):
-            at_arr[n].species = at["species"]
-            for c in range(3):
-                at_arr[n].pos[c] = at["pos"][c]
         d = MbDesc()
         d.a1[:] = list(desc["a1"])
         d.a2[:] = list(desc["a2"])
@@ -239,6 +280,13 @@ class Problem:
         self.h = h
         self.device = device
         self.nk = len(kf)
+
+    def wire_dims(self):
+        """Sizes of a 1D-periodic problem: splines along x and z, Gauss points along x and z, ny."""
+        v = [c_int64() for _ in range(5)]
+        _check(load().mb_wire_dims(self.h, *[ctypes.byref(x) for x in v]))
+        nbx, nbz, nxq, nzq, ny = (x.value for x in v)
+        return {"nbx": nbx, "nbz": nbz, "nxq": nxq, "nzq": nzq, "ny": ny}
 
     def close(self):
         if getattr(self, "h", None):

@@ -167,3 +167,38 @@ def test_tune_choices_persist_through_the_cache_file(tmp_path):
     assert g2.tune_get(1, "fp32")["local_kernel"] == -1
     for pr in (g, s, g2, s2, t2):
         pr.close()
+
+
+def test_wire_handles_on_the_host():
+    # 1D-periodic form: sizes and plane-wave sets against the oracle, calls of the slab
+    # refused, inconsistent descriptions refused
+    from oracle import wire
+    for d in (workloads.wire_micro(), workloads.ribbon_narrow(), workloads.ribbon()):
+        p = mbks.Problem(d, device=None)
+        wd = p.wire_dims()
+        xb, zb = wire.basis_x(d), wire.basis_z(d)
+        assert (wd["nbx"], wd["nbz"], wd["nxq"], wd["nzq"], wd["ny"]) == (xb.nb, zb.nb, len(xb.zq), len(zb.zq), d["ny"])
+        for ik in range(len(d["kpts"])):
+            dm = p.dims(ik)
+            m, kg2 = p.gvectors(ik)
+            mo, q = wire.gset(d, ik)
+            assert dm["nb"] == xb.nb * zb.nb and dm["ng"] == len(mo)
+            assert np.array_equal(m[:, 0], mo) and np.all(m[:, 1] == 0)
+            assert np.max(np.abs(kg2 - q * q)) < 1e-12 * np.max(q * q)
+        for call in (p.zrule, p.zbands, p.projectors, p.augmentation, lambda: p.tune_get(0)):
+            with pytest.raises(mbks.MbError) as e:
+                call()
+            assert e.value.status == -1
+        p.close()
+    slab = mbks.Problem(workloads.tiny(), device=None)
+    with pytest.raises(mbks.MbError):
+        slab.wire_dims()
+    slab.close()
+    base = workloads.wire_micro()
+    bad = [dict(base, ny=10), dict(base, ny=8, ecut=40.0), dict(base, period=-1.0),
+           dict(base, breakpoints_x=[0.0, 1.0, 1.0, 2.0]),
+           dict(base, species=[dict(base["species"][0], q_s=0.2)] + base["species"][1:])]
+    for d in bad:
+        with pytest.raises(mbks.MbError) as e:
+            mbks.Problem(d, device=None)
+        assert e.value.status == -1
