@@ -365,6 +365,81 @@ def density_leg(torch, mbks, workloads, d, reps=3):
     return res
 
 
+def ribbon_leg(torch, mbks, workloads, reps=5, full=True):
+    """The 1D-periodic form on the 19-line armchair ribbon (B-splines along x and z,
+    plane waves along y): hpsi_apply on k-point 0 with 96 band-vectors in FP64 and FP32,
+    the local kernel against its flop model, and the time to the 96 lowest eigenpairs
+    of k-point 0 (and of all 4 k-points one after another) mixed and FP64."""
+    d = workloads.ribbon()
+    p = mbks.Problem(d, device=0)
+    dm, wd = p.dims(0), p.wire_dims()
+    M = d["nbands"]
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(14064967)
+    res = {"workload": d["name"], "kpoints": len(d["kpts"]), "bands": M, "n_per_k": dm["ng"] * dm["nb"],
+           "plane_waves": dm["ng"], "splines_x": wd["nbx"], "splines_z": wd["nbz"], "ny": wd["ny"],
+           "projectors": dm["np"]}
+    # flop model of the local kernel per band: per (x_q, z_p) line two ny-point FFTs
+    # (10 ny log2 ny), the potential multiply (2 ny), evaluate and project (32 N_G)
+    ny = wd["ny"]
+    lines = wd["nxq"] * wd["nzq"]
+    fl_band = lines * (10 * ny * np.log2(ny) + 2 * ny + 32 * dm["ng"])
+    res["local_gflop_per_band"] = round(float(fl_band) / 1e9, 4)
+    for prec, ct in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+        x = torch.randn((M, dm["nb"], dm["ld"]), dtype=ct, device="cuda:0", generator=gen)
+        x[:, :, dm["ng"]:] = 0
+        y = torch.empty_like(x)
+        p.hpsi(0, x, y, prec)
+        torch.cuda.synchronize()
+        mbks.timer_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            p.hpsi(0, x, y, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        st = mbks.timer_read()
+        mbks.timer_enable(False)
+        ms = e0.elapsed_time(e1) / reps
+        stage = {k: round(v[0] / reps, 3) for k, v in st.items() if v[1]}
+        loc = stage.get("local" if prec == "fp64" else "local32")
+        peak = 78.6 if prec == "fp64" else 157.3
+        rec = {"band_vectors_per_s": round(M / (ms * 1e-3), 1), "ms_per_call": round(ms, 3),
+               "stages_ms_per_call": stage}
+        if loc:
+            tf = fl_band * M / (loc * 1e-3) / 1e12
+            rec["local_kernel_alu"] = {"achieved_tflops": round(float(tf), 2), "peak": peak,
+                                       "frac": round(float(tf) / peak, 4)}
+        res[f"hpsi_{prec}"] = rec
+        del x, y
+        torch.cuda.empty_cache()
+        log("ribbon hpsi", prec, rec)
+    nks = range(len(d["kpts"])) if full else [0]
+    for prec in ("fp32", "fp64"):
+        tot, iters, resid = 0.0, [], 0.0
+        for ik in nks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eps, xs, info, stt = p.lanczos_lowest(ik, M, prec, raise_not_converged=False)
+            torch.cuda.synchronize()
+            dt = 1e3 * (time.perf_counter() - t0)
+            if ik == 0:
+                res[f"eig_k0_{prec}"] = {"ms": round(dt, 1), "status": stt, "iters": info["iters"],
+                                         "iters_reduced_precision": info["iters_low"],
+                                         "max_resid": info["max_resid"]}
+            tot += dt
+            iters.append(info["iters"])
+            resid = max(resid, info["max_resid"])
+            del xs
+        res[f"eig_all_{prec}"] = {"ms": round(tot, 1), "eigenpairs": len(nks) * M, "iters_per_k": iters,
+                                  "max_resid": resid}
+        log("ribbon eigen", prec, res[f"eig_all_{prec}"])
+    res["eig_all_speedup_mixed_vs_fp64"] = round(res["eig_all_fp64"]["ms"] / res["eig_all_fp32"]["ms"], 3)
+    torch.cuda.empty_cache()
+    p.close()
+    return res
+
+
 def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
     """FP64 hpsi_apply on k-point 0 (320 vectors), and the time to the 320 lowest
     eigenpairs of k-point 0 (the share of one GPU in a k-point split over 8) in the
@@ -432,18 +507,30 @@ def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
     res["eig_k0_speedup_mixed_vs_fp64"] = round(res["eig_k0_fp64"]["ms"] / res["eig_k0_fp32"]["ms"], 3)
     res["eig_k0_max_diff_mixed_vs_fp64"] = float(np.max(np.abs(eigs["fp32"] - eigs["fp64"])))
     if full_eig:
+        # all 8 k-points x 320 eigenpairs in one lanczos_lowest_batched call per form (as
+        # many k-points at a time as the free device memory holds)
         nk = len(d["kpts"])
         b = mbks.Batch([(p, ik) for ik in range(nk)])
+        all_e = {}
         for prec in ("fp32", "fp64"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             e, xs, infos, stt = b.lanczos_lowest([M] * nk, prec, raise_not_converged=False)
             torch.cuda.synchronize()
-            res[f"eig_all_{prec}"] = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": stt,
-                                      "max_resid": max(i["max_resid"] for i in infos)}
+            rec = {"ms": round(1e3 * (time.perf_counter() - t0), 1), "status": stt,
+                   "eigenpairs": nk * M, "iters_per_k": [i["iters"] for i in infos],
+                   "max_resid": max(i["max_resid"] for i in infos)}
+            if golden and "0" in golden["kpoints"]:
+                ref = np.array(golden["kpoints"]["0"]["eps"])
+                rec["k0_max_eig_err_vs_oracle"] = float(np.max(np.abs(e[0][:len(ref)] - ref)))
+            res[f"eig_all_{prec}"] = rec
+            all_e[prec] = e
             del xs
             torch.cuda.empty_cache()
-            log("surface solve all k", prec, res[f"eig_all_{prec}"])
+            log("surface solve all k", prec, rec)
+        res["eig_all_speedup_mixed_vs_fp64"] = round(res["eig_all_fp64"]["ms"] / res["eig_all_fp32"]["ms"], 3)
+        res["eig_all_max_diff_mixed_vs_fp64"] = float(max(np.max(np.abs(all_e["fp32"][k] - all_e["fp64"][k]))
+                                                       for k in range(nk)))
         b.close()
     p.close()
     return res
@@ -459,12 +546,14 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eigen", action="store_true", help="skip the surface FP64 / eigenpair leg")
-    ap.add_argument("--full-eig", action="store_true",
-                    help="also time all 8 x 320 eigenpairs of the surface slab, mixed and FP64 (minutes)")
+    ap.add_argument("--no-full-eig", action="store_true",
+                    help="skip the time to all 8 x 320 eigenpairs of the surface slab (mixed and FP64)")
+    ap.add_argument("--full-eig", action="store_true", help="(default) kept for old command lines")
     ap.add_argument("--no-graphene", action="store_true", help="skip the graphene-like slab leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem uneven batch leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
     ap.add_argument("--no-density", action="store_true", help="skip the density / Hartree leg")
+    ap.add_argument("--no-ribbon", action="store_true", help="skip the 1D-periodic ribbon leg")
     ap.add_argument("--no-uspp", action="store_true",
                     help="skip the graphene-like slab with augmentation charges (ultrasoft overlap)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
@@ -578,12 +667,13 @@ def main(argv=None):
     surf = {"workload": d["name"], "stages_ms_per_step": stage_ms, "bf16x3": bf,
             "autotune_k0": tuned[0] if tuned else None}
     if not args.no_eigen:
-        surf.update(surface_fp64_and_eigen_leg(torch, mbks, workloads, d, args.full_eig))
+        surf.update(surface_fp64_and_eigen_leg(torch, mbks, workloads, d, not args.no_full_eig))
     graphene = None if args.no_graphene else graphene_leg(torch, mbks, workloads)
     batched = None if args.no_batched else batched_leg(args, torch, mbks, workloads)
     c3 = None if args.no_c3 else c3_leg(torch, mbks, workloads)
     uspp = None if args.no_uspp else uspp_leg(torch, mbks, workloads)
     dens = None if args.no_density else density_leg(torch, mbks, workloads, d)
+    ribbon = None if args.no_ribbon else ribbon_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -615,6 +705,7 @@ def main(argv=None):
         "supercell_2x2": c3,
         "ultrasoft_graphene": uspp,
         "density_hartree": dens,
+        "ribbon_1d_periodic": ribbon,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -11,7 +11,8 @@
 //                  rows shared with the next round carry over in LDS, so every F row is
 //                  written once, complete (no atomics);
 //   k_wire_combine y(G,i,j) = sum_p w_p B_j(z_p) F(i, z_p, G) + T c + sum_p F_p X_p Z_p P_p,
-//                  the banded kinetic and overlap sums in FP64.
+//                  the banded kinetic and overlap sums in FP64, one thread per (band, i, G)
+//                  and chunk of 4 z rows.
 // S^{-1} = S_x^{-1} (x) S_z^{-1}: two banded Cholesky substitutions.  The eigensolver's
 // preconditioner (T + sigma S)^{-1} diagonalises the z direction (D_z u = lambda S_z u,
 // u S_z-orthonormal): per z eigenvector j' and G it is the banded x problem
@@ -19,6 +20,8 @@
 // transform, banded x substitutions and the back transform.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "cplx.h"
@@ -106,16 +109,16 @@ constexpr size_t wire_hdr() {
     return ((sizeof(cx<T>) * NY + sizeof(int32_t) * NY + 255) / 256) * 256;
 }
 
-template <typename T, int NY, int Q>
+template <typename T, int NY, int Q, int NT>
 size_t wire_local_lds(int ng, int nq) {
-    const int LR = WNT / Q, RI = LR / nq, NR = RI + 3;
+    const int LR = NT / Q, RI = LR / nq, NR = RI + 3;
     return wire_hdr<T, NY>() + sizeof(cx<T>) * (size_t)ng * (2 * NR + LR);
 }
 
-template <typename TI, typename T, int NY, int Q>
-__global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
+template <typename TI, typename T, int NY, int Q, int NT>
+__global__ __launch_bounds__(NT) void k_wire_local(WLocalArgs<TI, T> a) {
     constexpr int L = NY / Q;
-    constexpr int LR = WNT / Q;  // lines per round
+    constexpr int LR = NT / Q;  // lines per round
     extern __shared__ unsigned char smem_raw[];
     const int RI = LR / a.nq;    // knot intervals per round (host checks >= 1)
     const int NR = RI + 3;       // spline rows a round touches
@@ -133,11 +136,11 @@ __global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
     if (p >= a.nzq) return;
     const int e = p / a.nq;  // z knot interval of the point
     const int tid = threadIdx.x;
-    for (int k = tid; k < NY; k += WNT) {
+    for (int k = tid; k < NY; k += NT) {
         tw[k] = a.tw[k];
         gt[k] = a.gtab[k];
     }
-    for (int o = tid; o < NR * a.ng; o += WNT) acc[o] = mk<T>(0, 0);
+    for (int o = tid; o < NR * a.ng; o += NT) acc[o] = mk<T>(0, 0);
     T bzv[KORD];
 #pragma unroll
     for (int t = 0; t < KORD; ++t) bzv[t] = a.bz[(size_t)p * KORD + t];
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
         const int r1 = min(r0 + RI, a.nintx);
         const int nrow = r1 - r0 + 3;  // spline rows r0 - 1 .. r1 + 1
         // z contraction of the rows this round needs
-        for (int o = tid; o < nrow * a.ng; o += WNT) {
+        for (int o = tid; o < nrow * a.ng; o += NT) {
             const int rl = o / a.ng, g = o - rl * a.ng;
             const int i = r0 - 1 + rl;
             cx<T> v = mk<T>(0, 0);
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
         __syncthreads();
 
         // x projection onto the spline rows of the round
-        for (int o = tid; o < nrow * a.ng; o += WNT) {
+        for (int o = tid; o < nrow * a.ng; o += NT) {
             const int rl = o / a.ng, g = o - rl * a.ng;
             const int i = r0 - 1 + rl;
             cx<T> v = acc[o];
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
         // rows below r1 - 1 are complete (the next interval starts at row r1 - 1)
         const bool last = r1 >= a.nintx;
         const int ndone = last ? nrow : nrow - 3;
-        for (int o = tid; o < ndone * a.ng; o += WNT) {
+        for (int o = tid; o < ndone * a.ng; o += NT) {
             const int rl = o / a.ng, g = o - rl * a.ng;
             const int i = r0 - 1 + rl;
             if (i >= 0 && i < a.nbx) Fb[((size_t)i * a.nzq + p) * a.ld + g] = acc[o];
@@ -238,24 +241,34 @@ __global__ __launch_bounds__(WNT) void k_wire_local(WLocalArgs<TI, T> a) {
         if (last) break;
         __syncthreads();
         // carry the three open rows to the front (through tb, free until the next stage)
-        for (int o = tid; o < 3 * a.ng; o += WNT) tb[o] = acc[(size_t)(nrow - 3) * a.ng + o];
+        for (int o = tid; o < 3 * a.ng; o += NT) tb[o] = acc[(size_t)(nrow - 3) * a.ng + o];
         __syncthreads();
-        for (int o = tid; o < NR * a.ng; o += WNT) acc[o] = o < 3 * a.ng ? tb[o] : mk<T>(0, 0);
+        for (int o = tid; o < NR * a.ng; o += NT) acc[o] = o < 3 * a.ng ? tb[o] : mk<T>(0, 0);
         __syncthreads();
     }
 }
 
-template <typename TI, typename T, int NY, int Q>
-mb_status wire_local_launch(const WLocalArgs<TI, T>& a, hipStream_t s) {
-    const size_t lds = wire_local_lds<T, NY, Q>(a.ng, a.nq);
+template <typename TI, typename T, int NY, int Q, int NT>
+mb_status wire_local_launch_nt(const WLocalArgs<TI, T>& a, hipStream_t s) {
+    const size_t lds = wire_local_lds<T, NY, Q, NT>(a.ng, a.nq);
     if (lds > 160 * 1024) return set_error(MB_ERR_INVALID_ARG, "1D-periodic local kernel: plane-wave set too large for LDS");
-    auto kern = k_wire_local<TI, T, NY, Q>;
+    auto kern = k_wire_local<TI, T, NY, Q, NT>;
     if (lds > 64 * 1024) MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const size_t nwg = (size_t)a.nbands * a.nzq;
     if (nwg > 0x7fffffffull) return set_error(MB_ERR_INVALID_ARG, "1D-periodic local kernel: too many bands");
-    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(WNT), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nwg), dim3(NT), lds, s, a);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
+}
+
+// 512 threads per workgroup (MBKS_WIRE_LOCAL_THREADS=256 selects 256: half the lines per
+// round, twice the rounds; measured on the 19-line ribbon, 96 bands: 6.5 against 7.2 ms in
+// FP64, 3.5 against 3.7 ms in FP32)
+template <typename TI, typename T, int NY, int Q>
+mb_status wire_local_launch(const WLocalArgs<TI, T>& a, hipStream_t s) {
+    const char* sel = getenv("MBKS_WIRE_LOCAL_THREADS");
+    if (sel && std::string(sel) == "256") return wire_local_launch_nt<TI, T, NY, Q, 256>(a, s);
+    return wire_local_launch_nt<TI, T, NY, Q, 512>(a, s);
 }
 
 template <typename TI, typename T>
@@ -334,63 +347,142 @@ __device__ __forceinline__ double band_at(const double* m, int i, int i2) {
     return d < KORD ? m[lo * KORD + d] : 0.0;
 }
 
-template <typename TI, typename T>
+// One thread per (band, x row i, G) and a chunk of WJB consecutive z rows j0 .. j0+WJB-1
+// (the chunk is blockIdx.y, so the z band and spline coefficients are uniform over the
+// workgroup): each coefficient row and each F row loaded serves every output of the chunk
+// it touches (the kinetic stencil as z sums per x neighbour, then the x sum).
+template <typename TI, typename T, int WJB>
 __global__ __launch_bounds__(256) void k_wire_combine(WCombineArgs<TI, T> a) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    const int nrows = a.nbx * a.nbz;
-    if (o >= (int64_t)nrows * a.ld) return;
-    const int row = (int)(o / a.ld), g = (int)(o - (int64_t)row * a.ld);
-    const int i = row / a.nbz, j = row - i * a.nbz;
-    const size_t vb = (size_t)b * nrows * a.ld;
-    const size_t out = vb + (size_t)row * a.ld + g;
+    const int j0 = blockIdx.y * WJB;
+    const int b = blockIdx.z;
+    if (o >= (int64_t)a.nbx * a.ld) return;
+    const int i = (int)(o / a.ld), g = (int)(o - (int64_t)i * a.ld);
+    const int nj = min(WJB, a.nbz - j0);
+    const size_t vb = (size_t)b * a.nbx * a.nbz * a.ld;
+    const size_t ob = vb + ((size_t)i * a.nbz + j0) * a.ld + g;
     if (g >= a.ng) {
-        a.y[out] = mk<TI>(0, 0);
-        if (a.sy) a.sy[out] = mk<TI>(0, 0);
+        for (int t = 0; t < nj; ++t) {
+            a.y[ob + (size_t)t * a.ld] = mk<TI>(0, 0);
+            if (a.sy) a.sy[ob + (size_t)t * a.ld] = mk<TI>(0, 0);
+        }
         return;
     }
     const double k2 = a.s_only ? 0.0 : 0.5 * a.kg2[g];
-    cx<double> kin = mk<double>(0, 0), sc = mk<double>(0, 0);
+    cx<double> kin[WJB], sc[WJB];
+#pragma unroll
+    for (int t = 0; t < WJB; ++t) kin[t] = sc[t] = mk<double>(0, 0);
     for (int i2 = max(0, i - 3); i2 <= min(a.nbx - 1, i + 3); ++i2) {
         const double sxv = band_at(a.sx, i, i2), dxv = band_at(a.dx, i, i2);
-        for (int j2 = max(0, j - 3); j2 <= min(a.nbz - 1, j + 3); ++j2) {
-            const double szv = band_at(a.sz, j, j2), dzv = band_at(a.dz, j, j2);
-            const cx<TI> cv = a.c[vb + ((size_t)i2 * a.nbz + j2) * a.ld + g];
-            const double ss = sxv * szv;
-            const double kk = 0.5 * (dxv * szv + sxv * dzv) + k2 * ss;
-            kin.x = fma(kk, (double)cv.x, kin.x);
-            kin.y = fma(kk, (double)cv.y, kin.y);
-            sc.x = fma(ss, (double)cv.x, sc.x);
-            sc.y = fma(ss, (double)cv.y, sc.y);
+        const cx<TI>* cr = a.c + vb + (size_t)i2 * a.nbz * a.ld + g;
+        cx<double> az[WJB], dz[WJB];
+#pragma unroll
+        for (int t = 0; t < WJB; ++t) az[t] = dz[t] = mk<double>(0, 0);
+#pragma unroll
+        for (int u = 0; u < WJB + 6; ++u) {
+            const int jj = j0 - 3 + u;
+            if (jj < 0 || jj >= a.nbz) continue;
+            const cx<TI> cv = cr[(size_t)jj * a.ld];
+            const double vr = (double)cv.x, vi = (double)cv.y;
+#pragma unroll
+            for (int t = 0; t < WJB; ++t) {
+                const int dj = u - 3 - t;
+                if (dj < -3 || dj > 3 || j0 + t >= a.nbz) continue;
+                const double sv = band_at(a.sz, j0 + t, jj), dv = band_at(a.dz, j0 + t, jj);
+                az[t].x = fma(sv, vr, az[t].x);
+                az[t].y = fma(sv, vi, az[t].y);
+                dz[t].x = fma(dv, vr, dz[t].x);
+                dz[t].y = fma(dv, vi, dz[t].y);
+            }
+        }
+        const double ka = 0.5 * dxv + k2 * sxv, kd = 0.5 * sxv;
+#pragma unroll
+        for (int t = 0; t < WJB; ++t) {
+            kin[t].x = fma(ka, az[t].x, fma(kd, dz[t].x, kin[t].x));
+            kin[t].y = fma(ka, az[t].y, fma(kd, dz[t].y, kin[t].y));
+            sc[t].x = fma(sxv, az[t].x, sc[t].x);
+            sc[t].y = fma(sxv, az[t].y, sc[t].y);
         }
     }
     if (a.s_only) {
-        a.y[out] = mk<TI>((TI)sc.x, (TI)sc.y);
+#pragma unroll
+        for (int t = 0; t < WJB; ++t)
+            if (t < nj) a.y[ob + (size_t)t * a.ld] = mk<TI>((TI)sc[t].x, (TI)sc[t].y);
         return;
     }
-    cx<T> v = mk<T>(0, 0);
+    cx<T> v[WJB];
+#pragma unroll
+    for (int t = 0; t < WJB; ++t) v[t] = mk<T>(0, 0);
     if (a.F) {
         const cx<T>* Fr = a.F + ((size_t)b * a.nbx + i) * a.nzq * a.ld + g;
-        for (int s = max(0, j - 2); s <= min(a.nintz - 1, j + 1); ++s) {
-            const int t = j - s + 1;
-            for (int jq = 0; jq < a.nq; ++jq) {
-                const int p = s * a.nq + jq;
-                rfma(v, a.wbz[(size_t)p * KORD + t], Fr[(size_t)p * a.ld]);
+        // the Gauss points of the intervals meeting the chunk, as one flat range (the
+        // interval index is uniform, so the loads of consecutive points overlap)
+        const int p_lo = max(0, j0 - 2) * a.nq, p_hi = (min(a.nintz - 1, j0 + WJB) + 1) * a.nq;
+#pragma unroll 5
+        for (int p = p_lo; p < p_hi; ++p) {
+            const int s = p / a.nq;
+            const cx<T> f = Fr[(size_t)p * a.ld];
+#pragma unroll
+            for (int t = 0; t < WJB; ++t) {
+                const int tt = j0 + t - s + 1;
+                if (tt < 0 || tt > 3 || j0 + t >= a.nbz) continue;
+                rfma(v[t], a.wbz[(size_t)p * KORD + tt], f);
             }
         }
     }
     if (a.proj) {
         for (int k = a.ploff[i]; k < a.ploff[i + 1]; ++k) {
             const int q = a.plist[k];
-            if (j < a.zwin[2 * q] || j > a.zwin[2 * q + 1]) continue;
-            const T w = a.X[(size_t)q * a.nbx + i] * a.Z[(size_t)q * a.nbz + j];
-            cx<T> t = mk<T>(0, 0);
-            cfma(t, a.Fp[(size_t)q * a.ld + g], a.proj[(size_t)b * a.np + q]);
-            rfma(v, w, t);
+            const int z0 = a.zwin[2 * q], z1 = a.zwin[2 * q + 1];
+            if (z1 < j0 || z0 >= j0 + WJB) continue;
+            cx<T> cf = mk<T>(0, 0);
+            cfma(cf, a.Fp[(size_t)q * a.ld + g], a.proj[(size_t)b * a.np + q]);
+            cf = cscale(cf, a.X[(size_t)q * a.nbx + i]);
+#pragma unroll
+            for (int t = 0; t < WJB; ++t) {
+                const int j = j0 + t;
+                if (j < z0 || j > z1) continue;
+                rfma(v[t], a.Z[(size_t)q * a.nbz + j], cf);
+            }
         }
     }
-    a.y[out] = mk<TI>((TI)(kin.x + (double)v.x), (TI)(kin.y + (double)v.y));
-    if (a.sy) a.sy[out] = mk<TI>((TI)sc.x, (TI)sc.y);
+#pragma unroll
+    for (int t = 0; t < WJB; ++t) {
+        if (t >= nj) continue;
+        a.y[ob + (size_t)t * a.ld] = mk<TI>((TI)(kin[t].x + (double)v[t].x), (TI)(kin[t].y + (double)v[t].y));
+        if (a.sy) a.sy[ob + (size_t)t * a.ld] = mk<TI>((TI)sc[t].x, (TI)sc[t].y);
+    }
+}
+
+// launches the combine over band chunks of at most 65,535 (grid z limit); z rows per
+// thread: 4 (MBKS_WIRE_COMBINE_ROWS=8 selects 8: 181 against 108 VGPRs, slower on the
+// 19-line ribbon, 3.5 against 2.7 ms per 96 bands in FP64)
+template <typename TI, typename T, int WJB>
+mb_status launch_wire_combine_jb(WCombineArgs<TI, T> a, hipStream_t s) {
+    const int64_t n = (int64_t)a.nbx * a.ld;
+    const int njc = (a.nbz + WJB - 1) / WJB;
+    const size_t vstride = (size_t)a.nbx * a.nbz * a.ld, fstride = (size_t)a.nbx * a.nzq * a.ld;
+    const int total = a.nbands;
+    for (int b0 = 0; b0 < total; b0 += 65535) {
+        WCombineArgs<TI, T> c = a;
+        c.nbands = std::min(65535, total - b0);
+        c.c = a.c + b0 * vstride;
+        c.y = a.y + b0 * vstride;
+        if (a.sy) c.sy = a.sy + b0 * vstride;
+        if (a.F) c.F = a.F + b0 * fstride;
+        if (a.proj) c.proj = a.proj + (size_t)b0 * a.np;
+        hipLaunchKernelGGL((k_wire_combine<TI, T, WJB>), dim3((unsigned)((n + 255) / 256), njc, c.nbands), dim3(256),
+                           0, s, c);
+        MB_HIP_TRY(hipGetLastError());
+    }
+    return MB_OK;
+}
+
+template <typename TI, typename T>
+mb_status launch_wire_combine(const WCombineArgs<TI, T>& a, hipStream_t s) {
+    const char* sel = getenv("MBKS_WIRE_COMBINE_ROWS");
+    if (sel && std::string(sel) == "8") return launch_wire_combine_jb<TI, T, 8>(a, s);
+    return launch_wire_combine_jb<TI, T, 4>(a, s);
 }
 
 // ---- banded substitutions -----------------------------------------------------------------
@@ -630,11 +722,8 @@ mb_status wire_apply_t(Problem* p, int ik, const void* c, void* y, void* sy, int
     a.nzq = w.z.nzq;
     a.np = p->np;
     a.s_only = 0;
-    const int64_t n = (int64_t)nbx * nbz * ld;
     StageScope ts_(MB_STAGE_COMBINE, s, nbands);
-    hipLaunchKernelGGL((k_wire_combine<TI, T>), dim3((unsigned)((n + 255) / 256), nbands), dim3(256), 0, s, a);
-    MB_HIP_TRY(hipGetLastError());
-    return MB_OK;
+    return launch_wire_combine<TI, T>(a, s);
 }
 
 template <typename TI>
@@ -659,11 +748,8 @@ mb_status wire_spsi_t(Problem* p, int ik, const void* c, void* y, int nbands, in
     a.nzq = w.z.nzq;
     a.np = p->np;
     a.s_only = 1;
-    const int64_t n = (int64_t)w.x.nb * w.z.nb * ld;
     StageScope ts_(MB_STAGE_SPSI, s, nbands);
-    hipLaunchKernelGGL((k_wire_combine<TI, TI>), dim3((unsigned)((n + 255) / 256), nbands), dim3(256), 0, s, a);
-    MB_HIP_TRY(hipGetLastError());
-    return MB_OK;
+    return launch_wire_combine<TI, TI>(a, s);
 }
 
 template <typename TI>

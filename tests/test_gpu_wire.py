@@ -220,3 +220,23 @@ def test_wire_refuses_calls_of_the_slab_only():
             call()
         assert e.value.status == -1
     p.close()
+
+
+@pytest.mark.parametrize("cfg", ["micro", "narrow"])
+def test_wire_kernel_variants_match(cfg, monkeypatch):
+    # 256-thread local kernel (half the lines per round) and 8 z rows per combine thread
+    # against the defaults (512 threads, 4 rows), FP64 and FP32
+    d = workloads.wire_micro(seed=2, nint=16, ecut=6.0, ny=32, kfrac=0.41) if cfg == "micro" else workloads.ribbon_narrow()
+    print(f"[case] wire kernel variants {cfg}", flush=True)
+    p, dm, wd = _setup(d)
+    ng, ld, nx, nz = dm["ng"], dm["ld"], wd["nbx"], wd["nbz"]
+    x = _block(50, 3, nx, nz, ng, ld)
+    for prec in ("fp64", "fp32"):
+        ref = _apply(p, "hpsi", 0, x, prec)
+        monkeypatch.setenv("MBKS_WIRE_LOCAL_THREADS", "256")
+        monkeypatch.setenv("MBKS_WIRE_COMBINE_ROWS", "8")
+        got = _apply(p, "hpsi", 0, x, prec)
+        monkeypatch.delenv("MBKS_WIRE_LOCAL_THREADS")
+        monkeypatch.delenv("MBKS_WIRE_COMBINE_ROWS")
+        assert rel_err(got, ref) < (1e-13 if prec == "fp64" else 1e-6)
+    p.close()
