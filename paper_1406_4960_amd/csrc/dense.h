@@ -6,8 +6,10 @@
 namespace mb {
 
 // C_z = A_z^H B_z with A_z, B_z given by pointer tables (z-major), K elements per vector.
+// herm: the caller knows C_z is Hermitian (A^H H A, A^H S A); the wide matrix-core path then
+// computes the upper tiles only and fills the rest by conjugation.
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
-                     void* scratch, size_t scratch_bytes, hipStream_t s);
+                     void* scratch, size_t scratch_bytes, hipStream_t s, bool herm = false);
 // Y_{z,n} = alpha sum_m W_z[m][n] X_{z,m} + beta Y_{z,n}; W_z is MI x NO row-major.
 // low: the wide combinations may run with FP32 matrix-core arithmetic (reduced-precision
 // cycles of the eigensolver)

@@ -201,17 +201,29 @@ __global__ __launch_bounds__(256) void k_gram64(const zc* const* ta, const zc* c
 // D[4r + l/16][l%16], r < 4 (unlike the FP32 16x16x4 form, whose D rows are 4(l/16) + r).
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
+// herm != 0 (MA == NB, Hermitian result): only the tiles with tm <= tn are computed
+// (tiles_m (tiles_m + 1) / 2 of them); k_gram_reduce fills the others by conjugation.
 __global__ __launch_bounds__(256) void k_gram_mfma(const zc* const* ta, const zc* const* tb, int MA, int NB,
                                                    int64_t K, int64_t kchunk, int nchunk, int tiles_m, int tiles_n,
-                                                   zc* part) {
+                                                   zc* part, int herm) {
     __shared__ zc As[G64][GK64 + 1];
     __shared__ zc Bs[G64][GK64 + 1];
     const unsigned L = xcd_logical(blockIdx.x, gridDim.x);
-    const int ntile = tiles_m * tiles_n;
+    const int ntile = herm ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
     const int tile = (int)(L % ntile);
     const int chunk = (int)((L / ntile) % nchunk);
     const int z = (int)(L / ntile / nchunk);
-    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    int tm = tile / tiles_n, tn = tile % tiles_n;
+    if (herm) {
+        // row tm of the upper triangle holds tiles_m - tm tiles
+        tm = 0;
+        int rem = tile;
+        while (rem >= tiles_m - tm) {
+            rem -= tiles_m - tm;
+            ++tm;
+        }
+        tn = tm + rem;
+    }
     const int m0 = tm * G64, n0 = tn * G64;
     const int64_t k0 = (int64_t)chunk * kchunk;
     const int64_t k1 = min(K, k0 + kchunk);
@@ -393,12 +405,24 @@ __global__ __launch_bounds__(256) void k_gram_tiny(const zc* const* ta, const zc
 }
 
 // one wave per output element: lanes stride over the chunks, then a shuffle tree
-__global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz) {
+// htile > 0: Hermitian product computed on the tiles (of htile rows) with tm <= tn only;
+// an element of a lower tile is the conjugate of its mirror
+__global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, int MA, int NB, int nchunk, int nz,
+                                                     int htile) {
     const size_t per = (size_t)MA * NB;
     const size_t idx = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
     const int lane = threadIdx.x % 64;
     if (idx >= per * nz) return;
-    const size_t z = idx / per, e = idx % per;
+    const size_t z = idx / per;
+    size_t e = idx % per;
+    bool mirror = false;
+    if (htile > 0) {
+        const int m = (int)(e / NB), n = (int)(e % NB);
+        if (m / htile > n / htile) {
+            e = (size_t)n * NB + m;
+            mirror = true;
+        }
+    }
     double re = 0.0, im = 0.0;
     for (int c = lane; c < nchunk; c += 64) {
         zc v = part[(z * nchunk + c) * per + e];
@@ -409,7 +433,7 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const zc* part, zc* out, in
         re += __shfl_down(re, off, 64);
         im += __shfl_down(im, off, 64);
     }
-    if (lane == 0) out[idx] = mk<double>(re, im);
+    if (lane == 0) out[idx] = mk<double>(re, mirror ? -im : im);
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,8 +1394,14 @@ static bool gram_mfma_enabled() {
     return !(e && e[0] == '0');
 }
 
+// MBKS_GRAM_HERM=0 computes Hermitian products on every tile (for cross-checks)
+static bool gram_herm_enabled() {
+    const char* e = getenv("MBKS_GRAM_HERM");
+    return !(e && e[0] == '0');
+}
+
 mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int NB, int nz, int64_t K, void* out,
-                     void* scratch, size_t scratch_bytes, hipStream_t s) {
+                     void* scratch, size_t scratch_bytes, hipStream_t s, bool herm) {
     if (MA <= 0 || NB <= 0 || nz <= 0) return MB_OK;
     const bool tiny = MA <= TINY && NB <= TINY;  // all outputs of a chunk in one block
     const bool skinny = !tiny && MA <= SKINNY;    // one block per output column
@@ -1381,7 +1411,9 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     const bool wide = big && MA >= 256 && NB >= 256 && gram64_enabled();
     const int tile = wide ? G64 : big ? GT2 : GT, kstep = (tiny || skinny) ? 256 : wide ? GK64 : big ? GK2 : GK;
     int tiles_m = (MA + tile - 1) / tile, tiles_n = (NB + tile - 1) / tile;
-    int ntiles = tiny ? nz : skinny ? NB * nz : tiles_m * tiles_n * nz;
+    // Hermitian products on the matrix cores: the upper tiles only
+    const bool htri = herm && MA == NB && wide && gram_mfma_enabled() && gram_herm_enabled();
+    int ntiles = tiny ? nz : skinny ? NB * nz : (htri ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n) * nz;
     // at least 256 (64 for the wide tiles) k per chunk; about 1024 blocks in all
     // (4096 for the narrow kernel, whose blocks are short; the tiny kernel's blocks end
     // in a reduction of up to 64 sums, so they take longer k ranges)
@@ -1406,9 +1438,10 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
         hipLaunchKernelGGL(k_gram_skinny, grid, dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB,
                            K, kchunk, nchunk, (zc*)scratch);
     else if (wide && gram_mfma_enabled())
-        hipLaunchKernelGGL(k_gram_mfma, dim3((unsigned)(tiles_m * tiles_n * nchunk * nz)), dim3(256), 0, s,
-                           (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk, tiles_m, tiles_n,
-                           (zc*)scratch);
+        hipLaunchKernelGGL(k_gram_mfma,
+                           dim3((unsigned)((htri ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n) * nchunk * nz)),
+                           dim3(256), 0, s, (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk,
+                           tiles_m, tiles_n, (zc*)scratch, htri ? 1 : 0);
     else if (wide)
         hipLaunchKernelGGL(k_gram64, dim3((unsigned)(tiles_m * tiles_n * nchunk * nz)), dim3(256), 0, s,
                            (const zc* const*)ta, (const zc* const*)tb, MA, NB, K, kchunk, nchunk, tiles_m, tiles_n,
@@ -1422,7 +1455,7 @@ mb_status dense_gram(const void* const* ta, const void* const* tb, int MA, int N
     MB_HIP_TRY(hipGetLastError());
     size_t tot = (size_t)MA * NB * nz;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot * 64 + 255) / 256)), dim3(256), 0, s, (const zc*)scratch,
-                       (zc*)out, MA, NB, nchunk, nz);
+                       (zc*)out, MA, NB, nchunk, nz, htri ? tile : 0);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }

@@ -117,8 +117,11 @@ struct Solver {
 
     // global Rayleigh-Ritz over the first n vectors of X (n = M or NG): keep M lowest
     mb_status global_rr(int n) {
-        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tHX, n, n, 1, K, Hp, gscratch, gscratch_bytes, s));
-        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tSX, n, n, 1, K, Sp, gscratch, gscratch_bytes, s));
+        // X^H H X and X^H S X are Hermitian: the matrix-core path computes half of each
+        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tHX, n, n, 1, K, Hp, gscratch, gscratch_bytes, s,
+                          true));
+        LZ_TRY(dense_gram((const void* const*)tX, (const void* const*)tSX, n, n, 1, K, Sp, gscratch, gscratch_bytes, s,
+                          true));
         LZ_TRY(dense_geneig(Hp, Sp, n, 1, evals, Y, gwork, status, s));
         LZ_TRY(dense_copy_cols(Y, n, M, n, W, s));
         LZ_TRY(dense_combo((const void* const*)tX, tXn, W, n, M, 1, K, 1.0, 0.0, s, low));

@@ -143,16 +143,19 @@ def test_lanczos_buffer_vectors(extra):
     p.close()
 
 
-@pytest.mark.parametrize("mfma", ["1", "0"])
+@pytest.mark.parametrize("mfma", ["1", "full", "0"])
 def test_lanczos_many_roots_wide_gram(mfma, monkeypatch):
     # 280 roots of the tiny cell (296 iterated vectors with the buffer, 298 with the
     # global Krylov vectors): the Gram products of the global Rayleigh-Ritz and
     # orthogonalisation steps take the 64 x 64-tile path, on the FP64 matrix cores
-    # (mfma = 1) or the vector kernel (mfma = 0)
+    # (mfma = 1: the Hermitian Rayleigh-Ritz products on the upper tiles only; full:
+    # every tile) or the vector kernel (mfma = 0)
     d = workloads.tiny()
     nev = 280
     print(f"[case] lanczos tiny nev={nev} mfma={mfma}", flush=True)
-    monkeypatch.setenv("MBKS_GRAM_MFMA", mfma)
+    monkeypatch.setenv("MBKS_GRAM_MFMA", "0" if mfma == "0" else "1")
+    if mfma == "full":
+        monkeypatch.setenv("MBKS_GRAM_HERM", "0")
     ref = solve.solve_problem(d, 0, nev=nev)[3]
     p = mbks.Problem(d, device=0)
     eig, x, info, st = p.lanczos_lowest(0, nev, "fp64")
