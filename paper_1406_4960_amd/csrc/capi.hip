@@ -53,7 +53,7 @@ void free_all(Problem* p) {
     if (p->device < 0) return;
     void* ptrs[] = {p->d_bval, p->d_bvalf, p->d_wbval, p->d_wbvalf, p->d_sband, p->d_sbandf, p->d_dband,
                     p->d_dbandf, p->d_lband, p->d_lbandf, p->d_Z, p->d_Zf, p->d_E, p->d_Ef, p->d_zwin,
-                    p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin,
+                    p->d_V, p->d_Vf, p->d_Vt, p->d_Vtf, p->d_tw1, p->d_tw1f, p->d_tw2, p->d_tw2f, p->d_gwin, p->d_rgoff, p->d_rglist,
                     p->d_Q, p->d_Qf, p->d_one, p->d_onef, p->d_iband, p->d_zq, p->d_wq, p->d_gnorm,
                     p->ws_hartree.ptr};
     for (void* q : ptrs)

@@ -15,6 +15,7 @@
 // both: D[4(l/16)+r][l%16], r < 4.  The order of the k sum inside a step is free,
 // so lane group g = l/16 takes the contiguous k range of its step.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "cplx.h"
@@ -89,6 +90,78 @@ __global__ __launch_bounds__(64) void k_nlproj_f32(const cx<TI>* c, const cx<flo
     }
 }
 
+// The same FP32 partials with up to MG projector groups per wave: the groups are the
+// ones whose z window holds the wave's spline row (slot blockIdx.z * MG + j of the row's
+// list), so the row's 16 band chunks are loaded once per k step and multiplied into the
+// accumulators of every group instead of once per group (on the 128x64 surface slab a row
+// lies in the windows of 7.4 groups on average).  Each group's products are issued in the
+// same order as in k_nlproj_f32, so the partials are the same.
+template <typename TI, int MG>
+__global__ __launch_bounds__(64) void k_nlproj_f32m(const cx<TI>* c, const cx<float>* F, const float* Z,
+                                                    const int32_t* rgoff, const int32_t* rglist,
+                                                    cx<float>* partial, int nbands, int np, int ng, int nb, int ld,
+                                                    int npad, int nbpad) {
+    const int i = blockIdx.x;
+    const int b0 = blockIdx.y * 16;
+    const int s0 = rgoff[i] + blockIdx.z * MG;
+    const int nslot = min(MG, rgoff[i + 1] - s0);
+    if (nslot <= 0) return;
+    const int lane = threadIdx.x;
+    const int m = lane % 16, g = lane / 16;
+    const int b = b0 + m;
+    const cx<TI>* cb = c + ((size_t)min(b, nbands - 1) * nb + i) * ld;
+    int grp[MG];
+    const cx<float>* Fp[MG];
+    v4f accr[MG], acci[MG];
+#pragma unroll
+    for (int j = 0; j < MG; ++j) {
+        grp[j] = j < nslot ? rglist[s0 + j] : 0;
+        Fp[j] = F + (size_t)min(grp[j] * 16 + m, np - 1) * ld;
+        accr[j] = v4f{0, 0, 0, 0};
+        acci[j] = v4f{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < ng; k0 += 16) {
+        cx<float> cv[4];
+        bool in[4];
+        int kc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * g + s;
+            in[s] = k < ng;
+            kc[s] = in[s] ? k : 0;
+            const cx<float> v = ldc<TI>(cb + kc[s]);
+            cv[s] = in[s] ? v : mk<float>(0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < MG; ++j) {
+            if (j >= nslot) break;
+            cx<float> fa[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const cx<float> fv = Fp[j][kc[s]];
+                fa[s] = in[s] ? fv : mk<float>(0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                accr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s].x, cv[s].x, accr[j], 0, 0, 0);
+                accr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s].y, cv[s].y, accr[j], 0, 0, 0);
+                acci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s].x, cv[s].y, acci[j], 0, 0, 0);
+                acci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[s].y, cv[s].x, acci[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MG; ++j) {
+        if (j >= nslot) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pr = grp[j] * 16 + 4 * g + r;
+            const float z = pr < np ? Z[(size_t)pr * nb + i] : 0.0f;
+            partial[((size_t)i * npad + pr) * nbpad + b0 + m] = mk<float>(z * accr[j][r], z * acci[j][r]);
+        }
+    }
+}
+
 // the same partials in FP64 on v_mfma_f64_16x16x4_f64, whose output layout differs:
 // lane l holds D[4r + l/16][l%16] (checked on gfx950)
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -139,6 +212,74 @@ __global__ __launch_bounds__(64) void k_nlproj_f64(const cx<double>* c, const cx
         const int pr = grp * 16 + 4 * r + g;
         const double z = pr < np ? Z[(size_t)pr * nb + i] : 0.0;
         partial[((size_t)i * npad + pr) * nbpad + b0 + m] = mk<double>(z * accr[r], z * acci[r]);
+    }
+}
+
+// FP64 partials with up to MG projector groups per wave (as k_nlproj_f32m); the FP64
+// output layout D[4r + l/16][l%16]
+template <int MG>
+__global__ __launch_bounds__(64) void k_nlproj_f64m(const cx<double>* c, const cx<double>* F, const double* Z,
+                                                    const int32_t* rgoff, const int32_t* rglist,
+                                                    cx<double>* partial, int nbands, int np, int ng, int nb, int ld,
+                                                    int npad, int nbpad) {
+    const int i = blockIdx.x;
+    const int b0 = blockIdx.y * 16;
+    const int s0 = rgoff[i] + blockIdx.z * MG;
+    const int nslot = min(MG, rgoff[i + 1] - s0);
+    if (nslot <= 0) return;
+    const int lane = threadIdx.x;
+    const int m = lane % 16, g = lane / 16;
+    const int b = b0 + m;
+    const cx<double>* cb = c + ((size_t)min(b, nbands - 1) * nb + i) * ld;
+    int grp[MG];
+    const cx<double>* Fp[MG];
+    v4d accr[MG], acci[MG];
+#pragma unroll
+    for (int j = 0; j < MG; ++j) {
+        grp[j] = j < nslot ? rglist[s0 + j] : 0;
+        Fp[j] = F + (size_t)min(grp[j] * 16 + m, np - 1) * ld;
+        accr[j] = v4d{0, 0, 0, 0};
+        acci[j] = v4d{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < ng; k0 += 16) {
+        cx<double> cv[4];
+        bool in[4];
+        int kc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * g + s;
+            in[s] = k < ng;
+            kc[s] = in[s] ? k : 0;
+            const cx<double> v = cb[kc[s]];
+            cv[s] = in[s] ? v : mk<double>(0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < MG; ++j) {
+            if (j >= nslot) break;
+            cx<double> fa[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const cx<double> fv = Fp[j][kc[s]];
+                fa[s] = in[s] ? fv : mk<double>(0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].x, cv[s].x, accr[j], 0, 0, 0);
+                accr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].y, cv[s].y, accr[j], 0, 0, 0);
+                acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[s].x, cv[s].y, acci[j], 0, 0, 0);
+                acci[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-fa[s].y, cv[s].x, acci[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MG; ++j) {
+        if (j >= nslot) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pr = grp[j] * 16 + 4 * r + g;
+            const double z = pr < np ? Z[(size_t)pr * nb + i] : 0.0;
+            partial[((size_t)i * npad + pr) * nbpad + b0 + m] = mk<double>(z * accr[j][r], z * acci[j][r]);
+        }
     }
 }
 
@@ -259,6 +400,20 @@ mb_status upload_group_windows(Problem* p) {
     }
     MB_HIP_TRY(hipMalloc(&p->d_gwin, gw.size() * sizeof(int32_t)));
     MB_HIP_TRY(hipMemcpy(p->d_gwin, gw.data(), gw.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> off(p->nb + 1, 0), list;
+    p->rg_max = 0;
+    for (int i = 0; i < p->nb; ++i) {
+        off[i] = (int32_t)list.size();
+        for (int gi = 0; gi < ngrp; ++gi)
+            if (gw[2 * gi] <= i && i <= gw[2 * gi + 1]) list.push_back(gi);
+        p->rg_max = std::max(p->rg_max, (int)list.size() - off[i]);
+    }
+    off[p->nb] = (int32_t)list.size();
+    if (list.empty()) list.push_back(0);
+    MB_HIP_TRY(hipMalloc(&p->d_rgoff, off.size() * sizeof(int32_t)));
+    MB_HIP_TRY(hipMemcpy(p->d_rgoff, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    MB_HIP_TRY(hipMalloc(&p->d_rglist, list.size() * sizeof(int32_t)));
+    MB_HIP_TRY(hipMemcpy(p->d_rglist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     return MB_OK;
 }
 
@@ -284,10 +439,19 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
     }
     StageScope ts_(MB_STAGE_NL_PROJECT, s, nbands);
     dim3 grid(p->nb, nbpad / 16, ngrp);
+    const char* multi_env = getenv("MBKS_NL_MULTI");
+    const bool multi = !(multi_env && multi_env[0] == '0') && p->d_rgoff && p->rg_max > 1;
+    constexpr int MG = 4;  // projector groups per wave (MBKS_NL_MULTI=0: one)
+    const dim3 gm(p->nb, nbpad / 16, (std::max(p->rg_max, 1) + MG - 1) / MG);
     if (mode == 0) {
         cx<double>* part64 = (cx<double>*)nlpart;
-        hipLaunchKernelGGL(k_nlproj_f64, grid, dim3(64), 0, s, (const cx<double>*)c, (const cx<double>*)kp.d_F64,
-                           p->d_Z, p->d_gwin, part64, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
+        if (multi)
+            hipLaunchKernelGGL(k_nlproj_f64m<MG>, gm, dim3(64), 0, s, (const cx<double>*)c,
+                               (const cx<double>*)kp.d_F64, p->d_Z, p->d_rgoff, p->d_rglist, part64, nbands, p->np,
+                               kp.ng, p->nb, ld, npad, nbpad);
+        else
+            hipLaunchKernelGGL(k_nlproj_f64, grid, dim3(64), 0, s, (const cx<double>*)c, (const cx<double>*)kp.d_F64,
+                               p->d_Z, p->d_gwin, part64, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
         MB_HIP_TRY(hipGetLastError());
         const int tot = nbands * p->np;
         const double* sc = scale == PROJ_Q ? p->d_Q : scale == PROJ_ONE ? p->d_one : p->d_E;
@@ -298,7 +462,14 @@ mb_status launch_nl_project_mfma(Problem* p, int ik, const void* c, void* proj, 
     }
     cx<float>* part = (cx<float>*)nlpart;
     const cx<float>* F = (const cx<float>*)kp.d_F32;
-    if (mode == 1) {
+    if (mode == 1 && multi) {
+        if (vin64)
+            hipLaunchKernelGGL((k_nlproj_f32m<double, MG>), gm, dim3(64), 0, s, (const cx<double>*)c, F, p->d_Zf,
+                               p->d_rgoff, p->d_rglist, part, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
+        else
+            hipLaunchKernelGGL((k_nlproj_f32m<float, MG>), gm, dim3(64), 0, s, (const cx<float>*)c, F, p->d_Zf,
+                               p->d_rgoff, p->d_rglist, part, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);
+    } else if (mode == 1) {
         if (vin64)
             hipLaunchKernelGGL(k_nlproj_f32<double>, grid, dim3(64), 0, s, (const cx<double>*)c, F, p->d_Zf,
                                p->d_gwin, part, nbands, p->np, kp.ng, p->nb, ld, npad, nbpad);

@@ -155,6 +155,11 @@ struct Problem {
     double* d_iband = nullptr;  // identity band (nb x kappa): the combine pass as y = c + expansion
     int32_t* d_zwin = nullptr;
     int32_t* d_gwin = nullptr;  // union z-window of each group of 16 projectors
+    // per spline row i: the groups of 16 projectors whose union z-window holds it
+    // (d_rgoff[i] .. d_rgoff[i+1] into d_rglist); rg_max = the largest count
+    int32_t* d_rgoff = nullptr;
+    int32_t* d_rglist = nullptr;
+    int rg_max = 0;
     double* d_V = nullptr;     float* d_Vf = nullptr;   // nzq x N1 x N2
     double* d_Vt = nullptr;    float* d_Vtf = nullptr;  // nzq x N2 x N1 (plane kernel grids only)
     void* d_tw1 = nullptr; void* d_tw1f = nullptr;      // N1 twiddles exp(+2 pi i k / N1)

@@ -303,6 +303,26 @@ def test_projector_matrix_cores_match_vector_kernel(cfg, monkeypatch):
     p.close()
 
 
+@pytest.mark.parametrize("cfg,nbands", [("surface", 19), ("graphene_2x2", 21)])
+def test_projector_groups_per_wave_give_the_same_projections(cfg, nbands, monkeypatch):
+    # FP32 and FP64 matrix-core projections with up to 4 projector groups per wave (default
+    # when a spline row lies in the windows of several groups) against one group per wave:
+    # each group's products are issued in the same order, so H c is the same to rounding
+    d = workloads.CONFIGS[cfg]()
+    print(f"[case] projector groups per wave {cfg}", flush=True)
+    p, dm, _ = _setup(d, 0)
+    x = random_lib_block(43, nbands, dm["nb"], dm["ng"], dm["ld"])
+    monkeypatch.setenv("MBKS_NL_KERNEL", "mfma")
+    y_multi = _run(p, "hpsi", 0, x, "fp32")
+    y64_multi = _run(p, "hpsi", 0, x, "fp64")
+    monkeypatch.setenv("MBKS_NL_MULTI", "0")
+    y_one = _run(p, "hpsi", 0, x, "fp32")
+    y64_one = _run(p, "hpsi", 0, x, "fp64")
+    p.close()
+    assert rel_err(y_multi, y_one) < 1e-7
+    assert rel_err(y64_multi, y64_one) < 1e-15
+
+
 @pytest.mark.parametrize("cfg,prec,nbands,kernel", [("graphene_2x2", "fp64", 5, "default"),
                                                     ("graphene_2x2", "fp32", 5, "default"),
                                                     ("surface", "fp64", 2, "default"), ("surface", "fp32", 3, "default"),
