@@ -18,6 +18,7 @@
 // Lane layouts (gfx950): A[l%16][l/16], B[l/16][l%16]; output f32: D[4(l/16)+r][l%16],
 // f64: D[4r + l/16][l%16], r < 4.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "cplx.h"
@@ -28,7 +29,6 @@ namespace mb {
 namespace {
 
 constexpr int KORD = 4;
-constexpr int ZC_BB = 4;  // bands per wave
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -69,7 +69,7 @@ struct ZArgs {
 
 // One workgroup = 4 waves = 4 consecutive 16-column tiles of one 16-row tile, for
 // ZC_BB bands.  AUG: sy also takes the projector expansion of projq.
-template <typename TI, typename T, bool AUG>
+template <typename TI, typename T, bool AUG, int ZC_BB>
 __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
     using A = MfmaAcc<T>;
     using V = typename A::type;
@@ -256,12 +256,34 @@ mb_status zcombine_impl(Problem* p, int ik, const void* c, const void* u, const 
     a.nzq = p->nzq;
     a.np = p->np;
     if (p->np > 0 && !p->d_gwin) return set_error(MB_ERR_INVALID_ARG, "projector group windows not uploaded");
-    const dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((p->nb + 15) / 16), (unsigned)((nbands + ZC_BB - 1) / ZC_BB));
+    // bands per wave: 2 (MBKS_ZC_BANDS=1, 4 or 8 selects 1, 4 or 8).  Measured on the
+    // 128x64 surface slab, 320 bands: FP64 9.3 ms with 2 against 11.9 (4) and 18.7 (8);
+    // FP32 5.9 against 6.1 and 6.8 (more waves per SIMD hide the plane-row loads better)
+    const char* zb = getenv("MBKS_ZC_BANDS");
+    const int bbz = zb && zb[0] == '8' ? 8 : zb && zb[0] == '4' ? 4 : zb && zb[0] == '1' ? 1 : 2;
+    const dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((p->nb + 15) / 16), (unsigned)((nbands + bbz - 1) / bbz));
     StageScope ts_(MB_STAGE_COMBINE, s, nbands);
-    if (a.projq)
-        hipLaunchKernelGGL((k_zcombine<TI, T, true>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_zcombine<TI, T, false>), grid, dim3(256), 0, s, a);
+    if (bbz == 8) {
+        if (a.projq)
+            hipLaunchKernelGGL((k_zcombine<TI, T, true, 8>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_zcombine<TI, T, false, 8>), grid, dim3(256), 0, s, a);
+    } else if (bbz == 4) {
+        if (a.projq)
+            hipLaunchKernelGGL((k_zcombine<TI, T, true, 4>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_zcombine<TI, T, false, 4>), grid, dim3(256), 0, s, a);
+    } else if (bbz == 1) {
+        if (a.projq)
+            hipLaunchKernelGGL((k_zcombine<TI, T, true, 1>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_zcombine<TI, T, false, 1>), grid, dim3(256), 0, s, a);
+    } else {
+        if (a.projq)
+            hipLaunchKernelGGL((k_zcombine<TI, T, true, 2>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_zcombine<TI, T, false, 2>), grid, dim3(256), 0, s, a);
+    }
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }

@@ -323,6 +323,26 @@ def test_projector_groups_per_wave_give_the_same_projections(cfg, nbands, monkey
     assert rel_err(y64_multi, y64_one) < 1e-15
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zcombine_bands_per_wave_variants_match(prec, monkeypatch):
+    # the matrix-core combine pass with 1, 4 and 8 bands per wave against the default 2, on
+    # the surface slab with augmentation charges and a ragged band count
+    d = workloads.with_augmentation(workloads.surface())
+    print(f"[case] zcombine bands per wave {prec}", flush=True)
+    p, dm, _ = _setup(d, 0)
+    x = random_lib_block(44, 11, dm["nb"], dm["ng"], dm["ld"])
+    ref = _run(p, "hpsi", 0, x, prec)
+    ref_s = _run(p, "spsi", 0, x, prec)
+    for zb in ("1", "4", "8"):
+        monkeypatch.setenv("MBKS_ZC_BANDS", zb)
+        got = _run(p, "hpsi", 0, x, prec)
+        got_s = _run(p, "spsi", 0, x, prec)
+        assert rel_err(got, ref) < (1e-14 if prec == "fp64" else 1e-6), zb
+        assert rel_err(got_s, ref_s) < (1e-14 if prec == "fp64" else 1e-6), zb
+    monkeypatch.delenv("MBKS_ZC_BANDS")
+    p.close()
+
+
 @pytest.mark.parametrize("cfg,prec,nbands,kernel", [("graphene_2x2", "fp64", 5, "default"),
                                                     ("graphene_2x2", "fp32", 5, "default"),
                                                     ("surface", "fp64", 2, "default"), ("surface", "fp32", 3, "default"),
