@@ -353,7 +353,9 @@ typedef struct {
                              converge); < 0: min(16, max(4, nev / 4)) */
     int32_t dense_low;    /* MB_FP32/MB_BF16X3: 1 (default) = during the reduced-precision cycles the
                              vector combinations of 128 or more vectors (rotations, Gram-Schmidt
-                             updates) use FP32 matrix-core arithmetic on the FP64 vectors; 0 = FP64
+                             updates) use FP32 matrix-core arithmetic on the FP64 vectors, and the
+                             Krylov vectors are orthogonalised against the trial vectors in one
+                             classical Gram-Schmidt pass instead of two; 0 = FP64 and two passes
                              throughout.  Gram products stay FP64 (the projected problems need their
                              overlap matrices to FP64 accuracy); the FP64 cycles that finish the
                              solve are unaffected. */
@@ -382,8 +384,12 @@ void mb_lanczos_default_opts(mb_lanczos_opts* opts);
  * K (H - theta S), K = (T + sigma S)^{-1}.
  * prec = MB_FP64: all in FP64.  MB_FP32 / MB_BF16X3: H is applied in reduced
  * precision until every residual is below opts->switch_tol, then the solve
- * continues in FP64 (orthonormalisation, Krylov coefficients and every
- * projected eigenproblem are FP64 throughout).
+ * continues in FP64 (Gram products, Krylov coefficients and every projected
+ * eigenproblem are FP64 throughout; opts->dense_low sets the vector combinations
+ * and Gram-Schmidt passes of the reduced-precision cycles).
+ * Soft locking: a block whose residuals are all <= opts->tol sits out the block
+ * cycle (its vectors stay in every global Rayleigh-Ritz step) until a residual
+ * rises above opts->tol again.
  * x0: device complex128 [nev][N_b][ld] start vectors, or NULL for a seeded random
  * start.  eig: host, nev doubles (ascending).  x: device complex128
  * [nev][N_b][ld] output, S-orthonormal.  info and opts may be NULL (defaults).

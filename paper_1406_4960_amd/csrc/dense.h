@@ -30,8 +30,11 @@ mb_status dense_random(void* x, int nvec, int nb, int ld, int ng, uint64_t seed,
 size_t geneig_work_bytes(int N, int nz);
 mb_status dense_geneig(const void* H, const void* S, int N, int nz, double* evals, void* Y, void* gwork,
                        int* status, hipStream_t s, int* sweeps = nullptr);
+// map (device, nblocks entries, or null): block z's roots go to theta[map[z] * b + a]
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
-                       hipStream_t s);
+                       hipStream_t s, const int32_t* map = nullptr);
+// dst[v] = src[v] (K elements each) for the n vectors of two device pointer tables
+mb_status dense_copy_tab(void* const* dst, const void* const* src, int n, int64_t K, hipStream_t s);
 mb_status dense_copy_cols(const void* Y, int ldy, int ncols, int nrows, void* out, hipStream_t s);
 
 }  // namespace mb

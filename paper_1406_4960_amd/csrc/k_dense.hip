@@ -1322,7 +1322,9 @@ __global__ __launch_bounds__(256) void k_jacobi_round(zc* gwork, int N, int s, i
 // then any unpicked Ritz value among the b lowest replaces the highest picked
 // one (new roots).  Writes coefficient columns C_z (nr x b) and theta.
 // ---------------------------------------------------------------------------
-__global__ void k_select(const zc* Ys, const double* ev, int nr, int b, zc* C, double* theta_out, int nblocks) {
+// map (optional): block z's roots go to theta_out[map[z] * b + a] (a subset of the blocks)
+__global__ void k_select(const zc* Ys, const double* ev, int nr, int b, zc* C, double* theta_out, int nblocks,
+                         const int32_t* map) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= nblocks) return;
     const zc* Y = Ys + (size_t)z * nr * nr;
@@ -1361,9 +1363,17 @@ __global__ void k_select(const zc* Ys, const double* ev, int nr, int b, zc* C, d
     }
     for (int a = 0; a < b; ++a) {
         int r = pick[a];
-        theta_out[(size_t)z * b + a] = e[r];
+        theta_out[(size_t)(map ? map[z] : z) * b + a] = e[r];
         for (int i = 0; i < nr; ++i) C[((size_t)z * nr + i) * b + a] = Y[(size_t)i * nr + r];
     }
+}
+
+// dst[v][k] = src[v][k] for v < n (blockIdx.y), k < K
+__global__ void k_copy_tab(zc* const* dst, const zc* const* src, int64_t K) {
+    const zc* a = src[blockIdx.y];
+    zc* o = dst[blockIdx.y];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
+        o[k] = a[k];
 }
 
 __global__ void k_copy_cols(const zc* Y, int ldy, int ncols, int nrows, zc* out) {
@@ -1608,11 +1618,21 @@ size_t geneig_work_bytes(int N, int nz) {
 }
 
 mb_status dense_select(const void* Y, const double* ev, int nr, int b, void* C, double* theta, int nblocks,
-                       hipStream_t s) {
+                       hipStream_t s, const int32_t* map) {
     StageScope ts_(MB_STAGE_OTHER, s);
     if (b > 32 || nr > 64) return set_error(MB_ERR_INVALID_ARG, "block too large for selection");
     hipLaunchKernelGGL(k_select, dim3((nblocks + 63) / 64), dim3(64), 0, s, (const zc*)Y, ev, nr, b, (zc*)C, theta,
-                       nblocks);
+                       nblocks, map);
+    MB_HIP_TRY(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status dense_copy_tab(void* const* dst, const void* const* src, int n, int64_t K, hipStream_t s) {
+    if (n <= 0 || K <= 0) return MB_OK;
+    if (n > 65535) return set_error(MB_ERR_INVALID_ARG, "dense_copy_tab: too many vectors");
+    StageScope ts_(MB_STAGE_OTHER, s);
+    const unsigned gx = (unsigned)std::min<int64_t>((K + 255) / 256, 256);
+    hipLaunchKernelGGL(k_copy_tab, dim3(gx, (unsigned)n), dim3(256), 0, s, (zc* const*)dst, (const zc* const*)src, K);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
