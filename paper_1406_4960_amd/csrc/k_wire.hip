@@ -372,23 +372,41 @@ __global__ __launch_bounds__(256) void k_wire_combine(WCombineArgs<TI, T> a) {
     cx<double> kin[WJB], sc[WJB];
 #pragma unroll
     for (int t = 0; t < WJB; ++t) kin[t] = sc[t] = mk<double>(0, 0);
-    for (int i2 = max(0, i - 3); i2 <= min(a.nbx - 1, i + 3); ++i2) {
-        const double sxv = band_at(a.sx, i, i2), dxv = band_at(a.dx, i, i2);
+    // Banded sums over x (i2 = i - 3 .. i + 3) and z (the chunk's rows +- 3).  Loads take
+    // clamped, valid indices and out-of-range terms get zero coefficients, so that no
+    // load sits under a branch (the compiler waits for every load in flight where
+    // branches join, which serialized these loads)
+    for (int di = -(KORD - 1); di <= KORD - 1; ++di) {
+        const int i2r = i + di;
+        const bool iok = i2r >= 0 && i2r < a.nbx;
+        const int i2 = iok ? i2r : i;
+        const int xlo = min(i, i2), xd = iok ? (di >= 0 ? di : -di) : 0;
+        const double sx0 = a.sx[xlo * KORD + xd], dx0 = a.dx[xlo * KORD + xd];
+        const double sxv = iok ? sx0 : 0.0, dxv = iok ? dx0 : 0.0;
         const cx<TI>* cr = a.c + vb + (size_t)i2 * a.nbz * a.ld + g;
+        cx<TI> cv[WJB + 2 * (KORD - 1)];
+#pragma unroll
+        for (int u = 0; u < WJB + 2 * (KORD - 1); ++u) {
+            const int jj = min(max(j0 - (KORD - 1) + u, 0), a.nbz - 1);
+            cv[u] = cr[(size_t)jj * a.ld];
+        }
         cx<double> az[WJB], dz[WJB];
 #pragma unroll
         for (int t = 0; t < WJB; ++t) az[t] = dz[t] = mk<double>(0, 0);
 #pragma unroll
-        for (int u = 0; u < WJB + 6; ++u) {
-            const int jj = j0 - 3 + u;
-            if (jj < 0 || jj >= a.nbz) continue;
-            const cx<TI> cv = cr[(size_t)jj * a.ld];
-            const double vr = (double)cv.x, vi = (double)cv.y;
+        for (int u = 0; u < WJB + 2 * (KORD - 1); ++u) {
+            const int jj = j0 - (KORD - 1) + u;
+            const bool jok = jj >= 0 && jj < a.nbz;
+            const double vr = (double)cv[u].x, vi = (double)cv[u].y;
 #pragma unroll
             for (int t = 0; t < WJB; ++t) {
-                const int dj = u - 3 - t;
-                if (dj < -3 || dj > 3 || j0 + t >= a.nbz) continue;
-                const double sv = band_at(a.sz, j0 + t, jj), dv = band_at(a.dz, j0 + t, jj);
+                const int dj = u - (KORD - 1) - t;
+                if (dj < -(KORD - 1) || dj > KORD - 1) continue;  // compile-time
+                const int j = j0 + t;
+                const bool ok = jok && j < a.nbz;
+                const int zlo = ok ? min(j, jj) : 0, zd = dj >= 0 ? dj : -dj;
+                const double s0 = a.sz[zlo * KORD + zd], d0 = a.dz[zlo * KORD + zd];
+                const double sv = ok ? s0 : 0.0, dv = ok ? d0 : 0.0;
                 az[t].x = fma(sv, vr, az[t].x);
                 az[t].y = fma(sv, vi, az[t].y);
                 dz[t].x = fma(dv, vr, dz[t].x);
@@ -425,8 +443,9 @@ __global__ __launch_bounds__(256) void k_wire_combine(WCombineArgs<TI, T> a) {
 #pragma unroll
             for (int t = 0; t < WJB; ++t) {
                 const int tt = j0 + t - s + 1;
-                if (tt < 0 || tt > 3 || j0 + t >= a.nbz) continue;
-                rfma(v[t], a.wbz[(size_t)p * KORD + tt], f);
+                const bool ok = tt >= 0 && tt < KORD && j0 + t < a.nbz;
+                const T w0 = a.wbz[(size_t)p * KORD + (ok ? tt : 0)];
+                rfma(v[t], ok ? w0 : (T)0, f);
             }
         }
     }

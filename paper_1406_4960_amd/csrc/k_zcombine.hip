@@ -183,46 +183,57 @@ __global__ __launch_bounds__(256) void k_zcombine(ZArgs<TI, T> a) {
         }
     }
     if (Gm >= a.ld) return;
-    const double kk = gv ? 0.5 * a.kg2[Gm] : 0.0;
+    // Banded kinetic and overlap sums and the stores.  Every load takes a clamped, valid
+    // index and out-of-range terms are masked afterwards, so that no load sits under a
+    // lane-dependent branch (the compiler waits for every load in flight where such
+    // branches join, which would serialize the c-row and band loads)
+    const int Gc = gv ? Gm : 0;
+    const double kk = gv ? 0.5 * a.kg2[Gc] : 0.0;
 #pragma unroll
-    for (int bb = 0; bb < ZC_BB; ++bb) {
-        if (bb >= nbg) break;
-        const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + A::row(g, r);
+        const bool rowok = i < a.nb;
+        const int ic = rowok ? i : a.nb - 1;
+        double sv[2 * KORD - 1], tv[2 * KORD - 1];
+        int jr[2 * KORD - 1];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = i0 + A::row(g, r);
-            if (i >= a.nb) continue;
-            if (!gv) {
-                a.y[vb + (size_t)i * a.ld + Gm] = mk<TI>(0, 0);
-                if (a.sy) a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>(0, 0);
-                continue;
-            }
+        for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
+            const int j = ic + d;
+            const bool ok = j >= 0 && j < a.nb;
+            const int jc = ok ? j : ic;
+            const int lo = d >= 0 ? ic : jc;
+            const int dd = d >= 0 ? d : -d;
+            const double s0 = a.sband[lo * KORD + dd];
+            const double d0 = a.dband[lo * KORD + dd];
+            sv[d + KORD - 1] = ok ? s0 : 0.0;
+            tv[d + KORD - 1] = ok ? 0.5 * d0 : 0.0;
+            jr[d + KORD - 1] = jc;
+        }
+#pragma unroll
+        for (int bb = 0; bb < ZC_BB; ++bb) {
+            if (bb >= nbg) break;
+            const size_t vb = (size_t)(b0 + bb) * a.nb * a.ld;
             double sr = 0, si = 0, tr = 0, ti = 0;
 #pragma unroll
-            for (int d = -(KORD - 1); d <= KORD - 1; ++d) {
-                const int j = i + d;
-                if (j < 0 || j >= a.nb) continue;
-                const int lo = d >= 0 ? i : j;
-                const int dd = d >= 0 ? d : -d;
-                const cx<TI> cv = a.c[vb + (size_t)j * a.ld + Gm];
-                const double sv = a.sband[lo * KORD + dd];
-                const double tv = 0.5 * a.dband[lo * KORD + dd];
-                sr += sv * (double)cv.x;
-                si += sv * (double)cv.y;
-                tr += tv * (double)cv.x;
-                ti += tv * (double)cv.y;
+            for (int e = 0; e < 2 * KORD - 1; ++e) {
+                const cx<TI> cv = a.c[vb + (size_t)jr[e] * a.ld + Gc];
+                sr += sv[e] * (double)cv.x;
+                si += sv[e] * (double)cv.y;
+                tr += tv[e] * (double)cv.x;
+                ti += tv[e] * (double)cv.y;
             }
-            if (a.sy) {
-                double qr = 0.0, qi = 0.0;
-                if constexpr (AUG) {
-                    qr = (double)accq[bb][0][r];
-                    qi = (double)accq[bb][1][r];
-                }
-                a.sy[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)(sr + qr), (TI)(si + qi));
+            double qr = 0.0, qi = 0.0;
+            if constexpr (AUG) {
+                qr = (double)accq[bb][0][r];
+                qi = (double)accq[bb][1][r];
             }
             const double yr = tr + kk * sr + (double)acc[bb][0][r];
             const double yi = ti + kk * si + (double)acc[bb][1][r];
-            a.y[vb + (size_t)i * a.ld + Gm] = mk<TI>((TI)yr, (TI)yi);
+            if (rowok) {
+                // padding columns (G >= N_G) get zeros
+                a.y[vb + (size_t)i * a.ld + Gm] = gv ? mk<TI>((TI)yr, (TI)yi) : mk<TI>(0, 0);
+                if (a.sy) a.sy[vb + (size_t)i * a.ld + Gm] = gv ? mk<TI>((TI)(sr + qr), (TI)(si + qi)) : mk<TI>(0, 0);
+            }
         }
     }
 }
