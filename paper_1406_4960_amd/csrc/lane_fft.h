@@ -88,23 +88,86 @@ __device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, int e) {
 
 // Radix-2 decimation-in-frequency network over the Q lanes of a line (lane l of the
 // line = l): natural lane order in, lane l ends with the outputs of index bitrev(l).
-// Each stage of both networks is one fused form for every lane: y = u + s x with
-// s = -1 on the upper lane of a pair (bit m of l set) and +1 on the lower, and the
-// stage twiddle on the upper lane only (w = 1 on the lower lanes and in the last
-// stage of the DIF network / the first of the DIT network, which have none).
+// A stage pairs lanes l and l xor m: y = u + s x with s = -1 on the upper lane of the
+// pair (bit m of l set) and +1 on the lower, u the partner's value, then the stage
+// twiddle on the upper lane only (w = 1 on the lower lanes and in the last stage of the
+// DIF network / the first of the DIT network, which have none).  Where the exchange is
+// a single DPP move, the stage computes t = x + s u = s y instead, which lets the move
+// fold into the FMA as its DPP operand, and the sign s goes into the per-lane twiddle
+// (a factor of the next product, so the results are bitwise the same).
+template <typename T, int M, int Q>
+constexpr bool lane_fold() { return sizeof(T) == 4 && LaneMap<Q>::phys(M) != 4; }
+
+// DPP control of the single-move exchanges (physical xor 1, 2, 8)
+#define MB_DPP_CTRL_1 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+#define MB_DPP_CTRL_2 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+#define MB_DPP_CTRL_8 "row_ror:8 row_mask:0xf bank_mask:0xf"
+#define MB_FMAC_DPP(i, C) "v_fmac_f32_dpp %" #i ", %" #i ", %8 " C "\n"
+#define MB_FMAC_DPP4(C)                                                                                  \
+    "s_nop 1\n" MB_FMAC_DPP(0, C) MB_FMAC_DPP(1, C) MB_FMAC_DPP(2, C) MB_FMAC_DPP(3, C) MB_FMAC_DPP(4, C) \
+        MB_FMAC_DPP(5, C) MB_FMAC_DPP(6, C) MB_FMAC_DPP(7, C) "s_nop 1\n"
+
+// x[k] += s * (x[k] of physical lane p xor P), both components of 4 points, as
+// v_fmac_f32 with its DPP source operand (one instruction per component instead of a
+// DPP move and an FMA: the compiler does not fold DPP moves into FMAC).  The leading
+// s_nop covers the wait states a DPP read needs after the VALU writes of its operand
+// (the compiler inserts them for its own DPP instructions, not for inline assembly),
+// the trailing one those of any DPP read of the results that follows.
+template <int P>
+__device__ __forceinline__ void fmac_xor4(cx<float>* x, float s) {
+    static_assert(P == 1 || P == 2 || P == 8, "single-move exchange");
+    if constexpr (P == 1)
+        asm(MB_FMAC_DPP4(MB_DPP_CTRL_1)
+            : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
+              "+v"(x[3].y)
+            : "v"(s));
+    else if constexpr (P == 2)
+        asm(MB_FMAC_DPP4(MB_DPP_CTRL_2)
+            : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
+              "+v"(x[3].y)
+            : "v"(s));
+    else
+        asm(MB_FMAC_DPP4(MB_DPP_CTRL_8)
+            : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
+              "+v"(x[3].y)
+            : "v"(s));
+}
+
+// folded butterfly of a stage: x[k] <- x[k] + s x[k]' (x[k]' the partner lane's value)
+template <typename T, int L, int M, int Q>
+__device__ __forceinline__ void lane_fold_stage(cx<T>* x, T s) {
+    constexpr int P = LaneMap<Q>::phys(M);
+    int k = 0;
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (; k + 4 <= L; k += 4) fmac_xor4<P>(x + k, s);
+    }
+#pragma unroll
+    for (; k < L; ++k) {
+        const cx<T> u = lane_xor_cx<M, Q>(x[k]);
+        x[k] = mk<T>(fma(s, u.x, x[k].x), fma(s, u.y, x[k].y));
+    }
+}
+
 template <typename T, int L, int Q, int N, int SIGN, int QS = Q>
 __device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
     if constexpr (QS >= 2) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
         const T sg = h ? (T)-1 : (T)1;
+        constexpr bool fold = QS > 2 && lane_fold<T, m, Q>();
+        if constexpr (fold) {
+            lane_fold_stage<T, L, m, Q>(x, sg);
+        } else {
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
-            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
+            for (int k = 0; k < L; ++k) {
+                const cx<T> u = lane_xor_cx<m, Q>(x[k]);
+                x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
+            }
         }
         if constexpr (QS > 2) {
-            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+            cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+            if constexpr (fold) w = mk<T>(sg * w.x, sg * w.y);
 #pragma unroll
             for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
         }
@@ -113,23 +176,31 @@ __device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
 }
 
 // The mirrored decimation-in-time network: bit-reversed lanes in, natural order out.
+// ps: the sign a folded stage left on this lane's values, taken by the next stage's
+// twiddle (the last stage is never folded).
 template <typename T, int L, int Q, int N, int SIGN, int QS = 2>
-__device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw) {
+__device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw, T ps = (T)1) {
     if constexpr (QS <= Q) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
         const T sg = h ? (T)-1 : (T)1;
+        constexpr bool fold = QS < Q && lane_fold<T, m, Q>();
         if constexpr (QS > 2) {
-            const cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+            cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
+            w = mk<T>(ps * w.x, ps * w.y);
 #pragma unroll
             for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
         }
+        if constexpr (fold) {
+            lane_fold_stage<T, L, m, Q>(x, sg);
+        } else {
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const cx<T> u = lane_xor_cx<m, Q>(x[k]);
-            x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
+            for (int k = 0; k < L; ++k) {
+                const cx<T> u = lane_xor_cx<m, Q>(x[k]);
+                x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
+            }
         }
-        dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw);
+        dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw, fold ? sg : (T)1);
     }
 }
 
