@@ -18,15 +18,17 @@ __device__ __forceinline__ int bitrev_lane(int l) {
 }
 
 // Lane exchange v <- v of physical lane (p xor M) with DPP moves (VALU, no LDS
-// traffic): xor 1 and 2 are quad permutations, xor 8 the half-row rotation of a
-// 16-lane row, xor 4 two masked row shifts (lanes 0-3 and 8-11 of a row take
-// p + 4, lanes 4-7 and 12-15 take p - 4).
+// traffic): xor 1 and 2 are quad permutations, xor 7 the mirror of each 8-lane half
+// row, xor 8 the half-row rotation of a 16-lane row, xor 4 two masked row shifts
+// (lanes 0-3 and 8-11 of a row take p + 4, lanes 4-7 and 12-15 take p - 4).
 template <int M>
 __device__ __forceinline__ int lane_xor_i32(int v) {
     if constexpr (M == 1) {
         return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
     } else if constexpr (M == 2) {
         return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+    } else if constexpr (M == 7) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
     } else if constexpr (M == 4) {
         const int t = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);  // row_shl:4, banks 0, 2
         return __builtin_amdgcn_update_dpp(t, v, 0x114, 0xF, 0xA, false);         // row_shr:4, banks 1, 3
@@ -37,9 +39,10 @@ __device__ __forceinline__ int lane_xor_i32(int v) {
     }
 }
 
-// Lanes of a line of Q <= 16 points within a 16-lane row: logical lane bits 0, 1, 2,
-// 3 sit on physical bits 0, 1, 3, 2, so lines of up to 8 lanes exchange only through
-// single DPP moves (xor 1, 2, 8).
+// Lanes of a line of Q <= 16 points within a 16-lane row.  The map from logical lane
+// bits to physical positions is linear over GF(2) and sends logical xor 1, 2, 4, 8 to
+// physical xor 1, 2, 8 and (Q = 16) 7, so every exchange of every stage is a single
+// DPP move: p = b0 + 2 b1 + 8 b2 (Q <= 8) and p = b0 ^ 2 b1 ^ 8 b2 ^ 7 b3 (Q = 16).
 template <int Q>
 struct LaneMap {
     static_assert(Q == 2 || Q == 4 || Q == 8 || Q == 16, "lanes per line");
@@ -47,7 +50,10 @@ struct LaneMap {
     __device__ static int lane(int p) {
         if constexpr (Q <= 4) return p & (Q - 1);
         else if constexpr (Q == 8) return (p & 3) | (((p >> 3) & 1) << 2);
-        else return (p & 3) | (((p >> 3) & 1) << 2) | (((p >> 2) & 1) << 3);
+        else {
+            const int p2 = (p >> 2) & 1;
+            return ((p & 1) ^ p2) | ((((p >> 1) & 1) ^ p2) << 1) | (((p >> 3) & 1) << 2) | (p2 << 3);
+        }
     }
     // line of physical position p within its 16-lane row
     __device__ static int line(int p) {
@@ -56,7 +62,7 @@ struct LaneMap {
         else return 0;
     }
     // physical xor mask of logical mask m
-    static constexpr int phys(int m) { return m == 4 ? 8 : m == 8 ? 4 : m; }
+    static constexpr int phys(int m) { return m == 4 ? 8 : m == 8 ? 7 : m; }
 };
 
 template <int M>
@@ -98,16 +104,17 @@ __device__ __forceinline__ cx<T> tw_at(const cx<T>* tw, int e) {
 template <typename T, int M, int Q>
 constexpr bool lane_fold() { return sizeof(T) == 4 && LaneMap<Q>::phys(M) != 4; }
 
-// DPP control of the single-move exchanges (physical xor 1, 2, 8)
+// DPP control of the single-move exchanges (physical xor 1, 2, 7, 8)
 #define MB_DPP_CTRL_1 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
 #define MB_DPP_CTRL_2 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+#define MB_DPP_CTRL_7 "row_half_mirror row_mask:0xf bank_mask:0xf"
 #define MB_DPP_CTRL_8 "row_ror:8 row_mask:0xf bank_mask:0xf"
 #define MB_FMAC_DPP(i, C) "v_fmac_f32_dpp %" #i ", %" #i ", %8 " C "\n"
 #define MB_FMAC_DPP4(C)                                                                                  \
     "s_nop 1\n" MB_FMAC_DPP(0, C) MB_FMAC_DPP(1, C) MB_FMAC_DPP(2, C) MB_FMAC_DPP(3, C) MB_FMAC_DPP(4, C) \
         MB_FMAC_DPP(5, C) MB_FMAC_DPP(6, C) MB_FMAC_DPP(7, C) "s_nop 1\n"
 
-// x[k] += s * (x[k] of physical lane p xor P), both components of 4 points, as
+// x[k] += s * (x[k] of physical lane p xor P, P = 1, 2, 7, 8), both components of 4 points, as
 // v_fmac_f32 with its DPP source operand (one instruction per component instead of a
 // DPP move and an FMA: the compiler does not fold DPP moves into FMAC).  The leading
 // s_nop covers the wait states a DPP read needs after the VALU writes of its operand
@@ -115,7 +122,7 @@ constexpr bool lane_fold() { return sizeof(T) == 4 && LaneMap<Q>::phys(M) != 4; 
 // the trailing one those of any DPP read of the results that follows.
 template <int P>
 __device__ __forceinline__ void fmac_xor4(cx<float>* x, float s) {
-    static_assert(P == 1 || P == 2 || P == 8, "single-move exchange");
+    static_assert(P == 1 || P == 2 || P == 7 || P == 8, "single-move exchange");
     if constexpr (P == 1)
         asm(MB_FMAC_DPP4(MB_DPP_CTRL_1)
             : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
@@ -123,6 +130,11 @@ __device__ __forceinline__ void fmac_xor4(cx<float>* x, float s) {
             : "v"(s));
     else if constexpr (P == 2)
         asm(MB_FMAC_DPP4(MB_DPP_CTRL_2)
+            : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
+              "+v"(x[3].y)
+            : "v"(s));
+    else if constexpr (P == 7)
+        asm(MB_FMAC_DPP4(MB_DPP_CTRL_7)
             : "+v"(x[0].x), "+v"(x[0].y), "+v"(x[1].x), "+v"(x[1].y), "+v"(x[2].x), "+v"(x[2].y), "+v"(x[3].x),
               "+v"(x[3].y)
             : "v"(s));
