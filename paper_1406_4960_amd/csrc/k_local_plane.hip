@@ -159,7 +159,9 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
             line_fft<T, L2, +1>(x);
 #pragma unroll
             for (int k = 1; k < L2; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw2, l * k));
-            dif_lanes<T, L2, Q2, N2, +1>(x, l, tw2);
+            // the last stage's sign (-1 on lanes with bit 0 set) stays on the values: it
+            // marks the columns j2 >= N2 / 2, whose pass takes it into the potential
+            dif_lanes<T, L2, Q2, N2, +1, true>(x, l, tw2);
             cx<T>* dst = grid + (size_t)j1 * P + colpos<N2, Q2, PADB>(L2 * bitrev_lane<Q2>(l));
 #pragma unroll
             for (int k = 0; k < L2; ++k) dst[k] = x[k];
@@ -187,14 +189,19 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
             line_fft<T, L1, +1>(x);
 #pragma unroll
             for (int k = 1; k < L1; ++k) x[k] = cmul(x[k], tw_at<T, +1>(tw1, l * k));
-            dif_lanes<T, L1, Q1, N1, +1>(x, l, tw1);
+            // signs left on the values by folded last stages (+-1, products exact): the
+            // row pass's (columns j2 >= N2 / 2) and this network's, both taken by V
+            const T sgc = (lane_fold<T, 1, Q2>() && j2 >= N2 / 2) ? (T)-1 : (T)1;
+            const T sv = sgc * dif_lanes<T, L1, Q1, N1, +1, true>(x, l, tw1);
             const T* vc = a.Vt + ((size_t)q * N2 + j2) * N1 + L1 * bitrev_lane<Q1>(l);
 #pragma unroll
             for (int k = 0; k < L1; ++k) {
-                const T v = vc[k];
+                const T v = sv * vc[k];
                 x[k] = mk<T>(x[k].x * v, x[k].y * v);
             }
-            dit_lanes<T, L1, Q1, N1, -1>(x, l, tw1);
+            // the forward network's last sign (lane bit 3, i.e. the rows j1 with bit 3 of
+            // j1 mod Q1 set) goes on to the row pass, which takes it into its output scale
+            dit_lanes<T, L1, Q1, N1, -1, true>(x, l, tw1);
 #pragma unroll
             for (int k = 1; k < L1; ++k) x[k] = cmul(x[k], tw_at<T, -1>(tw1, l * k));
             line_fft<T, L1, -1>(x);
@@ -216,15 +223,18 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
             cx<T> x[L2];
 #pragma unroll
             for (int k = 0; k < L2; ++k) x[k] = src[k];
-            dit_lanes<T, L2, Q2, N2, -1>(x, l, tw2);
+            const T sr = dit_lanes<T, L2, Q2, N2, -1, true>(x, l, tw2);
 #pragma unroll
             for (int k = 1; k < L2; ++k) x[k] = cmul(x[k], tw_at<T, -1>(tw2, l * k));
             line_fft<T, L2, -1>(x);
+            // this network's last sign and the column pass's sign of row j1
+            const T sj = (lane_fold<T, Q1 / 2, Q1>() && ((j1 % Q1) & (Q1 >> 1))) ? (T)-1 : (T)1;
+            const T sc = a.inv_n * (sr * sj);
             cx<T>* uq = ub + (size_t)q * a.ld;
 #pragma unroll
             for (int m = 0; m < L2; ++m) {
                 const int g = gr[l + Q2 * m];
-                if (g >= 0) uq[g] = mk<T>(x[m].x * a.inv_n, x[m].y * a.inv_n);
+                if (g >= 0) uq[g] = mk<T>(x[m].x * sc, x[m].y * sc);
             }
         }
     }

@@ -161,13 +161,16 @@ __device__ __forceinline__ void lane_fold_stage(cx<T>* x, T s) {
     }
 }
 
-template <typename T, int L, int Q, int N, int SIGN, int QS = Q>
-__device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
+// FL (fold the last stage as well): the last stage's sign stays on the lane's values
+// too, and the network returns it (the caller takes it into its next product);
+// otherwise the network returns 1.
+template <typename T, int L, int Q, int N, int SIGN, bool FL = false, int QS = Q>
+__device__ __forceinline__ T dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
     if constexpr (QS >= 2) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
         const T sg = h ? (T)-1 : (T)1;
-        constexpr bool fold = QS > 2 && lane_fold<T, m, Q>();
+        constexpr bool fold = (QS > 2 || FL) && lane_fold<T, m, Q>();
         if constexpr (fold) {
             lane_fold_stage<T, L, m, Q>(x, sg);
         } else {
@@ -182,21 +185,24 @@ __device__ __forceinline__ void dif_lanes(cx<T>* x, int l, const cx<T>* tw) {
             if constexpr (fold) w = mk<T>(sg * w.x, sg * w.y);
 #pragma unroll
             for (int k = 0; k < L; ++k) x[k] = cmul(x[k], w);
+            return dif_lanes<T, L, Q, N, SIGN, FL, QS / 2>(x, l, tw);
+        } else {
+            return fold ? sg : (T)1;
         }
-        dif_lanes<T, L, Q, N, SIGN, QS / 2>(x, l, tw);
     }
+    return (T)1;
 }
 
 // The mirrored decimation-in-time network: bit-reversed lanes in, natural order out.
 // ps: the sign a folded stage left on this lane's values, taken by the next stage's
-// twiddle (the last stage is never folded).
-template <typename T, int L, int Q, int N, int SIGN, int QS = 2>
-__device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw, T ps = (T)1) {
+// twiddle; FL as for dif_lanes.
+template <typename T, int L, int Q, int N, int SIGN, bool FL = false, int QS = 2>
+__device__ __forceinline__ T dit_lanes(cx<T>* x, int l, const cx<T>* tw, T ps = (T)1) {
     if constexpr (QS <= Q) {
         constexpr int m = QS >> 1;
         const bool h = (l & m) != 0;
         const T sg = h ? (T)-1 : (T)1;
-        constexpr bool fold = QS < Q && lane_fold<T, m, Q>();
+        constexpr bool fold = (QS < Q || FL) && lane_fold<T, m, Q>();
         if constexpr (QS > 2) {
             cx<T> w = h ? tw_at<T, SIGN>(tw, (l & (m - 1)) * (N / QS)) : mk<T>(1, 0);
             w = mk<T>(ps * w.x, ps * w.y);
@@ -212,8 +218,9 @@ __device__ __forceinline__ void dit_lanes(cx<T>* x, int l, const cx<T>* tw, T ps
                 x[k] = mk<T>(fma(sg, x[k].x, u.x), fma(sg, x[k].y, u.y));
             }
         }
-        dit_lanes<T, L, Q, N, SIGN, QS * 2>(x, l, tw, fold ? sg : (T)1);
+        return dit_lanes<T, L, Q, N, SIGN, FL, QS * 2>(x, l, tw, fold ? sg : (T)1);
     }
+    return ps;
 }
 
 
