@@ -348,8 +348,11 @@ bool local_uses_planes(const Problem* p, int ik, int lp) {
     if (sel && (std::string(sel) == "generic" || std::string(sel) == "split")) return false;
     const KPoint::Tune& tn = p->kp[ik].tune[lp];
     if (tn.set) return tn.kind == 3;
-    // untuned: the plane kernel on the 128 x 64 grid; elsewhere when mb_autotune picks it
-    return p->N1 == 128 && p->N2 == 64;
+    // untuned: the plane kernel on the 128 x 64 grid, and in FP64 on the 36 x 36 grid
+    // (graphene-like slab, 32 bands: H 0.23 against 0.26 ms with the line kernel; in FP32
+    // the line kernel stays ahead, 0.072 against 0.080 ms local); elsewhere when
+    // mb_autotune picks it
+    return (p->N1 == 128 && p->N2 == 64) || (p->N1 == 36 && p->N2 == 36 && lp == 0);
 }
 
 mb_status launch_vgrid(Problem* p, hipStream_t s) {

@@ -282,10 +282,11 @@ mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, 
     // column, 8 per 64-point row; fewer registers), variant 1 holds 16 (8 and 4 lanes;
     // one lane-exchange stage less per line).  mb_autotune may pick either.
     constexpr int NT = 512;
-    // untuned: 16 points per lane in FP64 (30 ms against 50 ms per 320 bands of the
-    // surface slab), 8 in FP32 (16 ms against 19 ms)
+    // untuned: on the 128 x 64 grid 16 points per lane in FP64 (26 ms against 44 ms per 320
+    // bands of the surface slab), 8 in FP32 (13 ms against 18 ms); on the 36 x 36 grid 9
+    // points per lane (FP64: 0.15 against 0.28 ms per 32 bands of the graphene-like slab)
     const KPoint::Tune& tn = p->kp[ik].tune[sizeof(T) == 8 ? 0 : (sizeof(TI) == 8 ? 2 : 1)];
-    const int var = (tn.set && tn.kind == 3) ? tn.plane_var : (sizeof(T) == 8 ? 1 : 0);
+    const int var = (tn.set && tn.kind == 3) ? tn.plane_var : (sizeof(T) == 8 && p->N1 == 128 ? 1 : 0);
     static_assert(64 * 16 % 16 == 0, "column tasks fill whole 16-lane rows");
     if (p->N1 == 128 && p->N2 == 64) {
         if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1>(p, ik, c, u, nbands, ld, s);
