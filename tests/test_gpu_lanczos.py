@@ -124,6 +124,42 @@ def test_lanczos_graphene_full(ik, prec, tol):
     p.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-6)])
+def test_lanczos_partly_converged_start_locks_blocks(prec, tol):
+    # half of the start vectors are converged eigenvectors and half random: the first
+    # block cycles run with the converged blocks sitting out (soft locking, a partial
+    # set of active blocks and its own Rayleigh-Ritz tables), and the solve must still
+    # reach the stored oracle eigenvalues of all roots
+    g = _golden("graphene")
+    ref = np.array(g["kpoints"]["0"]["eps"])
+    d = workloads.graphene()
+    nev = d["nbands"]
+    print(f"[case] lanczos graphene k0 partly converged start {prec}", flush=True)
+    p = mbks.Problem(d, device=0)
+    eig, x, info, st = p.lanczos_lowest(0, nev, "fp64")
+    assert st == 0
+    dm = p.dims(0)
+    x0 = x.clone()
+    gen = torch.Generator().manual_seed(11)
+    half = nev // 2
+    rnd = torch.randn((nev - half, dm["nb"], dm["ng"]), generator=gen, dtype=torch.float64) + 1j * torch.randn(
+        (nev - half, dm["nb"], dm["ng"]), generator=gen, dtype=torch.float64)
+    x0[half:] = 0
+    x0[half:, :, : dm["ng"]] = rnd.to(DEV)
+    eig2, x2, info2, st2 = p.lanczos_lowest(0, nev, prec, x0=x0)
+    print(info2, np.max(np.abs(eig2 - ref)), flush=True)
+    assert st2 == 0 and info2["iters"] >= 2
+    # without locking every cycle applies H to 4 Krylov vectors of each of the M trial
+    # vectors' blocks and 2 global ones (M = nev + 8 buffer vectors, plus M at the start
+    # and M when a mixed solve switches to FP64): locked blocks must have saved some
+    M = nev + min(16, max(4, nev // 4))
+    assert info2["h_applies"] < 2 * M + info2["iters"] * (4 * M + 2) - 32
+    assert np.max(np.abs(eig2 - ref)) < tol
+    orth, res = _check_vectors(p, 0, x2, eig2, nev)
+    assert orth < 1e-10 and np.max(res) < 1e-6
+    p.close()
+
+
 @pytest.mark.parametrize("extra", [0, 3, 8])
 def test_lanczos_buffer_vectors(extra):
     # buffer vectors above the wanted roots change the iteration, not the result
