@@ -64,6 +64,10 @@ void free_all(Problem* p) {
                       kp.ws_small.ptr};
         for (void* q : kq)
             if (q) (void)hipFree(q);
+        if (kp.aux) (void)hipStreamSynchronize(kp.aux);
+        if (kp.ev_fork) (void)hipEventDestroy(kp.ev_fork);
+        if (kp.ev_join) (void)hipEventDestroy(kp.ev_join);
+        if (kp.aux) (void)hipStreamDestroy(kp.aux);
     }
 }
 
@@ -260,7 +264,21 @@ mb_status upload(Problem* p) {
     }
     MB_TRY(launch_vgrid(p, 0));
     MB_TRY(refresh_vt(p, 0));
+    // the projections' stream and events of each k-point (default priority)
+    if (plane_kernel_grid(p) && p->np > 0) {
+        for (auto& kp : p->kp) {
+            if (!kp.aux) MB_HIP_TRY(hipStreamCreateWithFlags(&kp.aux, hipStreamNonBlocking));
+            if (!kp.ev_fork) MB_HIP_TRY(hipEventCreateWithFlags(&kp.ev_fork, hipEventDisableTiming));
+            if (!kp.ev_join) MB_HIP_TRY(hipEventCreateWithFlags(&kp.ev_join, hipEventDisableTiming));
+        }
+    }
     return MB_OK;
+}
+
+// MBKS_NL_OVERLAP=0 keeps the projections on the caller's stream (read per call)
+static bool overlap_enabled() {
+    const char* e = getenv("MBKS_NL_OVERLAP");
+    return !(e && e[0] == '0');
 }
 
 // y = H c (sy = S c if non-null).  prec: 0 FP64, 1 FP32 (c64), 2 c128 vectors with FP32 local/nonlocal.
@@ -291,12 +309,30 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         }
         if (sy && p->uspp)
             projq = (char*)proj + (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
-        MB_TRY(project(p, ik, c, proj, nbands, ld, prec, s, ext ? ext->nlpart : nullptr, PROJ_E, projq));
     }
-    if (local_uses_planes(p, ik, lp)) {
+    const bool planes = local_uses_planes(p, ik, lp);
+    if (planes) {
+        // the projections (matrix cores, memory) run beside the plane kernel (bound by
+        // vector instruction issue) on the k-point's own stream: forked after everything
+        // the caller's stream has queued (c is ready, the previous call's combine pass has
+        // read the projection buffers), joined before the combine pass reads them
+        const bool overlap = p->np > 0 && kp.aux && overlap_enabled();
+        if (p->np > 0) {
+            hipStream_t sp = s;
+            if (overlap) {
+                MB_HIP_TRY(hipEventRecord(kp.ev_fork, s));
+                MB_HIP_TRY(hipStreamWaitEvent(kp.aux, kp.ev_fork, 0));
+                sp = kp.aux;
+            }
+            MB_TRY(project(p, ik, c, proj, nbands, ld, prec, sp, ext ? ext->nlpart : nullptr, PROJ_E, projq));
+            if (overlap) MB_HIP_TRY(hipEventRecord(kp.ev_join, kp.aux));
+        }
         MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s));
+        if (overlap) MB_HIP_TRY(hipStreamWaitEvent(s, kp.ev_join, 0));
         MB_TRY(launch_zcombine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, projq));
     } else {
+        if (p->np > 0)
+            MB_TRY(project(p, ik, c, proj, nbands, ld, prec, s, ext ? ext->nlpart : nullptr, PROJ_E, projq));
         MB_TRY(launch_local(p, ik, c, part, nbands, ld, lp, s));
         MB_TRY(launch_combine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, false, projq));
     }

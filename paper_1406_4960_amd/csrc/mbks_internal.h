@@ -95,6 +95,11 @@ struct KPoint {
     Workspace ws_aux;     // s_solve with augmentation charges in place: copy of r
     Workspace ws_lz;      // eigensolver vectors
     Workspace ws_small;   // eigensolver small matrices
+    // H applications on the plane-kernel grids run the projections on this stream,
+    // forked from and joined to the caller's stream by the two events, so that they
+    // overlap the plane kernel (created with the problem; null elsewhere)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // kernel choices measured by mb_autotune, per arithmetic class of the local part
     // (0: FP64, 1: FP32 with complex64 vectors, 2: FP32 with complex128 vectors)
     struct Tune {
