@@ -343,6 +343,25 @@ def test_zcombine_bands_per_wave_variants_match(prec, monkeypatch):
     p.close()
 
 
+@pytest.mark.parametrize("cfg,prec", [("surface", "fp32"), ("surface", "fp64"), ("graphene", "fp64")])
+def test_projections_beside_the_plane_kernel_give_the_same_h(cfg, prec, monkeypatch):
+    # the projections on the k-point's own stream (forked and joined by events) against
+    # the same projections on the caller's stream: identical kernels and inputs, so the
+    # outputs agree bit for bit, over repeated calls that reuse the buffers
+    d = getattr(workloads, cfg)()
+    print(f"[case] projection stream overlap {cfg} {prec}", flush=True)
+    p, dm, _ = _setup(d, 0)
+    x = random_lib_block(45, 13, dm["nb"], dm["ng"], dm["ld"])
+    monkeypatch.setenv("MBKS_NL_OVERLAP", "0")
+    ref = _run(p, "hpsi", 0, x, prec)
+    monkeypatch.setenv("MBKS_NL_OVERLAP", "1")
+    for _ in range(3):
+        got = _run(p, "hpsi", 0, x, prec)
+        assert np.array_equal(got, ref)
+    monkeypatch.delenv("MBKS_NL_OVERLAP")
+    p.close()
+
+
 @pytest.mark.parametrize("cfg,prec,nbands,kernel", [("graphene_2x2", "fp64", 5, "default"),
                                                     ("graphene_2x2", "fp32", 5, "default"),
                                                     ("surface", "fp64", 2, "default"), ("surface", "fp32", 3, "default"),
