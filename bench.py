@@ -26,6 +26,8 @@ Printed JSON line:
                    eigenpairs mixed vs FP64
   roofline         the local-potential plane kernel (largest share of a step), from HIP
                    events around its launches on the library's stream in the timed steps
+                   (the projections run beside it there); roofline.standalone: the same
+                   kernel in two more steps with the projections on the caller's stream
   cpu_baseline     the CPU FP64 oracle's matrix-free H (FFT local part) on a bounded
                    sample of the same workload
 """
@@ -660,6 +662,29 @@ def main(argv=None):
                 "hbm_gbs_algorithmic": round(alg_bytes / (avg_ms * 1e-3) / 1e9, 1)}
     if tr:
         roofline["traffic_over_algorithmic"] = round(tr["bytes_per_launch"] / alg_bytes, 3)
+    # In the timed steps the projections run beside the plane kernel on the k-point's own
+    # stream, so the kernel's launch time above includes sharing the GPU with them.  Its
+    # standalone rate, from two more steps with the projections on the caller's stream:
+    prev = os.environ.get("MBKS_NL_OVERLAP")
+    os.environ["MBKS_NL_OVERLAP"] = "0"
+    mbks.timer_enable(True)
+    for _ in range(2):
+        step(head)
+    torch.cuda.synchronize()
+    solo = mbks.timer_read()
+    mbks.timer_enable(False)
+    if prev is None:
+        del os.environ["MBKS_NL_OVERLAP"]
+    else:
+        os.environ["MBKS_NL_OVERLAP"] = prev
+    sms, scount, _ = solo[lname]
+    solo_ms = sms / scount
+    solo_ach = flops_b * per_launch / (solo_ms * 1e-3) / 1e12
+    roofline["standalone"] = {"avg_launch_ms": round(solo_ms, 4), "launches": scount,
+                              "achieved": round(solo_ach, 3), "frac": round(solo_ach / peak, 4),
+                              "note": "same kernel with the projections on the caller's stream "
+                                      "(not beside it), two extra steps"}
+    log("plane kernel standalone", round(solo_ms, 3), "ms", round(solo_ach, 2), "TFLOP/s")
     del xs, ys
     torch.cuda.empty_cache()
     p.close()

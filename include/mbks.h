@@ -33,6 +33,10 @@
  * buffers per k-point.  Calls on different k-points of one handle may run
  * concurrently (from different host threads, on different streams); calls on
  * the same k-point must not overlap (issue them on one stream from one thread).
+ * On the grids with a plane kernel, H applications with projectors also use a
+ * stream of the k-point's own (created with the handle, default priority): it is
+ * forked from `stream` and joined back to it by events inside the call, so the
+ * call's work is complete, and capturable into a graph, on `stream` alone.
  *
  * Errors: every entry point returns an mb_status; arguments are validated
  * before anything is enqueued.  mb_last_error() returns a thread-local message

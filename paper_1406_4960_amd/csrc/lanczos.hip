@@ -79,7 +79,6 @@ struct Solver {
     // below which a block sits out, per-cycle tables of a partial block set
     int na = 0;
     double lock_tol = 0.0;
-    int64_t locked_blocks = 0;
     void** tpart;
     int32_t* amap;
     std::vector<void*> h_ptab;
@@ -204,7 +203,6 @@ struct Solver {
             th.push_back(h_theta[best]);
         }
         na = (int)act.size();
-        locked_blocks += nbl - na;
         if (na == 0) return MB_OK;
         MB_HIP_TRY(hipMemcpyAsync(sel, seeds.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, s));
         MB_HIP_TRY(hipMemcpyAsync(theta_s, th.data(), na * sizeof(double), hipMemcpyHostToDevice, s));
