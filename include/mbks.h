@@ -214,6 +214,19 @@ mb_status mb_problem_set_potential(mb_problem* p, const double* v_host);
 mb_status hpsi_apply(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                      mb_precision prec, void* stream);
 
+/* y = H c for real wavefunctions at the Gamma point (k = 0): every band must satisfy
+ * c(-G) = conj c(G), i.e. psi(rho, z) real, the form the eigenvectors take there when
+ * the potential and projectors are real (the plane-wave half of the basis of Sec. II.A
+ * at k = 0).  The local part can then transform two bands per complex FFT
+ * (psi_a + i psi_b; the two results separate by the G -> -G symmetry), halving the
+ * transform work of hpsi_apply.  It does so where that is faster (the 128 x 64 grid with
+ * FP32 local arithmetic); elsewhere the bands are transformed one by one.  Vectors
+ * keep the full-sphere layout of hpsi_apply; for bands that are not real in space the
+ * result is not H c.  MB_ERR_INVALID_ARG if k-point ik is not Gamma or its G set is
+ * not closed under G -> -G.  Arguments, layout and errors otherwise as hpsi_apply. */
+mb_status hpsi_apply_gamma(mb_problem* p, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                           mb_precision prec, void* stream);
+
 /* hpsi_apply for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same operator
  * and kernels as hpsi_apply, with every work buffer (local partial rows, projections,

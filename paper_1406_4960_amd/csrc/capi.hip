@@ -172,9 +172,27 @@ mb_status ensure_hws(KPoint& kp, Workspace& w, size_t bytes) {
     return ensure_ws(w, bytes);
 }
 
-size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec) {
+// Real-wavefunction pairing (two bands per transform, in the plane kernel) where it was
+// measured faster: the 128 x 64 grid with FP32 local arithmetic (surface slab, 320 bands
+// at Gamma: H 17.5 against 20.8 ms).  In FP64 that plane kernel holds one workgroup per
+// CU, and the gather pass with its two barriers costs more than the halved transforms
+// save (H 47.2 against 37.7 ms); on the 36 x 36 grid nothing is gained (0.121 against
+// 0.118 ms FP32, 0.220 against 0.196 ms FP64).  MBKS_GAMMA_PAIR=1 pairs on every
+// plane-kernel grid, =0 never.
+bool gamma_pairs(const Problem* p, int lp) {
+    if (!plane_kernel_grid(p)) return false;
+    const char* e = getenv("MBKS_GAMMA_PAIR");
+    if (e && e[0] == '1') return true;
+    if (e && e[0] == '0') return false;
+    return p->N1 == 128 && p->N2 == 64 && lp != 0;
+}
+
+size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec, bool gamma) {
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;
-    const size_t rows = local_uses_planes(p, ik, lp) ? (size_t)p->nzq : (size_t)p->nint * 4;
+    // the plane kernel writes a row per Gauss plane, the others kappa rows per interval;
+    // real-wavefunction pairing takes the plane kernel
+    const bool planes = (gamma && gamma_pairs(p, lp)) || local_uses_planes(p, ik, lp);
+    const size_t rows = planes ? (size_t)p->nzq : (size_t)p->nint * 4;
     return (size_t)nbands * rows * ld * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
 }
 
@@ -282,8 +300,24 @@ static bool overlap_enabled() {
 }
 
 // y = H c (sy = S c if non-null).  prec: 0 FP64, 1 FP32 (c64), 2 c128 vectors with FP32 local/nonlocal.
+bool gamma_point(Problem* p, int ik) {
+    KPoint& kp = p->kp[ik];
+    if (kp.gamma_sym < 0) {
+        bool ok = p->kfrac[2 * ik] == 0.0 && p->kfrac[2 * ik + 1] == 0.0;
+        if (ok) {
+            std::vector<std::pair<int, int>> ms;
+            for (int g = 0; g < kp.ng; ++g) ms.emplace_back(kp.m[2 * g], kp.m[2 * g + 1]);
+            std::sort(ms.begin(), ms.end());
+            for (int g = 0; g < kp.ng && ok; ++g)
+                ok = std::binary_search(ms.begin(), ms.end(), std::make_pair(-kp.m[2 * g], -kp.m[2 * g + 1]));
+        }
+        kp.gamma_sym = ok ? 1 : 0;
+    }
+    return kp.gamma_sym == 1;
+}
+
 mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec, hipStream_t s,
-                  const HWork* ext) {
+                  const HWork* ext, bool gamma) {
     if (nbands == 0) return MB_OK;
     const int lp = prec == 3 ? 1 : prec == 4 ? 2 : prec;  // local / combine precision
     if (p->wire) {
@@ -293,7 +327,7 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
     KPoint& kp = p->kp[ik];
     void* part = ext ? ext->part : nullptr;
     if (!ext) {
-        MB_TRY(ensure_hws(kp, kp.ws_part, hwork_part_bytes(p, ik, nbands, ld, prec)));
+        MB_TRY(ensure_hws(kp, kp.ws_part, hwork_part_bytes(p, ik, nbands, ld, prec, gamma)));
         part = kp.ws_part.ptr;
     }
     void* proj = nullptr;
@@ -310,7 +344,10 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
         if (sy && p->uspp)
             projq = (char*)proj + (size_t)nbands * p->np * (lp == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
     }
-    const bool planes = local_uses_planes(p, ik, lp);
+    // real-wavefunction pairing lives in the plane kernel (the partial-row buffer above
+    // is sized by the same choice); elsewhere the bands go one by one
+    const bool pair = gamma && gamma_pairs(p, lp);
+    const bool planes = pair || local_uses_planes(p, ik, lp);
     if (planes) {
         // the projections (matrix cores, memory) run beside the plane kernel (bound by
         // vector instruction issue) on the k-point's own stream: forked after everything
@@ -327,7 +364,7 @@ mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nban
             MB_TRY(project(p, ik, c, proj, nbands, ld, prec, sp, ext ? ext->nlpart : nullptr, PROJ_E, projq));
             if (overlap) MB_HIP_TRY(hipEventRecord(kp.ev_join, kp.aux));
         }
-        MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s));
+        MB_TRY(launch_local_plane(p, ik, c, part, nbands, ld, lp, s, pair));
         if (overlap) MB_HIP_TRY(hipStreamWaitEvent(s, kp.ev_join, 0));
         MB_TRY(launch_zcombine(p, ik, c, part, proj, y, sy, nbands, ld, lp, s, projq));
     } else {
@@ -619,6 +656,23 @@ mb_status hpsi_apply(mb_problem* h, int ik, const void* c, void* y, int64_t nban
                        prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream);
 }
 
+
+mb_status hpsi_apply_gamma(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
+                           mb_precision prec, void* stream) {
+    mb_status st = mb::check_vec_args(h, ik, c, y, nbands, ld, "hpsi_apply_gamma");
+    if (st != MB_OK) return st;
+    if (mb::refuse_wire(h, "hpsi_apply_gamma") != MB_OK) return MB_ERR_INVALID_ARG;
+    if (prec != MB_FP64 && prec != MB_FP32 && prec != MB_BF16X3)
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_gamma: unknown precision");
+    if (!mb::gamma_point(&h->p, ik))
+        return set_error(MB_ERR_INVALID_ARG,
+                         "hpsi_apply_gamma: k-point is not Gamma or its G set is not closed under G -> -G");
+    size_t bytes = (size_t)nbands * h->p.nb * ld * (prec == MB_FP64 ? 16 : 8);
+    if (nbands > 0 && mb::ranges_overlap(c, bytes, y, bytes))
+        return set_error(MB_ERR_INVALID_ARG, "hpsi_apply_gamma: c and y overlap");
+    return mb::apply_h(&h->p, ik, c, y, nullptr, (int)nbands, (int)ld,
+                       prec == MB_FP64 ? 0 : prec == MB_FP32 ? 1 : 3, (hipStream_t)stream, nullptr, true);
+}
 
 mb_status hpsi_apply_noalloc(mb_problem* h, int ik, const void* c, void* y, int64_t nbands, int64_t ld,
                              mb_precision prec, void* stream) {

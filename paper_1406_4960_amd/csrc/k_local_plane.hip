@@ -48,6 +48,7 @@ struct PlaneArgs {
     const cx<T>* tw1;      // [N1]: exp(+2 pi i k / N1)
     const cx<T>* tw2;      // [N2]
     int nbands, ld, nint, nq, nb, nrows, nzq;
+    int nreal;             // real-wavefunction pairing: bands (nbands counts the pairs)
     T inv_n;
 };
 
@@ -73,7 +74,13 @@ constexpr size_t plane_lds() {
 
 // One workgroup per (band, chunk of PLANE_NI knot intervals): their Gauss planes one
 // after another.
-template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+// GAM: real wavefunctions at the Gamma point (c(-G) = conj c(G), so psi(rho, z) is real):
+// one complex transform serves two bands.  Work band b is the pair (2b, 2b + 1); the
+// row pass evaluates psi_2b + i psi_2b+1, the real potential keeps the two parts apart
+// in real space, and after the forward transform u = A + i B with A(-G) = conj A(G),
+// B(-G) = conj B(G), so A(G) = (u(G) + conj u(-G)) / 2 and B(G) = (u(G) - conj u(-G)) / 2i.
+// The forward row pass leaves the plane in LDS, and a gather pass reads G and -G.
+template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB, bool GAM>
 __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     constexpr int L1 = N1 / Q1, L2 = N2 / Q2;
     constexpr int P = plane_pitch<N2, Q2, PADB>();
@@ -116,8 +123,11 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
     }
     __syncthreads();
 
-    const cx<TI>* cb = a.c + (size_t)b * a.nb * a.ld;
-    cx<T>* ub = a.u + (size_t)b * a.nzq * a.ld;
+    const int b0 = GAM ? 2 * b : b;
+    const bool hasb = GAM && b0 + 1 < a.nreal;  // second band of the pair
+    const cx<TI>* cb = a.c + (size_t)b0 * a.nb * a.ld;
+    const cx<TI>* cb2 = hasb ? cb + (size_t)a.nb * a.ld : cb;  // weight 0 if absent
+    cx<T>* ub = a.u + (size_t)b0 * a.nzq * a.ld;
     // row tasks in whole 16-lane rows (a line's lanes are active or idle together)
     const int nrt = (a.nrows * Q2 + 15) / 16 * 16;
 
@@ -154,6 +164,12 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
                     const T w = gi[m] >= 0 ? bv[t] : (T)0;
                     x[m].x = fma(w, (T)v.x, x[m].x);
                     x[m].y = fma(w, (T)v.y, x[m].y);
+                    if constexpr (GAM) {  // + i c of the pair's second band
+                        const cx<TI> v2 = cb2[(size_t)row * a.ld + (gi[m] >= 0 ? gi[m] : 0)];
+                        const T w2 = hasb ? w : (T)0;
+                        x[m].x = fma(-w2, (T)v2.y, x[m].x);
+                        x[m].y = fma(w2, (T)v2.x, x[m].y);
+                    }
                 }
             }
             line_fft<T, L2, +1>(x);
@@ -229,18 +245,45 @@ __global__ __launch_bounds__(NT) void k_local_plane(PlaneArgs<TI, T> a) {
             line_fft<T, L2, -1>(x);
             // this network's last sign and the column pass's sign of row j1
             const T sj = (lane_fold<T, Q1 / 2, Q1>() && ((j1 % Q1) & (Q1 >> 1))) ? (T)-1 : (T)1;
-            const T sc = a.inv_n * (sr * sj);
-            cx<T>* uq = ub + (size_t)q * a.ld;
+            const T sc = a.inv_n * (sr * sj) * (GAM ? (T)0.5 : (T)1);
+            if constexpr (GAM) {
+                // the transformed row back to LDS in natural column order (this lane read
+                // its own block above; the lanes of a row share one wavefront)
+                cx<T>* dr = grid + (size_t)j1 * P;
 #pragma unroll
-            for (int m = 0; m < L2; ++m) {
-                const int g = gr[l + Q2 * m];
-                if (g >= 0) uq[g] = mk<T>(x[m].x * sc, x[m].y * sc);
+                for (int m = 0; m < L2; ++m)
+                    dr[colpos<N2, Q2, PADB>(l + Q2 * m)] = mk<T>(x[m].x * sc, x[m].y * sc);
+            } else {
+                cx<T>* uq = ub + (size_t)q * a.ld;
+#pragma unroll
+                for (int m = 0; m < L2; ++m) {
+                    const int g = gr[l + Q2 * m];
+                    if (g >= 0) uq[g] = mk<T>(x[m].x * sc, x[m].y * sc);
+                }
             }
+        }
+        if constexpr (GAM) {
+            // gather: the sphere is symmetric at Gamma, so -G sits on a sphere row too
+            __syncthreads();
+            cx<T>* uq = ub + (size_t)q * a.ld;
+            cx<T>* uq2 = uq + (size_t)a.nzq * a.ld;
+            for (int e = tid; e < a.nrows * N2; e += NT) {
+                const int rc = e / N2, j2 = e - rc * N2;
+                const int g = a.gtab[e];
+                if (g < 0) continue;
+                const int j1 = a.rows[rc];
+                const int n1 = j1 == 0 ? 0 : N1 - j1, n2 = j2 == 0 ? 0 : N2 - j2;
+                const cx<T> u = grid[(size_t)j1 * P + colpos<N2, Q2, PADB>(j2)];
+                const cx<T> um = grid[(size_t)n1 * P + colpos<N2, Q2, PADB>(n2)];
+                uq[g] = mk<T>(u.x + um.x, u.y - um.y);
+                if (hasb) uq2[g] = mk<T>(u.y + um.y, um.x - u.x);
+            }
+            __syncthreads();
         }
     }
 }
 
-template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB>
+template <typename TI, typename T, int N1, int N2, int Q1, int Q2, int NT, int PADB, bool GAM>
 mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, int ld, hipStream_t s) {
     const KPoint& kp = p->kp[ik];
     if (!kp.d_gtab || !p->d_Vt) return set_error(MB_ERR_INVALID_ARG, "plane kernel tables missing");
@@ -255,7 +298,8 @@ mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, i
     a.rows = kp.d_rows;
     a.tw1 = (const cx<T>*)(dbl ? p->d_tw1 : p->d_tw1f);
     a.tw2 = (const cx<T>*)(dbl ? p->d_tw2 : p->d_tw2f);
-    a.nbands = nbands;
+    a.nbands = GAM ? (nbands + 1) / 2 : nbands;
+    a.nreal = nbands;
     a.ld = ld;
     a.nint = p->nint;
     a.nq = p->nq;
@@ -265,17 +309,17 @@ mb_status plane_launch(Problem* p, int ik, const void* c, void* u, int nbands, i
     a.inv_n = (T)(1.0 / ((double)N1 * N2));
     constexpr size_t lds = plane_lds<T, N1, N2, Q2, PADB>();
     static_assert(lds <= 163840, "plane does not fit in LDS");
-    auto kern = k_local_plane<TI, T, N1, N2, Q1, Q2, NT, PADB>;
+    auto kern = k_local_plane<TI, T, N1, N2, Q1, Q2, NT, PADB, GAM>;
     if (lds > 65536)
         MB_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const unsigned units = (unsigned)nbands * (unsigned)((p->nint + PLANE_NI - 1) / PLANE_NI);
+    const unsigned units = (unsigned)a.nbands * (unsigned)((p->nint + PLANE_NI - 1) / PLANE_NI);
     StageScope ts_(dbl ? MB_STAGE_LOCAL : MB_STAGE_LOCAL32, s, nbands);
     hipLaunchKernelGGL(kern, dim3(units), dim3(NT), lds, s, a);
     MB_HIP_TRY(hipGetLastError());
     return MB_OK;
 }
 
-template <typename TI, typename T>
+template <typename TI, typename T, bool GAM>
 mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, int ld, hipStream_t s) {
     // Two lane splits, 512 threads each (FP64 planes fill one CU's LDS, FP32 planes two
     // workgroups per CU): variant 0 holds 8 points per lane (16 lanes per 128-point
@@ -289,15 +333,15 @@ mb_status plane_by_size(Problem* p, int ik, const void* c, void* u, int nbands, 
     const int var = (tn.set && tn.kind == 3) ? tn.plane_var : (sizeof(T) == 8 && p->N1 == 128 ? 1 : 0);
     static_assert(64 * 16 % 16 == 0, "column tasks fill whole 16-lane rows");
     if (p->N1 == 128 && p->N2 == 64) {
-        if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1>(p, ik, c, u, nbands, ld, s);
-        return plane_launch<TI, T, 128, 64, 16, 8, NT, 1>(p, ik, c, u, nbands, ld, s);
+        if (var == 1) return plane_launch<TI, T, 128, 64, 8, 4, NT, 1, GAM>(p, ik, c, u, nbands, ld, s);
+        return plane_launch<TI, T, 128, 64, 16, 8, NT, 1, GAM>(p, ik, c, u, nbands, ld, s);
     }
     // 36 x 36 (the graphene-like slab): lines of 36 = 4 x 9 points over 4 lanes (144 line
     // tasks per pass, 192 threads) or 2 x 18 over 2 lanes (72 tasks, 128 threads); the
     // planes are small enough for several workgroups per CU
     if (p->N1 == 36 && p->N2 == 36) {
-        if (var == 1) return plane_launch<TI, T, 36, 36, 2, 2, 128, 1>(p, ik, c, u, nbands, ld, s);
-        return plane_launch<TI, T, 36, 36, 4, 4, 192, 1>(p, ik, c, u, nbands, ld, s);
+        if (var == 1) return plane_launch<TI, T, 36, 36, 2, 2, 128, 1, GAM>(p, ik, c, u, nbands, ld, s);
+        return plane_launch<TI, T, 36, 36, 4, 4, 192, 1, GAM>(p, ik, c, u, nbands, ld, s);
     }
     return MB_ERR_INVALID_ARG;
 }
@@ -488,13 +532,19 @@ mb_status launch_density_plane(Problem* p, int ik, const void* c, int nbands, in
 }
 
 // Returns MB_ERR_INVALID_ARG (no message) if the grid has no plane kernel.
+// gamma: real-wavefunction pairing (Gamma point, c(-G) = conj c(G) for every band).
 mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,
-                             hipStream_t s) {
+                             hipStream_t s, bool gamma) {
     if (!plane_kernel_grid(p)) return MB_ERR_INVALID_ARG;
     if (nbands == 0) return MB_OK;
-    if (prec == 0) return plane_by_size<double, double>(p, ik, c, u, nbands, ld, s);
-    if (prec == 1) return plane_by_size<float, float>(p, ik, c, u, nbands, ld, s);
-    return plane_by_size<double, float>(p, ik, c, u, nbands, ld, s);
+    if (gamma) {
+        if (prec == 0) return plane_by_size<double, double, true>(p, ik, c, u, nbands, ld, s);
+        if (prec == 1) return plane_by_size<float, float, true>(p, ik, c, u, nbands, ld, s);
+        return plane_by_size<double, float, true>(p, ik, c, u, nbands, ld, s);
+    }
+    if (prec == 0) return plane_by_size<double, double, false>(p, ik, c, u, nbands, ld, s);
+    if (prec == 1) return plane_by_size<float, float, false>(p, ik, c, u, nbands, ld, s);
+    return plane_by_size<double, float, false>(p, ik, c, u, nbands, ld, s);
 }
 
 namespace {

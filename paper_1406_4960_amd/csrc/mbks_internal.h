@@ -86,6 +86,7 @@ struct KPoint {
     // preconditioner factors (T + sigma S_0) per G, [i][d][ld] doubles, built on demand
     double* d_pfac = nullptr;
     double pfac_sigma = -1.0;
+    int gamma_sym = -1;  // Gamma point with a G set closed under G -> -G: 1, else 0; -1 unknown
     // H work buffers (ws_part, ws_proj, ws_nlpart) sized once by mb_problem_reserve and
     // locked: calls that need more fail instead of reallocating, and solves do not free them
     bool locked = false;
@@ -246,7 +247,7 @@ struct HWork {
     void* nlpart = nullptr;
 };
 // bytes of each H work buffer for nbands vectors; prec as for apply_h
-size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec);
+size_t hwork_part_bytes(const Problem* p, int ik, int nbands, int ld, int prec, bool gamma = false);
 size_t hwork_proj_bytes(const Problem* p, int nbands, int prec);
 size_t hwork_nlpart_bytes(const Problem* p, int nbands, int prec);
 mb_status upload_group_windows(Problem* p);
@@ -267,8 +268,9 @@ mb_status launch_nl_project(Problem* p, int ik, const void* c, void* proj, int n
                             int prec, hipStream_t s, int scale = PROJ_E, void* projq = nullptr);
 // plane kernel (one output row per Gauss plane); MB_ERR_INVALID_ARG = no variant for this grid
 bool plane_kernel_grid(const Problem* p);
+// gamma: bands are real wavefunctions at the Gamma point, transformed two at a time
 mb_status launch_local_plane(Problem* p, int ik, const void* c, void* u, int nbands, int ld, int prec,
-                             hipStream_t s);
+                             hipStream_t s, bool gamma = false);
 // transposed potential copies for the plane kernel (after the potential changes)
 mb_status refresh_vt(Problem* p, hipStream_t s);
 // the local kernel apply_h runs for (k-point, local precision) writes one row per Gauss
@@ -380,7 +382,13 @@ bool timer_enabled();
 // prec: 0 FP64; 1 FP32 (complex64 vectors); 2 complex128 vectors with FP32 local and
 // nonlocal arithmetic; 3 = 1 and 4 = 2 with BF16x3 projector contractions.
 // ext: caller-provided work buffers (nothing allocated), else the k-point's own.
+// gamma: the bands are real wavefunctions at the Gamma point (c(-G) = conj c(G)); where
+// gamma_pairs() holds, their local part is transformed two bands at a time.
 mb_status apply_h(Problem* p, int ik, const void* c, void* y, void* sy, int nbands, int ld, int prec,
-                  hipStream_t s, const HWork* ext = nullptr);
+                  hipStream_t s, const HWork* ext = nullptr, bool gamma = false);
+// 1 if k-point ik is Gamma and its G set is closed under G -> -G, else 0 (cached)
+bool gamma_point(Problem* p, int ik);
+// real-wavefunction pairing is used for this grid and local precision
+bool gamma_pairs(const Problem* p, int lp);
 
 }  // namespace mb

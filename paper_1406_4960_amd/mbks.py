@@ -26,7 +26,7 @@ MB_MAX_GAUSS = 4
 EXPORTS = ("mb_init", "mb_problem_create", "mb_problem_destroy", "mb_problem_dims", "mb_problem_gvectors",
            "mb_problem_zrule", "mb_problem_zbands", "mb_problem_projectors", "mb_problem_augmentation",
            "mb_problem_set_potential",
-           "mb_problem_reserve", "hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
+           "mb_problem_reserve", "hpsi_apply", "hpsi_apply_gamma", "hpsi_apply_noalloc", "spsi_apply", "s_solve", "mb_lanczos_default_opts", "lanczos_lowest",
            "density_accumulate", "hartree_potential", "mb_tune_get", "mb_tune_set", "mb_tune_save",
            "mb_tune_load", "mb_batch_bind", "hpsi_apply_batched_bound", "mb_batch_create", "mb_batch_destroy", "hpsi_apply_batched", "lanczos_lowest_batched", "mb_autotune",
            "mb_small_geneig", "mb_timer_enable", "mb_timer_read", "mb_last_error", "mb_wire_create",
@@ -110,7 +110,7 @@ def load(path: str = LIB_PATH):
     lib.mb_problem_zbands.argtypes = [vp, vp, vp]
     lib.mb_problem_projectors.argtypes = [vp, c_int, vp, vp, vp]
     lib.mb_problem_set_potential.argtypes = [vp, vp]
-    for name in ("hpsi_apply", "hpsi_apply_noalloc", "spsi_apply", "s_solve"):
+    for name in ("hpsi_apply", "hpsi_apply_gamma", "hpsi_apply_noalloc", "spsi_apply", "s_solve"):
         getattr(lib, name).argtypes = [vp, c_int, vp, vp, c_int64, c_int64, c_int, vp]
     lib.mb_lanczos_default_opts.argtypes = [POINTER(LanczosOpts)]
     lib.mb_lanczos_default_opts.restype = None
@@ -361,6 +361,11 @@ class Problem:
     def hpsi(self, ik, c, y, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, c, y, prec)
         _check(load().hpsi_apply(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
+
+    def hpsi_gamma(self, ik, c, y, prec="fp64", stream=None):
+        """y = H c for real wavefunctions at Gamma (c(-G) = conj c(G) in every band)."""
+        nbands, ld = self._vec_args(ik, c, y, prec)
+        _check(load().hpsi_apply_gamma(self.h, ik, _ptr(c), _ptr(y), nbands, ld, _prec(prec), _stream(stream)))
 
     def hpsi_noalloc(self, ik, c, y, prec="fp64", stream=None):
         nbands, ld = self._vec_args(ik, c, y, prec)

@@ -33,6 +33,7 @@ family uses ``14064960 + 1000 * (p + 1)``.
 """
 from __future__ import annotations
 
+import copy
 import math
 
 import numpy as np
@@ -396,6 +397,15 @@ def wire_micro(seed: int = 0, nint: int = 6, ecut: float = 6.0, ny: int = 8, kfr
         "atoms": atoms,
         "nbands": 4,
     }
+
+
+def at_gamma(desc: dict) -> dict:
+    """The same cell with the single k-point Gamma (k = 0), where the eigenvectors can
+    be taken real in space."""
+    d = copy.deepcopy(desc)
+    d["name"] = desc["name"] + "-gamma"
+    d["kpts"] = [[0.0, 0.0]]
+    return d
 
 
 CONFIGS = {
