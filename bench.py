@@ -652,7 +652,7 @@ def main(argv=None):
     alg_bytes = bytes_b * per_launch + vbytes
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": tr["bytes_per_launch"] if tr else None,
-                "kernel": f"k_local_plane<{T}, {T}, 128, 64, {q1q2}, 512, 1> (evaluate / 2D FFT / V / "
+                "kernel": f"k_local_plane<{T}, {T}, 128, 64, {q1q2}, 512, 1, false> (evaluate / 2D FFT / V / "
                           f"2D FFT / gather, one output row per Gauss plane)",
                 "avg_launch_ms": round(avg_ms, 4), "launches": lcount, "bands_per_launch": per_launch,
                 "flops_per_launch": flops_b * per_launch,
