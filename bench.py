@@ -442,6 +442,44 @@ def ribbon_leg(torch, mbks, workloads, reps=5, full=True):
     return res
 
 
+def gamma_leg(torch, mbks, workloads, reps=5):
+    """Real wavefunctions at the Gamma point: the surface slab with k = 0, 320 seeded
+    band-vectors made real in space (c(G) <- (c(G) + conj c(-G)) / 2), H in FP32 through
+    hpsi_apply (band by band) and hpsi_apply_gamma (two bands per transform), and the
+    largest difference between the two results relative to the largest entry."""
+    d = workloads.at_gamma(workloads.surface())
+    p = mbks.Problem(d, device=0)
+    dm = p.dims(0)
+    M, ng = d["nbands"], dm["ng"]
+    m, _ = p.gvectors(0)
+    at = {(int(a), int(b)): g for g, (a, b) in enumerate(m)}
+    mir = torch.tensor([at[(-int(a), -int(b))] for a, b in m], device="cuda:0")
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(14064960)
+    x = torch.randn((M, dm["nb"], dm["ld"]), dtype=torch.complex64, device="cuda:0", generator=gen)
+    x[:, :, ng:] = 0
+    x[:, :, :ng] = 0.5 * (x[:, :, :ng] + x[:, :, mir].conj())
+    res = {"workload": d["name"], "bands": M, "precision": "fp32"}
+    outs = {}
+    for fn in ("hpsi", "hpsi_gamma"):
+        y = torch.empty_like(x)
+        f = getattr(p, fn)
+        f(0, x, y, "fp32")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f(0, x, y, "fp32")
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"{fn}_ms"] = round(e0.elapsed_time(e1) / reps, 3)
+        outs[fn] = y[:, :, :ng]
+    diff = (outs["hpsi_gamma"] - outs["hpsi"]).abs().max() / outs["hpsi"].abs().max()
+    res["rel_diff"] = float(diff)
+    p.close()
+    return res
+
+
 def surface_fp64_and_eigen_leg(torch, mbks, workloads, d, full_eig=False):
     """FP64 hpsi_apply on k-point 0 (320 vectors), and the time to the 320 lowest
     eigenpairs of k-point 0 (the share of one GPU in a k-point split over 8) in the
@@ -556,6 +594,7 @@ def main(argv=None):
     ap.add_argument("--no-c3", action="store_true", help="skip the 2x2-supercell mixed vs FP64 solve")
     ap.add_argument("--no-density", action="store_true", help="skip the density / Hartree leg")
     ap.add_argument("--no-ribbon", action="store_true", help="skip the 1D-periodic ribbon leg")
+    ap.add_argument("--no-gamma", action="store_true", help="skip the Gamma-point real-band leg")
     ap.add_argument("--no-uspp", action="store_true",
                     help="skip the graphene-like slab with augmentation charges (ultrasoft overlap)")
     ap.add_argument("--batched-solve-problems", type=int, default=6,
@@ -699,6 +738,7 @@ def main(argv=None):
     uspp = None if args.no_uspp else uspp_leg(torch, mbks, workloads)
     dens = None if args.no_density else density_leg(torch, mbks, workloads, d)
     ribbon = None if args.no_ribbon else ribbon_leg(torch, mbks, workloads)
+    gamma = None if args.no_gamma else gamma_leg(torch, mbks, workloads)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -731,6 +771,7 @@ def main(argv=None):
         "ultrasoft_graphene": uspp,
         "density_hartree": dens,
         "ribbon_1d_periodic": ribbon,
+        "gamma_real_bands": gamma,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
